@@ -1,0 +1,544 @@
+// CPU oracle for sparse tropical matrix factorization (FastSTMF).
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+// benchmark's CPU-baseline leg may load this library.  It shares no code,
+// header, table or helper with the HIP library; it is a plain, slow,
+// deliberately unblocked restatement of the paper's definitions:
+//
+//   * max-plus product          (A (x) B)_ij = max_k A_ik + B_kj      Sec. 2
+//   * masked min-plus residual  (A (x)* B)_ij = min over given A_ik, B_kj
+//                                of A_ik + B_kj                        Sec. 2
+//   * b-norm                    ||W||_b = sum |W_ij|, over given cells Sec. 3.6
+//   * argmax f(i,j), lowest index on ties                     Sec. 3.2.1 (TD)
+//   * td_col(j) = sum over rows of td(t, j)                   Sec. 3.2.1
+//   * TD_A k-selection from the additive union of the two
+//     argmax multisets                                        Sec. 3.2.1
+//   * F-ULF / F-URF                                           Algorithms 1, 2
+//   * FastSTMF = ByRow, random row permutation, TD_A, wide    Algorithm 3
+//
+// Every routine is a template over the value type T.  T = double is "the FP64
+// oracle": all value arithmetic in double on exactly promoted FP32 inputs.
+// T = float takes every value operation as one correctly rounded FP32
+// operation (the precision in which the GPU library decides accept/reject,
+// argmax and ordering), with error sums widened to double.  Sums of |d| run
+// in plain row-major order.  Built with -ffp-contract=off and no fast-math.
+//
+// Readings of points the paper leaves open (each is listed in the design
+// notes of the repository):
+//   - error, td and td_col range over observed cells only;
+//   - transpose iff rows > columns ("wide" means m <= n);
+//   - TD_A counts range over observed cells of row i and column j, the union
+//     is additive, ties go to the lowest index;
+//   - candidates j are the observed columns of row i ordered by td_col
+//     descending, ties by ascending j; F-URF is tried with the same (j, k)
+//     after F-ULF is rejected, and the first strict decrease (e' < e) ends the
+//     row;
+//   - initial V is the residual (-U)^T (x)* R for every component;
+//   - no-op rule: an operation whose step-2 write leaves the stored value
+//     unchanged, on a component last written by a completed operation, is
+//     counted as rejected without evaluation (exact arithmetic gives e' = e);
+//   - a pass with no accepted update is a fixed point: the rest of the
+//     trajectory is padded with the current error;
+//   - random draws: SplitMix64 (Steele, Lea, Flood 2014), bounded integers by
+//     rejection of x < 2^64 mod b then x mod b, Durstenfeld's Fisher-Yates
+//     from the last index down; draw order: permutation, then U0.
+//
+// Parity of the TD_A counting scope, the candidate tie order, the Random-Acol
+// column count and the random stream is unpinned: the paper fixes none of
+// them.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+
+namespace {
+
+enum { OK = 0, EINVAL_ = 1, EEMPTY = 2, ERANGE_ = 3 };
+
+// ---------------------------------------------------------------- randomness
+struct SplitMix64 {
+  uint64_t state;
+  uint64_t next() {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+};
+
+uint64_t draw_below(SplitMix64& g, uint64_t bound) {
+  uint64_t reject_under = (0ull - bound) % bound;  // 2^64 mod bound
+  while (true) {
+    uint64_t x = g.next();
+    if (x >= reject_under) return x % bound;
+  }
+}
+
+// ---------------------------------------------------------------- primitives
+// (U (x) V)_ij = max_l U_il + V_lj; A gets the lowest l reaching the maximum.
+template <class T>
+void maxplus(const T* U, const T* V, int m, int r, int n, T* P, int32_t* A) {
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < n; ++j) {
+      T best = U[(size_t)i * r + 0] + V[j];
+      int arg = 0;
+      for (int l = 1; l < r; ++l) {
+        T x = U[(size_t)i * r + l] + V[(size_t)l * n + j];
+        if (x > best) { best = x; arg = l; }
+      }
+      if (P) P[(size_t)i * n + j] = best;
+      if (A) A[(size_t)i * n + j] = arg;
+    }
+}
+
+// Column residual of component k: V_kj <- min over observed t of R_tj - U_tk.
+// This is (-U_.k)^T (x)* R restricted to the given cells of column j.
+template <class T>
+void col_res(const T* R, const uint8_t* M, int m, int n, int r, int k,
+             const T* U, T* V) {
+  for (int j = 0; j < n; ++j) {
+    bool seen = false;
+    T best = 0;
+    for (int t = 0; t < m; ++t) {
+      if (!M[(size_t)t * n + j]) continue;
+      T x = R[(size_t)t * n + j] - U[(size_t)t * r + k];
+      if (!seen || x < best) { best = x; seen = true; }
+    }
+    V[(size_t)k * n + j] = best;
+  }
+}
+
+// Row residual of component k: U_tk <- min over observed j of R_tj - V_kj.
+// This is R (x)* (-V_k.)^T restricted to the given cells of row t.
+template <class T>
+void row_res(const T* R, const uint8_t* M, int m, int n, int r, int k,
+             const T* V, T* U) {
+  for (int t = 0; t < m; ++t) {
+    bool seen = false;
+    T best = 0;
+    for (int j = 0; j < n; ++j) {
+      if (!M[(size_t)t * n + j]) continue;
+      T x = R[(size_t)t * n + j] - V[(size_t)k * n + j];
+      if (!seen || x < best) { best = x; seen = true; }
+    }
+    U[(size_t)t * r + k] = best;
+  }
+}
+
+// b-norm of R - U (x) V over the observed cells, summed in double in row-major
+// order.  The per-cell difference is taken in T and then widened.  td_col[j]
+// (nullable) gets the sum over the observed rows of column j; A (nullable) the
+// argmax of every cell (observed or not).
+template <class T>
+double masked_error(const T* R, const uint8_t* M, const T* U, const T* V,
+                    int m, int n, int r, double* td_col, int32_t* A) {
+  double e = 0.0;
+  if (td_col)
+    for (int j = 0; j < n; ++j) td_col[j] = 0.0;
+  for (int t = 0; t < m; ++t)
+    for (int j = 0; j < n; ++j) {
+      T best = U[(size_t)t * r + 0] + V[j];
+      int arg = 0;
+      for (int l = 1; l < r; ++l) {
+        T x = U[(size_t)t * r + l] + V[(size_t)l * n + j];
+        if (x > best) { best = x; arg = l; }
+      }
+      if (A) A[(size_t)t * n + j] = arg;
+      if (!M[(size_t)t * n + j]) continue;
+      T d = R[(size_t)t * n + j] - best;
+      double ad = std::fabs((double)d);
+      e += ad;
+      if (td_col) td_col[j] += ad;
+    }
+  return e;
+}
+
+// Algorithm 1 (F-ULF) at (i, j, k): back up U_.k and V_k., write
+// U_ik <- R_ij - V_kj, then V_k. <- column residual of U_.k, then
+// U_.k <- row residual of V_k., and return the new b-norm.
+template <class T>
+double f_ulf(const T* R, const uint8_t* M, T* U, T* V, int m, int n, int r,
+             int i, int j, int k, T* Ubak, T* Vbak, double* td_col, int32_t* A) {
+  for (int t = 0; t < m; ++t) Ubak[t] = U[(size_t)t * r + k];
+  for (int c = 0; c < n; ++c) Vbak[c] = V[(size_t)k * n + c];
+  U[(size_t)i * r + k] = R[(size_t)i * n + j] - V[(size_t)k * n + j];
+  col_res(R, M, m, n, r, k, U, V);
+  row_res(R, M, m, n, r, k, V, U);
+  return masked_error(R, M, U, V, m, n, r, td_col, A);
+}
+
+// Algorithm 2 (F-URF) at (i, j, k): the same with V_kj <- R_ij - U_ik and the
+// two residual steps in the other order.
+template <class T>
+double f_urf(const T* R, const uint8_t* M, T* U, T* V, int m, int n, int r,
+             int i, int j, int k, T* Ubak, T* Vbak, double* td_col, int32_t* A) {
+  for (int t = 0; t < m; ++t) Ubak[t] = U[(size_t)t * r + k];
+  for (int c = 0; c < n; ++c) Vbak[c] = V[(size_t)k * n + c];
+  V[(size_t)k * n + j] = R[(size_t)i * n + j] - U[(size_t)i * r + k];
+  row_res(R, M, m, n, r, k, V, U);
+  col_res(R, M, m, n, r, k, U, V);
+  return masked_error(R, M, U, V, m, n, r, td_col, A);
+}
+
+}  // namespace
+
+// ============================================================ C interface
+extern "C" {
+
+struct oracle_opts {
+  int init_mode;         // 0 random ints, 1 random Acol, 2 given U0
+  float init_lo, init_hi;// random-int range, inclusive
+  int acol_p;            // columns averaged per U column (random Acol)
+  const float* U0;       // given U0, working orientation (m' x r)
+  const int32_t* perm;   // nullable explicit working-row permutation
+  double eps;            // 0: run exactly `iters` passes (bar fixed points)
+  int count_scope;       // 0 observed cells, 1 every index
+  int noop_rule;         // 1: skip no-op trials as rejected
+  int integer_exact;     // 1: reject |value| >= 2^24
+};
+
+struct oracle_log {      // one record per row visit
+  int32_t iter, row, trials, noops, j, k, op;  // j = -1: nothing accepted
+  int32_t pad;
+  double e;
+};
+
+struct oracle_stats {
+  int64_t trials;        // evaluated trials
+  int64_t noops;         // trials skipped by the no-op rule
+  int64_t accepted;
+  int64_t row_visits;
+  int32_t iters_done;
+  int32_t transposed;
+  int64_t evaluated_cells;  // sum over evaluations of |Omega|
+};
+
+// ---- primitive entry points (f64: T = double, f32: T = float) ----
+#define ORACLE_PRIMS(SUF, T)                                                   \
+  void oracle_maxplus_##SUF(const T* U, const T* V, int m, int r, int n, T* P, \
+                            int32_t* A) {                                      \
+    maxplus<T>(U, V, m, r, n, P, A);                                           \
+  }                                                                            \
+  double oracle_masked_error_##SUF(const T* R, const uint8_t* M, const T* U,   \
+                                   const T* V, int m, int n, int r,            \
+                                   double* td_col, int32_t* A) {               \
+    return masked_error<T>(R, M, U, V, m, n, r, td_col, A);                    \
+  }                                                                            \
+  void oracle_col_res_##SUF(const T* R, const uint8_t* M, int m, int n, int r, \
+                            int k, const T* U, T* V) {                         \
+    col_res<T>(R, M, m, n, r, k, U, V);                                        \
+  }                                                                            \
+  void oracle_row_res_##SUF(const T* R, const uint8_t* M, int m, int n, int r, \
+                            int k, const T* V, T* U) {                         \
+    row_res<T>(R, M, m, n, r, k, V, U);                                        \
+  }                                                                            \
+  double oracle_update_U_##SUF(const T* R, const uint8_t* M, T* U, T* V,       \
+                               int m, int n, int r, int i, int j, int k,       \
+                               T* Ubak, T* Vbak, double* td_col) {             \
+    return f_ulf<T>(R, M, U, V, m, n, r, i, j, k, Ubak, Vbak, td_col, nullptr);\
+  }                                                                            \
+  double oracle_update_V_##SUF(const T* R, const uint8_t* M, T* U, T* V,       \
+                               int m, int n, int r, int i, int j, int k,       \
+                               T* Ubak, T* Vbak, double* td_col) {             \
+    return f_urf<T>(R, M, U, V, m, n, r, i, j, k, Ubak, Vbak, td_col, nullptr);\
+  }
+
+ORACLE_PRIMS(f64, double)
+ORACLE_PRIMS(f32, float)
+
+// First `count` outputs of SplitMix64 seeded with `seed`.
+void oracle_splitmix64(uint64_t seed, int count, uint64_t* out) {
+  SplitMix64 g{seed};
+  for (int c = 0; c < count; ++c) out[c] = g.next();
+}
+
+}  // extern "C"
+
+namespace {
+
+// Working orientation: transpose iff m > n, then rows permuted by perm.
+struct Working {
+  int m, n;            // working shape
+  bool transposed;
+  std::vector<float> R;
+  std::vector<uint8_t> M;
+  std::vector<int32_t> perm;
+};
+
+int build_working(const float* R, const uint8_t* M, int m, int n,
+                  const oracle_opts* o, uint64_t seed, Working& w,
+                  SplitMix64& g) {
+  w.transposed = m > n;
+  w.m = w.transposed ? n : m;
+  w.n = w.transposed ? m : n;
+  w.perm.resize(w.m);
+  if (o && o->perm) {
+    std::vector<char> hit(w.m, 0);
+    for (int a = 0; a < w.m; ++a) {
+      int p = o->perm[a];
+      if (p < 0 || p >= w.m || hit[p]) return EINVAL_;
+      hit[p] = 1;
+      w.perm[a] = p;
+    }
+  } else {
+    for (int a = 0; a < w.m; ++a) w.perm[a] = a;
+    for (int a = w.m - 1; a >= 1; --a) {
+      int b = (int)draw_below(g, (uint64_t)a + 1);
+      std::swap(w.perm[a], w.perm[b]);
+    }
+  }
+  (void)seed;
+  w.R.assign((size_t)w.m * w.n, 0.0f);
+  w.M.assign((size_t)w.m * w.n, 0);
+  for (int a = 0; a < w.m; ++a)
+    for (int b = 0; b < w.n; ++b) {
+      int src = w.perm[a];
+      size_t s = w.transposed ? ((size_t)b * n + src) : ((size_t)src * n + b);
+      uint8_t obs = M[s] ? 1 : 0;
+      w.M[(size_t)a * w.n + b] = obs;
+      // -0 becomes +0; unobserved values are never read into arithmetic.
+      w.R[(size_t)a * w.n + b] = obs ? (R[s] + 0.0f) : 0.0f;
+    }
+  return OK;
+}
+
+int init_U0(const Working& w, int r, const oracle_opts* o, SplitMix64& g,
+            std::vector<float>& U0) {
+  U0.assign((size_t)w.m * r, 0.0f);
+  int mode = o ? o->init_mode : 0;
+  if (mode == 2) {
+    if (!o->U0) return EINVAL_;
+    for (size_t q = 0; q < U0.size(); ++q) U0[q] = o->U0[q] + 0.0f;
+  } else if (mode == 0) {
+    float lo = o ? o->init_lo : 0.0f, hi = o ? o->init_hi : 100.0f;
+    int64_t span = (int64_t)hi - (int64_t)lo + 1;
+    if (span < 1) return EINVAL_;
+    for (int t = 0; t < w.m; ++t)
+      for (int l = 0; l < r; ++l)
+        U0[(size_t)t * r + l] =
+            (float)((int64_t)lo + (int64_t)draw_below(g, (uint64_t)span));
+  } else if (mode == 1) {
+    int p = (o && o->acol_p > 0) ? o->acol_p : 5;
+    std::vector<int> cols((size_t)r * p);
+    for (int l = 0; l < r; ++l)
+      for (int q = 0; q < p; ++q)
+        cols[(size_t)l * p + q] = (int)draw_below(g, (uint64_t)w.n);
+    for (int t = 0; t < w.m; ++t) {
+      // fallback: mean of the row's observed values
+      double rs = 0.0;
+      int rc = 0;
+      for (int b = 0; b < w.n; ++b)
+        if (w.M[(size_t)t * w.n + b]) { rs += (double)w.R[(size_t)t * w.n + b]; ++rc; }
+      for (int l = 0; l < r; ++l) {
+        double s = 0.0;
+        int c = 0;
+        for (int q = 0; q < p; ++q) {
+          int b = cols[(size_t)l * p + q];
+          if (w.M[(size_t)t * w.n + b]) { s += (double)w.R[(size_t)t * w.n + b]; ++c; }
+        }
+        double mean = c ? s / (double)c : rs / (double)rc;
+        U0[(size_t)t * r + l] = (float)mean + 0.0f;
+      }
+    }
+  } else {
+    return EINVAL_;
+  }
+  return OK;
+}
+
+template <class T>
+int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
+        int iters, uint64_t seed, const oracle_opts* o, float* U_out,
+        float* V_out, double* traj, oracle_log* log, int log_cap, int* log_len,
+        oracle_stats* st, int row_limit) {
+  if (m_in < 1 || n_in < 1 || r < 1 || r > 64 || iters < 0) return EINVAL_;
+  for (int i = 0; i < m_in; ++i) {
+    int c = 0;
+    for (int j = 0; j < n_in; ++j) c += Min[(size_t)i * n_in + j] ? 1 : 0;
+    if (!c) return EEMPTY;
+  }
+  for (int j = 0; j < n_in; ++j) {
+    int c = 0;
+    for (int i = 0; i < m_in; ++i) c += Min[(size_t)i * n_in + j] ? 1 : 0;
+    if (!c) return EEMPTY;
+  }
+  const bool int_exact = o && o->integer_exact;
+  if (int_exact)
+    for (size_t q = 0; q < (size_t)m_in * n_in; ++q)
+      if (Min[q] && !(std::fabs(Rin[q]) < 16777216.0f)) return ERANGE_;
+
+  SplitMix64 g{seed};
+  Working w;
+  int s = build_working(Rin, Min, m_in, n_in, o, seed, w, g);
+  if (s) return s;
+  std::vector<float> U0;
+  s = init_U0(w, r, o, g, U0);
+  if (s) return s;
+  if (int_exact)
+    for (float x : U0)
+      if (!(std::fabs(x) < 16777216.0f)) return ERANGE_;
+
+  const int m = w.m, n = w.n;
+  std::vector<T> R((size_t)m * n), U((size_t)m * r), V((size_t)r * n);
+  for (size_t q = 0; q < R.size(); ++q) R[q] = (T)w.R[q];
+  for (size_t q = 0; q < U.size(); ++q) U[q] = (T)U0[q];
+  const uint8_t* M = w.M.data();
+  for (int k = 0; k < r; ++k) col_res(R.data(), M, m, n, r, k, U.data(), V.data());
+
+  std::vector<double> td((size_t)n), td_try((size_t)n);
+  std::vector<int32_t> A((size_t)m * n), A_try((size_t)m * n);
+  std::vector<T> Ubak((size_t)m), Vbak((size_t)n);
+  std::vector<char> closed((size_t)r, 0);
+  int64_t omega = 0;
+  for (size_t q = 0; q < (size_t)m * n; ++q) omega += M[q];
+
+  double e = masked_error(R.data(), M, U.data(), V.data(), m, n, r, td.data(), A.data());
+  if (traj) traj[0] = e;
+  oracle_stats S{};
+  S.transposed = w.transposed;
+  S.evaluated_cells = omega;
+  int nlog = 0;
+  const int scope_all = o && o->count_scope == 1;
+  const int noop_rule = o ? o->noop_rule : 1;
+  const double eps = o ? o->eps : 0.0;
+
+  int it_done = 0;
+  bool stop = false;
+  int rows_left = row_limit > 0 ? row_limit : -1;
+  for (int it = 1; it <= iters && !stop; ++it) {
+    int64_t acc_this_pass = 0;
+    for (int i = 0; i < m; ++i) {
+      if (rows_left == 0) { stop = true; break; }
+      if (rows_left > 0) --rows_left;
+      // row multiset {{ f(i,t) }} as counts
+      std::vector<int> crow((size_t)r, 0);
+      for (int t = 0; t < n; ++t)
+        if (scope_all || M[(size_t)i * n + t]) crow[A[(size_t)i * n + t]]++;
+      // candidate columns: observed in row i, td_col descending, j ascending
+      std::vector<int> cand;
+      for (int j = 0; j < n; ++j)
+        if (M[(size_t)i * n + j]) cand.push_back(j);
+      std::stable_sort(cand.begin(), cand.end(),
+                       [&](int a, int b) { return td[a] > td[b]; });
+      oracle_log rec{it, i, 0, 0, -1, -1, -1, 0, e};
+      bool accepted = false;
+      for (int j : cand) {
+        std::vector<int> cnt(crow);
+        for (int t = 0; t < m; ++t)
+          if (scope_all || M[(size_t)t * n + j]) cnt[A[(size_t)t * n + j]]++;
+        int k = 0;
+        for (int l = 1; l < r; ++l)
+          if (cnt[l] > cnt[k]) k = l;
+        for (int op = 0; op < 2 && !accepted; ++op) {
+          T* Uik = &U[(size_t)i * r + k];
+          T* Vkj = &V[(size_t)k * n + j];
+          T Rij = R[(size_t)i * n + j];
+          if (noop_rule && closed[k]) {
+            bool same = op == 0 ? (T)(Rij - *Vkj) == *Uik : (T)(Rij - *Uik) == *Vkj;
+            if (same) { rec.noops++; S.noops++; continue; }
+          }
+          double e2 = op == 0
+              ? f_ulf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k,
+                      Ubak.data(), Vbak.data(), td_try.data(), A_try.data())
+              : f_urf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k,
+                      Ubak.data(), Vbak.data(), td_try.data(), A_try.data());
+          rec.trials++;
+          S.trials++;
+          S.evaluated_cells += omega;
+          if (e2 < e) {
+            e = e2;
+            td.swap(td_try);
+            A.swap(A_try);
+            closed[k] = 1;
+            accepted = true;
+            rec.j = j; rec.k = k; rec.op = op; rec.e = e;
+            S.accepted++;
+            acc_this_pass++;
+          } else {
+            for (int t = 0; t < m; ++t) U[(size_t)t * r + k] = Ubak[t];
+            for (int c = 0; c < n; ++c) V[(size_t)k * n + c] = Vbak[c];
+          }
+        }
+        if (accepted) break;
+      }
+      S.row_visits++;
+      if (log && nlog < log_cap) log[nlog] = rec;
+      nlog++;
+    }
+    if (stop && rows_left == 0) break;
+    it_done = it;
+    if (traj) traj[it] = e;
+    bool fixed_point = acc_this_pass == 0;
+    bool small_step = eps > 0.0 && traj && (traj[it - 1] - traj[it] < eps);
+    if (fixed_point || small_step) {
+      if (traj)
+        for (int q = it + 1; q <= iters; ++q) traj[q] = e;
+      stop = true;
+    }
+  }
+  S.iters_done = it_done;
+  if (log_len) *log_len = nlog;
+  if (st) *st = S;
+
+  // un-permute and un-transpose (Algorithm 3, output step)
+  std::vector<float> Uw((size_t)m * r);
+  for (int a = 0; a < m; ++a)
+    for (int l = 0; l < r; ++l) Uw[(size_t)w.perm[a] * r + l] = (float)U[(size_t)a * r + l];
+  if (!w.transposed) {
+    if (U_out) std::memcpy(U_out, Uw.data(), sizeof(float) * Uw.size());
+    if (V_out)
+      for (size_t q = 0; q < V.size(); ++q) V_out[q] = (float)V[q];
+  } else {
+    // original is n x m' ... U_out (m_in x r) = V_w^T, V_out (r x n_in) = U_unperm^T
+    if (U_out)
+      for (int a = 0; a < m_in; ++a)
+        for (int l = 0; l < r; ++l) U_out[(size_t)a * r + l] = (float)V[(size_t)l * n + a];
+    if (V_out)
+      for (int l = 0; l < r; ++l)
+        for (int b = 0; b < n_in; ++b) V_out[(size_t)l * n_in + b] = Uw[(size_t)b * r + l];
+  }
+  return OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Algorithm 3.  U_out (m x rank), V_out (rank x n) in the original
+// orientation; traj gets iters + 1 values; log (nullable) one record per row
+// visit.  row_limit > 0 stops after that many row visits (prefix runs).
+int oracle_fit_f64(const float* R, const uint8_t* M, int m, int n, int rank,
+                   int iters, uint64_t seed, const oracle_opts* o, float* U_out,
+                   float* V_out, double* traj, oracle_log* log, int log_cap,
+                   int* log_len, oracle_stats* st, int row_limit) {
+  return fit<double>(R, M, m, n, rank, iters, seed, o, U_out, V_out, traj, log,
+                     log_cap, log_len, st, row_limit);
+}
+int oracle_fit_f32(const float* R, const uint8_t* M, int m, int n, int rank,
+                   int iters, uint64_t seed, const oracle_opts* o, float* U_out,
+                   float* V_out, double* traj, oracle_log* log, int log_cap,
+                   int* log_len, oracle_stats* st, int row_limit) {
+  return fit<float>(R, M, m, n, rank, iters, seed, o, U_out, V_out, traj, log,
+                    log_cap, log_len, st, row_limit);
+}
+
+// Setup draws of a fit, for checking a library's own random stream: the
+// working permutation (m' entries) and U0 (m' x rank, working orientation).
+int oracle_draw_init(const float* R, const uint8_t* M, int m, int n, int rank,
+                     uint64_t seed, const oracle_opts* o, int32_t* perm_out,
+                     float* U0_out) {
+  SplitMix64 g{seed};
+  Working w;
+  int s = build_working(R, M, m, n, o, seed, w, g);
+  if (s) return s;
+  std::vector<float> U0;
+  s = init_U0(w, rank, o, g, U0);
+  if (s) return s;
+  if (perm_out) std::memcpy(perm_out, w.perm.data(), sizeof(int32_t) * w.perm.size());
+  if (U0_out) std::memcpy(U0_out, U0.data(), sizeof(float) * U0.size());
+  return OK;
+}
+
+}  // extern "C"

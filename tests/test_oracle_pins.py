@@ -1,0 +1,466 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types an oracle formula: each checks a property, a special
+case, a hand-derived example (tests/golden) or a brute-force search that a
+plausible mistake in the oracle (dropped term, wrong sign or index, transposed
+operand, wrong tie rule, wrong candidate order) would break.
+"""
+import itertools
+import collections
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2205_06619_amd import synth
+from conftest import read_golden
+
+PRECS = ("f64", "f32")
+
+
+# ------------------------------------------------------------------ random
+def test_splitmix64_published_outputs():
+    from conftest import GOLDEN
+    with open(GOLDEN + "/splitmix64_seed0.txt") as f:
+        want = [int(x.strip(), 16) for x in f if x.strip() and not x.startswith("#")]
+    got = [int(x) for x in oracle.splitmix64(0, 3)]
+    assert got == want
+
+
+def test_draw_init_permutation_and_range():
+    R, M = synth.int_planted(40, 30, 3, seed=1)
+    s, perm, U0 = oracle.draw_init(R, M, 4, seed=123, init_mode=0, init_lo=0, init_hi=100)
+    assert s == 0
+    assert sorted(perm.tolist()) == list(range(30))      # 40 x 30 is transposed
+    assert U0.shape == (30, 4)
+    assert np.all(U0 == np.round(U0)) and U0.min() >= 0 and U0.max() <= 100
+    # the draws depend on the seed
+    _, perm2, _ = oracle.draw_init(R, M, 4, seed=124)
+    assert not np.array_equal(perm, perm2)
+
+
+def test_draw_init_uniformity_of_permutation():
+    # Durstenfeld shuffle: every position equally likely (chi-square, 3 items)
+    R = np.zeros((3, 5), np.float32); M = np.ones((3, 5), np.uint8)
+    counts = collections.Counter()
+    for s in range(3000):
+        _, perm, _ = oracle.draw_init(R, M, 1, seed=s)
+        counts[tuple(perm)] += 1
+    assert len(counts) == 6
+    exp = 3000 / 6
+    chi2 = sum((c - exp) ** 2 / exp for c in counts.values())
+    assert chi2 < 20.5  # p ~ 0.001 at 5 dof
+
+
+# ------------------------------------------------------------------ max-plus
+@pytest.mark.parametrize("prec", PRECS)
+def test_maxplus_hand_example_with_tie(prec):
+    g = read_golden("a1_maxplus_tie.txt")
+    P, A = oracle.maxplus(g["U"], g["V"], prec)
+    np.testing.assert_array_equal(P, g["P"])
+    np.testing.assert_array_equal(A, g["A"])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_maxplus_rank1_is_outer_sum(prec):
+    rng = np.random.default_rng(0)
+    U = rng.integers(-50, 50, (7, 1)).astype(np.float32)
+    V = rng.integers(-50, 50, (1, 9)).astype(np.float32)
+    P, A = oracle.maxplus(U, V, prec)
+    np.testing.assert_array_equal(P, np.add.outer(U[:, 0], V[0]))
+    assert np.all(A == 0)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_maxplus_transpose_identity(prec):
+    # (U (x) V)^T = V^T (x) U^T  (used by the paper to justify transposing)
+    rng = np.random.default_rng(1)
+    U = rng.integers(0, 20, (5, 3)).astype(np.float32)
+    V = rng.integers(0, 20, (3, 8)).astype(np.float32)
+    P, _ = oracle.maxplus(U, V, prec)
+    Pt, _ = oracle.maxplus(V.T, U.T, prec)
+    np.testing.assert_array_equal(P.T, Pt)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_maxplus_associative_and_identity(prec):
+    rng = np.random.default_rng(2)
+    A = rng.integers(0, 30, (4, 3)).astype(np.float32)
+    B = rng.integers(0, 30, (3, 5)).astype(np.float32)
+    Cm = rng.integers(0, 30, (5, 2)).astype(np.float32)
+    AB, _ = oracle.maxplus(A, B, prec)
+    BC, _ = oracle.maxplus(B, Cm, prec)
+    L, _ = oracle.maxplus(AB, Cm, prec)
+    Rr, _ = oracle.maxplus(A, BC, prec)
+    np.testing.assert_array_equal(L, Rr)
+    E = np.full((3, 3), -np.inf, np.float32); np.fill_diagonal(E, 0)
+    AE, _ = oracle.maxplus(A, E, prec)
+    np.testing.assert_array_equal(AE, A)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_maxplus_distributes_over_tropical_sum(prec):
+    rng = np.random.default_rng(3)
+    A1 = rng.integers(0, 9, (4, 3)).astype(np.float32)
+    A2 = rng.integers(0, 9, (4, 3)).astype(np.float32)
+    B = rng.integers(0, 9, (3, 6)).astype(np.float32)
+    L, _ = oracle.maxplus(np.maximum(A1, A2), B, prec)
+    P1, _ = oracle.maxplus(A1, B, prec)
+    P2, _ = oracle.maxplus(A2, B, prec)
+    np.testing.assert_array_equal(L, np.maximum(P1, P2))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_argmax_is_lowest_index_reaching_max(prec):
+    rng = np.random.default_rng(4)
+    U = rng.integers(0, 3, (6, 5)).astype(np.float32)   # many ties
+    V = rng.integers(0, 3, (5, 7)).astype(np.float32)
+    P, A = oracle.maxplus(U, V, prec)
+    for i in range(6):
+        for j in range(7):
+            terms = U[i] + V[:, j]
+            a = A[i, j]
+            assert terms[a] == P[i, j]
+            assert np.all(terms[:a] < P[i, j])
+            assert np.all(terms <= P[i, j])
+
+
+# ------------------------------------------------------------------ residuals
+@pytest.mark.parametrize("prec", PRECS)
+def test_masked_residual_hand_example(prec):
+    g = read_golden("a2_masked_residual.txt")
+    R, M, U = g["R"], g["M"].astype(np.uint8), g["U"]
+    V = oracle.col_res(R, M, U, np.zeros((1, 2)), 0, prec)
+    np.testing.assert_array_equal(V, g["V"])
+    U2 = oracle.row_res(R, M, np.zeros((2, 1)), V, 0, prec)
+    np.testing.assert_array_equal(U2, g["Uback"])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("seed", range(6))
+def test_residuals_are_greatest_integer_solutions(prec, seed):
+    # row residual x = R (x)* (-v)^T is the greatest x with x_t + v_j <= R_tj
+    # on every given cell; enumerate integer candidates around it.
+    R, M = synth.tiny_int_case(5, 6, 1, seed, hi=6)
+    rng = np.random.default_rng(seed)
+    v = rng.integers(-3, 4, (1, 6)).astype(np.float64)
+    U = oracle.row_res(R, M, np.zeros((5, 1)), v, 0, prec)
+    for t in range(5):
+        ok = lambda x: all(x + v[0, j] <= R[t, j] for j in range(6) if M[t, j])
+        assert ok(U[t, 0]) and not ok(U[t, 0] + 1)
+        for x in range(-20, 20):
+            if ok(x):
+                assert x <= U[t, 0]
+    u = rng.integers(-3, 4, (5, 1)).astype(np.float64)
+    V = oracle.col_res(R, M, u, np.zeros((1, 6)), 0, prec)
+    for j in range(6):
+        ok = lambda y: all(u[t, 0] + y <= R[t, j] for t in range(5) if M[t, j])
+        assert ok(V[0, j]) and not ok(V[0, j] + 1)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_residual_closure(prec):
+    # x^b#b = x^b for the residuation pair (exact on integers)
+    R, M = synth.tiny_int_case(6, 8, 2, 7, hi=9)
+    U = np.random.default_rng(7).integers(0, 9, (6, 2)).astype(np.float64)
+    V = oracle.col_res(R, M, U, np.zeros((2, 8)), 1, prec)
+    U2 = oracle.row_res(R, M, U, V, 1, prec)
+    V2 = oracle.col_res(R, M, U2, V, 1, prec)
+    np.testing.assert_array_equal(V, V2)
+    assert np.all(U2[:, 1] >= U[:, 1])       # closure is extensive
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_unobserved_values_never_read(prec):
+    R, M = synth.tiny_int_case(6, 7, 2, 11, hi=9)
+    R2 = R.copy(); R2[M == 0] = np.nan
+    U = np.random.default_rng(11).integers(0, 9, (6, 2)).astype(np.float32)
+    V = oracle.col_res(R, M, U, np.zeros((2, 7)), 0, prec)
+    V = oracle.col_res(R, M, U, V, 1, prec)
+    V2 = oracle.col_res(R2, M, U, np.zeros((2, 7)), 0, prec)
+    V2 = oracle.col_res(R2, M, U, V2, 1, prec)
+    np.testing.assert_array_equal(V, V2)
+    e1, td1, _ = oracle.masked_error(R, M, U, V, prec)
+    e2, td2, _ = oracle.masked_error(R2, M, U, V, prec)
+    assert e1 == e2 and np.array_equal(td1, td2)
+
+
+# ------------------------------------------------------------------ b-norm
+@pytest.mark.parametrize("prec", PRECS)
+def test_error_zero_at_principal_solution(prec):
+    # a solvable system U* (x) V = R has the residual of U* as a solution
+    R, _ = synth.int_planted(12, 9, 3, seed=5)
+    rng = np.random.default_rng(5)
+    Ustar = rng.integers(0, 101, (12, 3)).astype(np.float32)
+    R = synth.maxplus_planted(Ustar, rng.integers(0, 101, (3, 9)))
+    M = np.ones_like(R, dtype=np.uint8)
+    V = np.zeros((3, 9))
+    for k in range(3):
+        V = oracle.col_res(R, M, Ustar, V, k, prec)
+    e, td, _ = oracle.masked_error(R, M, Ustar, V, prec)
+    assert e == 0.0 and np.all(td == 0)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_error_of_residual_fit_is_sum_of_gaps(prec):
+    # after residual steps P <= R on given cells, so |R - P| = R - P and the
+    # b-norm equals the sum of R minus the sum of P over given cells
+    R, M = synth.tiny_int_case(7, 9, 3, 3, hi=20)
+    U = np.random.default_rng(3).integers(0, 20, (7, 3)).astype(np.float64)
+    V = np.zeros((3, 9))
+    for k in range(3):
+        V = oracle.col_res(R, M, U, V, k, prec)
+    P, _ = oracle.maxplus(U, V, prec)
+    assert np.all(P[M == 1] <= R[M == 1])
+    e, td, _ = oracle.masked_error(R, M, U, V, prec)
+    assert e == float(R[M == 1].sum() - P[M == 1].sum())
+    assert e == pytest.approx(td.sum(), abs=0)
+    # a per-column problem has td_col as its whole error
+    for j in range(9):
+        ej, _, _ = oracle.masked_error(R[:, j:j + 1], M[:, j:j + 1], U, V[:, j:j + 1], prec)
+        assert ej == td[j]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_error_sign_and_shift_invariance(prec):
+    R, M = synth.tiny_int_case(6, 8, 2, 9, hi=30)
+    rng = np.random.default_rng(9)
+    U = rng.integers(-5, 40, (6, 2)).astype(np.float64)
+    V = rng.integers(-5, 40, (2, 8)).astype(np.float64)
+    e, _, _ = oracle.masked_error(R, M, U, V, prec)
+    P, _ = oracle.maxplus(U, V, prec)
+    assert e == float(np.abs(R - P)[M == 1].sum())  # both signs occur here
+    e2, _, _ = oracle.masked_error(R + 17, M, U + 17, V, prec)
+    e3, _, _ = oracle.masked_error(R + 5, M, U, V + 5, prec)
+    assert e == e2 == e3
+
+
+# ------------------------------------------------------------------ F-ULF/F-URF
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("op", ["U", "V"])
+@pytest.mark.parametrize("seed", range(5))
+def test_update_invariants(prec, op, seed):
+    R, M = synth.tiny_int_case(6, 9, 3, seed, hi=12, missing=0.3)
+    rng = np.random.default_rng(seed)
+    U = rng.integers(0, 12, (6, 3)).astype(np.float64)
+    V = np.zeros((3, 9))
+    for k in range(3):
+        V = oracle.col_res(R, M, U, V, k, prec)
+    obs = np.argwhere(M == 1)
+    i, j = obs[rng.integers(len(obs))]
+    k = int(rng.integers(3))
+    U2, V2, e, Ub, Vb, td = oracle.update(op, R, M, U, V, i, j, k, prec)
+    # backups are the pre-update column / row
+    np.testing.assert_array_equal(Ub, U[:, k]); np.testing.assert_array_equal(Vb, V[k])
+    # only column k of U and row k of V change
+    others = [q for q in range(3) if q != k]
+    np.testing.assert_array_equal(U2[:, others], U[:, others])
+    np.testing.assert_array_equal(V2[others], V[others])
+    # component k is residual-consistent: U_tk + V_kj <= R_tj on given cells,
+    # and the last residual step is tight
+    lhs = U2[:, k][:, None] + V2[k][None, :]
+    assert np.all(lhs[M == 1] <= R[M == 1])
+    if op == "U":
+        np.testing.assert_array_equal(oracle.row_res(R, M, U2, V2, k, prec), U2)
+    else:
+        np.testing.assert_array_equal(oracle.col_res(R, M, U2, V2, k, prec), V2)
+    # returned error is the b-norm of the new state, with td_col
+    e_ref, td_ref, _ = oracle.masked_error(R, M, U2, V2, prec)
+    assert e == e_ref and np.array_equal(td, td_ref)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_update_step2_takes_effect(prec):
+    # F-ULF at (i,j,k) makes U_ik at least R_ij - V_kj (old V) when the
+    # component starts closed: the written value survives the closure.
+    R, M = synth.tiny_int_case(5, 7, 2, 21, hi=15, missing=0.0)
+    U = np.random.default_rng(21).integers(0, 15, (5, 2)).astype(np.float64)
+    V = np.zeros((2, 7))
+    for k in range(2):
+        V = oracle.col_res(R, M, U, V, k, prec)
+        U = oracle.row_res(R, M, U, V, k, prec)
+    changed = 0
+    for i, j in itertools.product(range(5), range(7)):
+        U2, V2, *_ = oracle.update("U", R, M, U, V, i, j, 0, prec)
+        assert U2[i, 0] >= R[i, j] - V[0, j]
+        assert U2[i, 0] + V2[0, j] <= R[i, j]
+        changed += int(not np.array_equal(U2, U))
+        U3, V3, *_ = oracle.update("V", R, M, U, V, i, j, 0, prec)
+        assert V3[0, j] >= R[i, j] - U[i, 0]
+    assert changed > 0
+
+
+# ------------------------------------------------------------------ Algorithm 3
+def _parse_a3():
+    g = read_golden("a3_fit_2x2.txt")
+    return g
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("noop", [1, 0])
+def test_fit_hand_derived_2x2(prec, noop):
+    g = _parse_a3()
+    R = g["R"].astype(np.float32); M = np.ones((2, 2), np.uint8)
+    res = oracle.fit(R, M, 2, 2, prec=prec, init_mode=2, U0=np.zeros((2, 2)),
+                     perm=np.array([0, 1]), noop_rule=noop)
+    assert res.status == 0
+    np.testing.assert_array_equal(res.traj, [float(x) for x in g["traj"][0]])
+    np.testing.assert_array_equal(res.U, g["U"]); np.testing.assert_array_equal(res.V, g["V"])
+    if noop:
+        want = [[int(x) for x in row] for row in g["log"]]
+        got = [[int(r["iter"]), int(r["row"]), int(r["trials"]), int(r["noops"]),
+                int(r["j"]), int(r["k"]), int(r["op"])] for r in res.log]
+        assert got == want
+
+
+def _brute_force_row(R, M, U, V, i, e, closed, noop_rule, prec):
+    """Independent restatement of one row visit of Algorithm 3 by brute force:
+    every (j, op) is evaluated from scratch with no early exit, the TD_A index
+    is counted with a Counter over the two multisets, and the first strict
+    decrease in (td_col desc, j asc; F-ULF then F-URF) order is returned."""
+    m, n = R.shape; r = U.shape[1]
+    _, td, A = oracle.masked_error(R, M, U, V, prec)
+    row_ms = [A[i, t] for t in range(n) if M[i, t]]
+    order = sorted([j for j in range(n) if M[i, j]], key=lambda j: (-td[j], j))
+    results = []
+    for j in order:
+        col_ms = [A[t, j] for t in range(m) if M[t, j]]
+        cnt = collections.Counter(row_ms) + collections.Counter(col_ms)
+        best = max(cnt.values())
+        k = min(l for l in range(r) if cnt.get(l, 0) == best)
+        for op in ("U", "V"):
+            T = np.float32 if prec == "f32" else np.float64
+            if noop_rule and closed[k]:
+                if op == "U" and T(T(R[i, j]) - T(V[k, j])) == T(U[i, k]):
+                    results.append((j, k, op, None)); continue
+                if op == "V" and T(T(R[i, j]) - T(U[i, k])) == T(V[k, j]):
+                    results.append((j, k, op, None)); continue
+            U2, V2, e2, *_ = oracle.update(op, R, M, U, V, i, j, k, prec)
+            results.append((j, k, op, (e2, U2, V2)))
+    for j, k, op, res in results:
+        if res is not None and res[0] < e:
+            return j, k, op, res
+    return None
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("seed", range(4))
+def test_fit_rows_match_brute_force(prec, seed):
+    m, n, r = 5, 7, 3
+    R, M = synth.tiny_int_case(m, n, r, 40 + seed, hi=9, missing=0.2, planted=True)
+    U0 = np.random.default_rng(seed).integers(0, 10, (m, r)).astype(np.float32)
+    perm = np.arange(m)
+    iters = 3
+    res = oracle.fit(R, M, r, iters, prec=prec, init_mode=2, U0=U0, perm=perm)
+    assert res.status == 0
+    # replay with brute force
+    U = U0.astype(np.float64); V = np.zeros((r, n))
+    for k in range(r):
+        V = oracle.col_res(R, M, U, V, k, prec)
+    e, _, _ = oracle.masked_error(R, M, U, V, prec)
+    closed = [False] * r
+    logi = 0
+    for it in range(1, iters + 1):
+        if logi >= len(res.log):
+            break
+        for i in range(m):
+            rec = res.log[logi]; logi += 1
+            got = _brute_force_row(R, M, U, V, i, e, closed, True, prec)
+            if got is None:
+                assert rec["j"] == -1
+            else:
+                j, k, op, (e2, U2, V2) = got
+                assert (rec["j"], rec["k"], rec["op"]) == (j, k, 0 if op == "U" else 1)
+                assert rec["e"] == e2
+                U, V, e = U2, V2, e2
+                closed[k] = True
+    np.testing.assert_array_equal(res.U, U.astype(np.float32))
+    np.testing.assert_array_equal(res.V, V.astype(np.float32))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_fit_trajectory_monotone_and_logs_strict(prec):
+    R, M = synth.int_planted(30, 24, 3, seed=8)
+    res = oracle.fit(R, M, 3, 4, seed=8, prec=prec, integer_exact=1)
+    assert res.status == 0
+    assert np.all(np.diff(res.traj) <= 0)
+    prev = res.traj[0]
+    for rec in res.log:
+        if rec["j"] >= 0:
+            assert rec["e"] < prev
+            prev = rec["e"]
+
+
+def test_fit_f32_equals_f64_on_integers_and_noop_rule_is_neutral():
+    R, M = synth.int_planted(24, 40, 3, seed=9)
+    a = oracle.fit(R, M, 3, 5, seed=9, prec="f64")
+    b = oracle.fit(R, M, 3, 5, seed=9, prec="f32")
+    c = oracle.fit(R, M, 3, 5, seed=9, prec="f32", noop_rule=0)
+    for x in (b, c):
+        np.testing.assert_array_equal(a.traj, x.traj)
+        np.testing.assert_array_equal(a.U, x.U)
+        np.testing.assert_array_equal(a.V, x.V)
+    assert c.stats["noops"] == 0 and b.stats["noops"] > 0
+    assert c.stats["trials"] == b.stats["trials"] + b.stats["noops"]
+
+
+def test_fit_metamorphic_shifts():
+    # R + c with U0 + c gives (U + c, V); R + 1 beta^T gives (U, V + beta)
+    R, M = synth.int_planted(20, 26, 2, seed=10)
+    U0 = np.random.default_rng(10).integers(0, 100, (20, 2)).astype(np.float32)
+    perm = np.random.default_rng(1).permutation(20)
+    base = oracle.fit(R, M, 2, 3, prec="f32", init_mode=2, U0=U0, perm=perm)
+    sh = oracle.fit(R + 7, M, 2, 3, prec="f32", init_mode=2, U0=U0 + 7, perm=perm)
+    np.testing.assert_array_equal(sh.U, base.U + 7); np.testing.assert_array_equal(sh.V, base.V)
+    np.testing.assert_array_equal(sh.traj, base.traj)
+    beta = np.random.default_rng(2).integers(-5, 5, (1, 26)).astype(np.float32)
+    cs = oracle.fit(R + beta, M, 2, 3, prec="f32", init_mode=2, U0=U0, perm=perm)
+    np.testing.assert_array_equal(cs.U, base.U); np.testing.assert_array_equal(cs.V, base.V + beta)
+    np.testing.assert_array_equal(cs.traj, base.traj)
+
+
+def test_fit_transpose_symmetry():
+    # Algorithm 3 transposes a tall matrix itself, so fit(R^T) returns the
+    # transposed factors of fit(R) (same seed, same working problem)
+    R, M = synth.int_planted(18, 30, 3, seed=12)
+    a = oracle.fit(R, M, 3, 3, seed=5, prec="f32")
+    b = oracle.fit(R.T.copy(), M.T.copy(), 3, 3, seed=5, prec="f32")
+    assert b.stats["transposed"] == 1 and a.stats["transposed"] == 0
+    np.testing.assert_array_equal(a.traj, b.traj)
+    np.testing.assert_array_equal(a.U, b.V.T); np.testing.assert_array_equal(a.V, b.U.T)
+
+
+def test_fit_output_unpermutes():
+    # the returned factors are in the caller's row order: their error on the
+    # original matrix equals the last trajectory value
+    R, M = synth.int_planted(16, 25, 3, seed=13)
+    a = oracle.fit(R, M, 3, 3, seed=77, prec="f64")
+    e, _, _ = oracle.masked_error(R, M, a.U, a.V, "f64")
+    assert e == a.traj[-1]
+    Rt, Mt = R.T.copy(), M.T.copy()
+    b = oracle.fit(Rt, Mt, 3, 3, seed=77, prec="f64")
+    e2, _, _ = oracle.masked_error(Rt, Mt, b.U, b.V, "f64")
+    assert e2 == b.traj[-1]
+
+
+def test_fit_errors():
+    R, M = synth.int_planted(10, 12, 2, seed=14)
+    M2 = M.copy(); M2[3] = 0
+    assert oracle.fit(R, M2, 2, 1).status == 2
+    M3 = M.copy(); M3[:, 5] = 0
+    assert oracle.fit(R, M3, 2, 1).status == 2
+    assert oracle.fit(R, M, 0, 1).status == 1
+    assert oracle.fit(R, M, 65, 1).status == 1
+    Rb = R.copy(); Rb[M == 1] = 2.0 ** 24
+    assert oracle.fit(Rb, M, 2, 1, integer_exact=1).status == 3
+    Rn = R.copy(); Rn[M == 0] = np.nan
+    a = oracle.fit(R, M, 2, 2, seed=3); b = oracle.fit(Rn, M, 2, 2, seed=3)
+    np.testing.assert_array_equal(a.traj, b.traj)
+
+
+def test_fixed_point_padding():
+    R, M = synth.int_planted(10, 14, 2, seed=15)
+    a = oracle.fit(R, M, 2, 40, seed=1, prec="f64")
+    assert a.stats["iters_done"] < 40
+    d = a.stats["iters_done"]
+    assert np.all(a.traj[d:] == a.traj[d])
