@@ -1,0 +1,253 @@
+/* stmf.h -- C ABI of the MI355X (gfx950) FastSTMF library.
+ *
+ * Sparse tropical matrix factorization R ~ U (x) V over the max-plus semiring,
+ * (U (x) V)_ij = max_l (U_il + V_lj)  (paper, Section 2), scored by the b-norm
+ * sum |R_ij - (U (x) V)_ij| over the observed cells only (Section 3.6), with
+ * the factors updated by FastSTMF (Algorithm 3: ByRow strategy, random row
+ * permutation, TD_A candidate selection, wide orientation) through the F-ULF
+ * and F-URF steps (Algorithms 1 and 2).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are dense, row-major, contiguous.  Values are IEEE binary32
+ *     (float); error sums are binary64 (double).
+ *   - Pointers documented "device" point to GPU memory owned by the caller;
+ *     "host" pointers to host memory owned by the caller.  The library never
+ *     allocates GPU memory: calls that need scratch take a workspace
+ *     (ws, ws_bytes) whose required size is returned by the matching
+ *     *_workspace() function; ws must be 256-byte aligned.
+ *   - M is a uint8 mask: 0 = missing, nonzero = observed.  Values of R at
+ *     missing cells are never used in arithmetic (they may be NaN).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     stream-ordered; argument errors are detected and returned before any
+ *     work is queued.  Calls documented "synchronous" wait for the stream.
+ *   - Indices are 0-based.  Ties in an argmax go to the lowest index
+ *     (Section 3.2.1, TD selection).
+ *   - Return value: an stmf_status.  After STMF_EHIP the stream's state is
+ *     unspecified.
+ *   - Thread safety: calls on different streams with disjoint buffers and
+ *     workspaces may run concurrently; the library keeps no global mutable
+ *     state besides a per-device property cache.
+ */
+#ifndef STMF_H
+#define STMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STMF_OK = 0,
+  STMF_EINVAL = 1,      /* bad argument (size, rank, index, null pointer, option)   */
+  STMF_EEMPTY_LINE = 2, /* a row or column of M has no observed cell                 */
+  STMF_ERANGE = 3,      /* integer-exact mode: a value with |x| >= 2^24, or a value
+                           outside the finite range the library accepts (|x| < 1e30) */
+  STMF_ENOMEM = 4,      /* workspace too small or misaligned                         */
+  STMF_EHIP = 5,        /* a HIP runtime call failed                                 */
+  STMF_EBUSY = 6,       /* serving engine: no slot or not enough memory free         */
+  STMF_ETIMEOUT = 7     /* a cooperative fit stopped: a group barrier waited > 4 s   */
+} stmf_status;
+
+/* Short English description of a status code (static string). */
+const char* stmf_status_str(int status);
+
+/* Library version as "major.minor.patch" (static string). */
+const char* stmf_version(void);
+
+/* ---------------------------------------------------------------- primitives */
+
+/* Max-plus product P = U (x) V (Section 2):
+ *   P[i*n + j] = max_l U[i*r + l] + V[l*n + j],  U m x r, V r x n (device).
+ * argmax (device, nullable, m x n int32) gets the lowest l reaching the max
+ * (the index f(i,j) of Section 3.2.1).  1 <= r <= 64; m, n >= 1. */
+int stmf_maxplus_product(const float* U, const float* V, int m, int r, int n,
+                         float* P, int32_t* argmax, void* stream);
+
+/* Workspace bytes of stmf_masked_error for an m x n matrix. */
+size_t stmf_masked_error_workspace(int m, int n, int r);
+
+/* Masked b-norm (Section 3.6, restricted to observed cells):
+ *   err[0] = sum over observed (i,j) of |R_ij - (U (x) V)_ij|
+ * Each difference is one FP32 subtraction, widened to FP64 and summed in a
+ * fixed order.  td_col (device, nullable, n doubles) gets the per-column sums
+ * td_col(j) of Section 3.2.1.  R m x n, M m x n, U m x r, V r x n (device);
+ * err is a device pointer to one double. */
+int stmf_masked_error(const float* R, const uint8_t* M, const float* U,
+                      const float* V, int m, int n, int r, double* err,
+                      double* td_col, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes of stmf_update_U / stmf_update_V. */
+size_t stmf_update_workspace(int m, int n, int r);
+
+/* F-ULF (Algorithm 1) at (i, j, k), in place on U (m x r) and V (r x n):
+ *   U_col_prev <- U[:,k], V_row_prev <- V[k,:]   (the backups Algorithm 1 returns)
+ *   U_ik <- R_ij - V_kj
+ *   V_kc <- min over observed t of R_tc - U_tk   for every column c
+ *   U_tk <- min over observed c of R_tc - V_kc   for every row t
+ *   err[0] <- masked b-norm of the new state
+ * The call never accepts or restores: the caller compares err with the
+ * previous error and copies the backups back to reject.  Requires M[i,j]
+ * observed (checked, synchronously: STMF_EINVAL otherwise) and 0 <= k < r.
+ * A line of M with no observed cell makes the matching residual +inf.
+ * U_col_prev (m floats), V_row_prev (n floats), err (1 double): device. */
+int stmf_update_U(const float* R, const uint8_t* M, float* U, float* V, int m,
+                  int n, int r, int i, int j, int k, float* U_col_prev,
+                  float* V_row_prev, double* err, void* ws, size_t ws_bytes,
+                  void* stream);
+
+/* F-URF (Algorithm 2): as stmf_update_U with V_kj <- R_ij - U_ik as the
+ * written value and the two residual steps in the order row residual of
+ * V_k. into U_.k first, then column residual of U_.k into V_k.. */
+int stmf_update_V(const float* R, const uint8_t* M, float* U, float* V, int m,
+                  int n, int r, int i, int j, int k, float* U_col_prev,
+                  float* V_row_prev, double* err, void* ws, size_t ws_bytes,
+                  void* stream);
+
+/* ---------------------------------------------------------------- fitting */
+
+typedef struct {
+  int init_mode;        /* 0 random integers in [init_lo, init_hi] (default),
+                           1 Random Acol (Section 3.3): U_tl = mean of the observed
+                             values of row t over acol_p randomly drawn columns,
+                             falling back to the row's observed mean,
+                           2 given: U0 (host, m' x rank, working orientation)     */
+  float init_lo, init_hi;
+  int acol_p;           /* columns averaged per U column in Random Acol (default 5) */
+  const float* U0;      /* host, init_mode 2                                        */
+  const int32_t* perm;  /* host, nullable: working-row permutation (m' entries)     */
+  double eps;           /* stop when a pass lowers the error by less (0 = off)      */
+  int count_scope;      /* TD_A counts over: 0 observed cells (default), 1 all cells */
+  int noop_rule;        /* 1 (default): a trial whose written value equals the
+                           stored one on a component last set by an accepted
+                           update is rejected without evaluation                     */
+  int integer_exact;    /* 1: STMF_ERANGE unless every observed |R| and |U0| < 2^24  */
+  void* decision_log;   /* device, nullable: one stmf_log_rec per row visit          */
+  int log_cap;          /* capacity of decision_log in records                       */
+  int batch_first;      /* speculative trials in the first batch of a row (default 8) */
+  int batch_max;        /* largest batch, <= 64 (default 64)                          */
+  int group_size;       /* workgroups cooperating on one fit (0 = automatic)          */
+  int max_row_visits;   /* stop after this many row visits (0 = no limit)            */
+} stmf_options;
+
+/* Per-row-visit decision record (decision_log). */
+typedef struct {
+  int32_t iter, row, trials, noops, j, k, op, pad; /* op 0 F-ULF, 1 F-URF; j = -1: none */
+  double e;                                        /* error after the visit             */
+} stmf_log_rec;
+
+/* Counters of a finished fit. */
+typedef struct {
+  long long trials;       /* trials the method evaluates (up to each accepted one) */
+  long long spec_trials;  /* trials evaluated, speculative ones included            */
+  long long noops;        /* trials skipped by the no-op rule                       */
+  long long accepted;     /* accepted updates                                       */
+  long long row_visits;
+  long long cells;        /* sum over evaluated trials of the observed-cell count   */
+  int iters_done;         /* passes run (fewer than iters at a fixed point)         */
+  int transposed;         /* 1 if the working orientation is R^T                    */
+  int m_work, n_work;     /* working shape (m' <= n')                               */
+  int group_size;         /* workgroups used                                        */
+  int nlog;               /* row visits logged (may exceed log_cap)                 */
+} stmf_fit_info;
+
+/* Defaults for every option. */
+void stmf_options_default(stmf_options* opt);
+
+/* Workspace bytes of stmf_fit for an m x n matrix at this rank and options. */
+size_t stmf_fit_workspace(int m, int n, int rank, int iters, const stmf_options* opt);
+
+/* FastSTMF (Algorithm 3).  Synchronous.
+ *   R, M: m x n (device).  U_out: m x rank, V_out: rank x n (device), in the
+ *   caller's orientation and row order.  err_traj (host, nullable): iters + 1
+ *   doubles, err_traj[p] = error after pass p (after initialisation for p = 0);
+ *   after a fixed point (a pass with no accepted update) or the eps stop the
+ *   rest is padded with the last value.  info (host, nullable).
+ *   seed drives SplitMix64: the working-row permutation is drawn first
+ *   (Durstenfeld shuffle), then the initial U.
+ * Errors: STMF_EINVAL, STMF_EEMPTY_LINE, STMF_ERANGE, STMF_ENOMEM, STMF_EHIP,
+ * STMF_ETIMEOUT. */
+int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters,
+             uint64_t seed, float* U_out, float* V_out, double* err_traj,
+             const stmf_options* opt, stmf_fit_info* info, void* ws,
+             size_t ws_bytes, void* stream);
+
+/* Setup draws of stmf_fit without fitting (host outputs): the working-row
+ * permutation (m' = min(m, n) entries) and the initial U (m' x rank, working
+ * orientation, before Random Acol averaging when init_mode = 1, which instead
+ * writes the drawn column indices, rank x acol_p, as floats). */
+int stmf_draw_init(int m, int n, int rank, uint64_t seed, const stmf_options* opt,
+                   int32_t* perm_out, float* U0_out);
+
+/* ---------------------------------------------------------------- batched */
+
+/* One problem of a batched fit.  R, M, U_out, V_out, err_traj: device.
+ * U_out holds `restarts` consecutive m x rank blocks, V_out `restarts`
+ * rank x n blocks and err_traj `restarts` blocks of iters + 1 doubles.
+ * status (written by the call) is per problem. */
+typedef struct {
+  const float* R;
+  const uint8_t* M;
+  int m, n, rank, iters;
+  uint64_t seed;
+  float* U_out;
+  float* V_out;
+  double* err_traj;
+  int status;
+  int pad;
+} stmf_problem;
+
+/* Workspace bytes of stmf_fit_batched. */
+size_t stmf_fit_batched_workspace(const stmf_problem* probs, int nprob, int restarts,
+                                  const stmf_options* opt);
+
+/* Many independent fits in one persistent launch (one workgroup per fit,
+ * longest fits first).  Restart q of problem p uses seed
+ * SplitMix64(probs[p].seed) output q.  Synchronous.  info (host, nullable)
+ * gets the summed counters.  Results equal stmf_fit with the same seed and
+ * group_size 1. */
+int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts,
+                     const stmf_options* opt, stmf_fit_info* info, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- serving */
+
+typedef struct stmf_engine stmf_engine;
+
+/* A continuous-batching engine over a caller-owned device arena (ws, bytes).
+ * Up to max_slots fits are resident at once; each holds its working matrix,
+ * factors and state in the arena from admission to retirement. */
+int stmf_engine_create(void* ws, size_t ws_bytes, int max_slots,
+                       const stmf_options* opt, stmf_engine** out);
+void stmf_engine_destroy(stmf_engine* eng);
+
+/* Arena bytes one job of this shape needs (admission footprint). */
+size_t stmf_job_footprint(int m, int n, int rank, int iters);
+
+/* Admit a job: copies R/M (device) into the arena and initialises the fit.
+ * STMF_EBUSY if no slot or not enough contiguous arena memory is free.
+ * Stream-ordered on `stream`; *slot gets the job's slot. */
+int stmf_engine_admit(stmf_engine* eng, const float* R, const uint8_t* M, int m,
+                      int n, int rank, int iters, uint64_t seed, int* slot,
+                      void* stream);
+
+/* Advance every active job by at most max_rows row visits, in one launch
+ * (one workgroup per job).  Stream-ordered; call stmf_engine_poll after
+ * synchronising the stream to see which jobs finished. */
+int stmf_batch_tick(stmf_engine* eng, int max_rows, void* stream);
+
+/* Synchronous: *done = 1 when the job in `slot` has finished. */
+int stmf_engine_poll(stmf_engine* eng, int slot, int* done, void* stream);
+
+/* Copy a finished job's results out (device U_out m x rank, V_out rank x n,
+ * host err_traj iters + 1 or NULL) and free its slot and arena memory.
+ * Synchronous. */
+int stmf_engine_retire(stmf_engine* eng, int slot, float* U_out, float* V_out,
+                       double* err_traj, stmf_fit_info* info, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STMF_H */

@@ -1,0 +1,863 @@
+// Host side of the C ABI declared in include/stmf.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/stmf.h"
+#include "stmf_internal.h"
+
+namespace stmf {
+
+// kernels (stmf_fit.hip, stmf_prims.hip, stmf_setup.hip)
+__global__ void fit_kernel(const FitDev* fits, int nfits, int gsize, int max_rows, unsigned* queue);
+size_t fit_smem_bytes();
+size_t masked_error_ws(int m, int n);
+hipError_t launch_maxplus(const float*, const float*, int, int, int, float*, int32_t*, hipStream_t);
+hipError_t launch_masked_error(const float*, const uint8_t*, const float*, const float*, int, int,
+                               int, double*, double*, void*, hipStream_t);
+hipError_t launch_update(int, const float*, const uint8_t*, float*, float*, int, int, int, int, int,
+                         int, float*, float*, double*, void*, hipStream_t);
+__global__ void check_count_kernel(const float*, const uint8_t*, int, int, int*, int*, CheckOut*);
+__global__ void check_empty_kernel(const int*, const int*, int, int, CheckOut*);
+__global__ void fill_u32_kernel(unsigned*, size_t, unsigned);
+__global__ void pack_kernel(const float*, const uint8_t*, int, int, int, int, int, int, const int*,
+                            float*);
+__global__ void transpose_kernel(const float*, int, int, float*);
+__global__ void u0_given_kernel(const float*, int, int, int, float*);
+__global__ void u0_acol_kernel(const float*, int, int, int, int, int, int, const int*, float*);
+__global__ void vinit_kernel(const float*, const float*, int, int, int, int, int, float*);
+__global__ void output_kernel(const float*, const float*, int, int, int, int, int, int, const int*,
+                              float*, float*);
+__global__ void copy_f64_kernel(const double*, double*, int);
+
+// ---------------------------------------------------------------- randomness
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): a Weyl sequence with step
+// 0x9E3779B97F4A7C15 passed through a 64-bit mixing finaliser.
+struct Rng {
+  uint64_t s;
+  uint64_t next() {
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  // uniform in [0, bound): reject draws below 2^64 mod bound, then reduce
+  uint64_t below(uint64_t bound) {
+    const uint64_t floor_ = (~bound + 1) % bound;
+    for (;;) {
+      uint64_t x = next();
+      if (x >= floor_) return x % bound;
+    }
+  }
+};
+
+// ---------------------------------------------------------------- helpers
+static inline size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+static inline int rup(int x, int a) { return (x + a - 1) / a * a; }
+
+#define HIPCHK(expr)                                   \
+  do {                                                 \
+    hipError_t _e = (expr);                            \
+    if (_e != hipSuccess) return STMF_EHIP;            \
+  } while (0)
+
+struct DevProps {
+  int cus = 0;
+  int coresident = 0;  // fit_kernel workgroups that fit at once
+  bool ok = false;
+};
+
+static std::mutex g_props_mu;
+static DevProps g_props[64];
+
+static int device_props(DevProps& out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return STMF_EHIP;
+  std::lock_guard<std::mutex> lk(g_props_mu);
+  DevProps& p = g_props[dev];
+  if (!p.ok) {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    p.cus = prop.multiProcessorCount;
+    const size_t smem = fit_smem_bytes();
+    HIPCHK(hipFuncSetAttribute((const void*)fit_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)smem));
+    int per = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)fit_kernel, NTHR, smem));
+    p.coresident = per * p.cus;
+    p.ok = true;
+  }
+  out = p;
+  return STMF_OK;
+}
+
+void options_default(stmf_options* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->init_mode = 0;
+  o->init_lo = 0.0f;
+  o->init_hi = 100.0f;
+  o->acol_p = 5;
+  o->noop_rule = 1;
+  o->batch_first = 8;
+  o->batch_max = TMAX;
+}
+
+static int check_options(const stmf_options& o) {
+  if (o.init_mode < 0 || o.init_mode > 2) return STMF_EINVAL;
+  if (o.init_mode == 2 && !o.U0) return STMF_EINVAL;
+  if (o.init_mode == 0 && !(o.init_hi >= o.init_lo)) return STMF_EINVAL;
+  if (o.init_mode == 1 && o.acol_p < 1) return STMF_EINVAL;
+  if (o.count_scope < 0 || o.count_scope > 1) return STMF_EINVAL;
+  if (o.batch_first < 1 || o.batch_max < 1 || o.batch_max > TMAX) return STMF_EINVAL;
+  if (o.group_size < 0 || o.log_cap < 0 || o.max_row_visits < 0) return STMF_EINVAL;
+  if (!(o.eps >= 0.0)) return STMF_EINVAL;
+  return STMF_OK;
+}
+
+// ---------------------------------------------------------------- layout
+struct Layout {
+  int m, n, r, iters;
+  int mw, nw, ldm, ldn, nrt, nct, ldmax, G, acol_p;
+  int transposed;
+  size_t Rw, RwT, Uc, V, td, tdpart, crow, ccol, colst, rowst, colpart, rowpart, order, cand,
+      tvec, epart, closed, traj, ctl, dev, perm, stage, check, rowc, colc;
+  size_t total;
+};
+
+static void make_layout(int m, int n, int r, int iters, int G, int acol_p, Layout& L) {
+  L.m = m; L.n = n; L.r = r; L.iters = iters; L.G = G; L.acol_p = acol_p;
+  L.transposed = m > n;
+  L.mw = L.transposed ? n : m;
+  L.nw = L.transposed ? m : n;
+  L.ldm = rup(L.mw, TS);
+  L.ldn = rup(L.nw, TS);
+  L.nrt = L.ldm / TS;
+  L.nct = L.ldn / TS;
+  L.ldmax = std::max(L.ldm, L.ldn);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o += al256(bytes); return at; };
+  L.Rw = take((size_t)L.ldm * L.ldn * 4);
+  L.RwT = take((size_t)L.ldn * L.ldm * 4);
+  L.Uc = take((size_t)r * L.ldm * 4);
+  L.V = take((size_t)r * L.ldn * 4);
+  L.td = take((size_t)L.ldn * 8);
+  L.tdpart = take((size_t)L.nrt * L.ldn * 8);
+  L.crow = take((size_t)L.ldm * r * 4);
+  L.ccol = take((size_t)L.ldn * r * 4);
+  L.colst = take((size_t)r * L.ldn * sizeof(Top2));
+  L.rowst = take((size_t)r * L.ldm * sizeof(Top2));
+  L.colpart = take((size_t)L.nrt * L.ldn * sizeof(Top2));
+  L.rowpart = take((size_t)L.nct * L.ldm * sizeof(Top2));
+  L.order = take((size_t)L.ldn * 4);
+  L.cand = take((size_t)L.ldn * 4);
+  L.tvec = take((size_t)2 * TMAX * L.ldmax * 4);
+  L.epart = take((size_t)TMAX * G * 8);
+  L.closed = take((size_t)r * 4);
+  L.traj = take((size_t)(iters + 1) * 8);
+  L.ctl = take(sizeof(FitCtl));
+  L.dev = take(sizeof(FitDev));
+  L.perm = take((size_t)L.mw * 4);
+  L.stage = take(std::max((size_t)L.mw * r * 4, (size_t)r * acol_p * 4));
+  L.check = take(sizeof(CheckOut));
+  L.rowc = take((size_t)m * 4);
+  L.colc = take((size_t)n * 4);
+  L.total = o;
+}
+
+static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int observed) {
+  FitDev d;
+  std::memset(&d, 0, sizeof(d));
+  d.m = L.mw; d.n = L.nw; d.r = L.r;
+  d.ldm = L.ldm; d.ldn = L.ldn; d.nrt = L.nrt; d.nct = L.nct;
+  d.iters = L.iters;
+  d.noop_rule = o.noop_rule; d.count_scope = o.count_scope;
+  d.tmax = o.batch_max;
+  d.t0 = std::min(o.batch_first, o.batch_max);
+  d.log_cap = o.decision_log ? o.log_cap : 0;
+  d.eps = o.eps;
+  d.omega = observed;
+  d.Rw = (const float*)(base + L.Rw);
+  d.RwT = (const float*)(base + L.RwT);
+  d.Uc = (float*)(base + L.Uc);
+  d.V = (float*)(base + L.V);
+  d.td = (double*)(base + L.td);
+  d.tdpart = (double*)(base + L.tdpart);
+  d.crow = (int*)(base + L.crow);
+  d.ccol = (int*)(base + L.ccol);
+  d.colst = (Top2*)(base + L.colst);
+  d.rowst = (Top2*)(base + L.rowst);
+  d.colpart = (Top2*)(base + L.colpart);
+  d.rowpart = (Top2*)(base + L.rowpart);
+  d.order = (int*)(base + L.order);
+  d.cand = (int*)(base + L.cand);
+  d.tvec = (unsigned*)(base + L.tvec);
+  d.epart = (double*)(base + L.epart);
+  d.closed = (int*)(base + L.closed);
+  d.traj = (double*)(base + L.traj);
+  d.log = (LogRec*)o.decision_log;
+  d.ctl = (FitCtl*)(base + L.ctl);
+  d.ldmax = L.ldmax;
+  d.gsize = L.G;
+  return d;
+}
+
+static int fill_u32(void* p, size_t count, unsigned v, hipStream_t s) {
+  if (!count) return STMF_OK;
+  size_t blocks = std::min<size_t>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (unsigned*)p, count, v);
+  return hipGetLastError() == hipSuccess ? STMF_OK : STMF_EHIP;
+}
+
+// Check R and M (synchronous): empty lines, non-finite observed values,
+// magnitudes.  Uses the layout's rowc/colc/check scratch.
+static int check_inputs(const float* R, const uint8_t* M, const Layout& L, char* base, int int_exact,
+                        hipStream_t s, int* observed = nullptr) {
+  int st = fill_u32(base + L.rowc, (size_t)L.m, 0, s);
+  if (!st) st = fill_u32(base + L.colc, (size_t)L.n, 0, s);
+  if (!st) st = fill_u32(base + L.check, sizeof(CheckOut) / 4, 0, s);
+  if (st) return st;
+  const size_t total = (size_t)L.m * L.n;
+  const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(check_count_kernel, dim3(blocks), dim3(256), 0, s, R, M, L.m, L.n,
+                     (int*)(base + L.rowc), (int*)(base + L.colc), (CheckOut*)(base + L.check));
+  const int mx = std::max(L.m, L.n);
+  hipLaunchKernelGGL(check_empty_kernel, dim3((mx + 255) / 256), dim3(256), 0, s,
+                     (const int*)(base + L.rowc), (const int*)(base + L.colc), L.m, L.n,
+                     (CheckOut*)(base + L.check));
+  HIPCHK(hipGetLastError());
+  CheckOut h;
+  HIPCHK(hipMemcpyAsync(&h, base + L.check, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (observed) *observed = h.observed;
+  if (h.empty_rows || h.empty_cols) return STMF_EEMPTY_LINE;
+  if (h.nonfinite) return STMF_EINVAL;
+  if (h.too_big) return STMF_ERANGE;
+  if (int_exact && h.not_int24) return STMF_ERANGE;
+  return STMF_OK;
+}
+
+// Draws of a fit from its seed: the working permutation (unless given), then
+// the initial U (random integers) or the Random Acol column indices.
+static int draw_setup(const Layout& L, uint64_t seed, const stmf_options& o,
+                      std::vector<int32_t>& perm, std::vector<float>& U0, std::vector<int32_t>& cols) {
+  Rng g{seed};
+  perm.resize(L.mw);
+  if (o.perm) {
+    std::vector<char> hit(L.mw, 0);
+    for (int a = 0; a < L.mw; ++a) {
+      int p = o.perm[a];
+      if (p < 0 || p >= L.mw || hit[p]) return STMF_EINVAL;
+      hit[p] = 1;
+      perm[a] = p;
+    }
+  } else {
+    for (int a = 0; a < L.mw; ++a) perm[a] = a;
+    for (int a = L.mw - 1; a >= 1; --a) {
+      int b = (int)g.below((uint64_t)a + 1);
+      std::swap(perm[a], perm[b]);
+    }
+  }
+  if (o.init_mode == 0) {
+    const int64_t lo = (int64_t)o.init_lo, hi = (int64_t)o.init_hi;
+    const uint64_t span = (uint64_t)(hi - lo + 1);
+    U0.resize((size_t)L.mw * L.r);
+    for (size_t q = 0; q < U0.size(); ++q) U0[q] = (float)(lo + (int64_t)g.below(span));
+  } else if (o.init_mode == 1) {
+    cols.resize((size_t)L.r * o.acol_p);
+    for (size_t q = 0; q < cols.size(); ++q) cols[q] = (int)g.below((uint64_t)L.nw);
+  } else {
+    U0.assign(o.U0, o.U0 + (size_t)L.mw * L.r);
+  }
+  return STMF_OK;
+}
+
+// Working matrix, initial U and V, control block: everything a fit kernel
+// needs, stream-ordered.  Host vectors must outlive the copies: the caller
+// synchronises before they go out of scope.
+static int prepare_fit(const float* R, const uint8_t* M, const Layout& L, char* base,
+                       const stmf_options& o, const std::vector<int32_t>& perm,
+                       const std::vector<float>& U0, const std::vector<int32_t>& cols,
+                       hipStream_t s) {
+  if (o.integer_exact && o.init_mode != 1)
+    for (float x : U0)
+      if (!(std::fabs(x) < 16777216.0f)) return STMF_ERANGE;
+  for (float x : U0)
+    if (!std::isfinite(x) || std::fabs(x) >= 1e30f) return STMF_ERANGE;
+  HIPCHK(hipMemcpyAsync(base + L.perm, perm.data(), perm.size() * 4, hipMemcpyHostToDevice, s));
+  {
+    dim3 grid((L.ldn + 255) / 256, L.ldm);
+    hipLaunchKernelGGL(pack_kernel, grid, dim3(256), 0, s, R, M, L.n, L.mw, L.nw, L.ldm, L.ldn,
+                       L.transposed, (const int*)(base + L.perm), (float*)(base + L.Rw));
+    dim3 tg(L.ldn / TS, L.ldm / TS);
+    hipLaunchKernelGGL(transpose_kernel, tg, dim3(256), 0, s, (const float*)(base + L.Rw), L.ldm,
+                       L.ldn, (float*)(base + L.RwT));
+  }
+  if (o.init_mode == 1) {
+    HIPCHK(hipMemcpyAsync(base + L.stage, cols.data(), cols.size() * 4, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(u0_acol_kernel, dim3((L.ldm + 255) / 256), dim3(256), 0, s,
+                       (const float*)(base + L.Rw), L.mw, L.nw, L.ldm, L.ldn, L.r, o.acol_p,
+                       (const int*)(base + L.stage), (float*)(base + L.Uc));
+  } else {
+    HIPCHK(hipMemcpyAsync(base + L.stage, U0.data(), U0.size() * 4, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(u0_given_kernel, dim3((L.ldm + 255) / 256, L.r), dim3(256), 0, s,
+                       (const float*)(base + L.stage), L.mw, L.r, L.ldm, (float*)(base + L.Uc));
+  }
+  hipLaunchKernelGGL(vinit_kernel, dim3((L.ldn + 255) / 256, L.r), dim3(256), 0, s,
+                     (const float*)(base + L.Rw), (const float*)(base + L.Uc), L.mw, L.nw, L.ldm,
+                     L.ldn, L.r, (float*)(base + L.V));
+  HIPCHK(hipGetLastError());
+  int st = fill_u32(base + L.ctl, sizeof(FitCtl) / 4, 0, s);
+  if (!st) st = fill_u32(base + L.closed, (size_t)L.r, 0, s);
+  if (!st) st = fill_u32(base + L.traj, (size_t)(L.iters + 1) * 2, 0, s);
+  return st;
+}
+
+static int launch_output(const Layout& L, char* base, float* U_out, float* V_out, hipStream_t s) {
+  const int mx = std::max(L.mw, L.nw);
+  hipLaunchKernelGGL(output_kernel, dim3((mx + 255) / 256, L.r), dim3(256), 0, s,
+                     (const float*)(base + L.Uc), (const float*)(base + L.V), L.mw, L.nw, L.ldm,
+                     L.ldn, L.r, L.transposed, (const int*)(base + L.perm), U_out, V_out);
+  return hipGetLastError() == hipSuccess ? STMF_OK : STMF_EHIP;
+}
+
+static int launch_fit_kernel(const FitDev* dev_fits, int nfits, int G, int grid, int max_rows,
+                             unsigned* queue, hipStream_t s) {
+  const size_t smem = fit_smem_bytes();
+  if (G > 1) {
+    void* args[] = {(void*)&dev_fits, (void*)&nfits, (void*)&G, (void*)&max_rows, (void*)&queue};
+    HIPCHK(hipLaunchCooperativeKernel((const void*)fit_kernel, dim3(grid), dim3(NTHR), args,
+                                      (unsigned)smem, s));
+  } else {
+    hipLaunchKernelGGL(fit_kernel, dim3(grid), dim3(NTHR), smem, s, dev_fits, nfits, G, max_rows,
+                       queue);
+    HIPCHK(hipGetLastError());
+  }
+  return STMF_OK;
+}
+
+static void fill_info(stmf_fit_info* info, const FitCtl& c, const Layout& L) {
+  if (!info) return;
+  info->trials += c.trials;
+  info->spec_trials += c.spec_trials;
+  info->noops += c.noops;
+  info->accepted += c.accepted;
+  info->row_visits += c.row_visits;
+  info->cells += c.cells;
+  info->iters_done = c.iters_done;
+  info->transposed = L.transposed;
+  info->m_work = L.mw;
+  info->n_work = L.nw;
+  info->group_size = L.G;
+  info->nlog += c.nlog;
+}
+
+static int auto_group(const Layout& L, const DevProps& P, int requested) {
+  const int ntiles = L.nrt * L.nct;
+  int G = requested > 0 ? requested : ntiles;
+  G = std::min(G, ntiles);
+  G = std::min(G, P.coresident);
+  return std::max(G, 1);
+}
+
+}  // namespace stmf
+
+using namespace stmf;
+
+// ================================================================ C ABI
+extern "C" {
+
+const char* stmf_status_str(int s) {
+  switch (s) {
+    case STMF_OK: return "ok";
+    case STMF_EINVAL: return "invalid argument";
+    case STMF_EEMPTY_LINE: return "a row or column has no observed cell";
+    case STMF_ERANGE: return "value out of the supported range";
+    case STMF_ENOMEM: return "workspace too small or misaligned";
+    case STMF_EHIP: return "HIP runtime error";
+    case STMF_EBUSY: return "no free slot or memory";
+    case STMF_ETIMEOUT: return "cooperative fit timed out at a group barrier";
+    default: return "unknown status";
+  }
+}
+
+const char* stmf_version(void) { return "0.1.0"; }
+
+void stmf_options_default(stmf_options* o) {
+  if (o) options_default(o);
+}
+
+int stmf_maxplus_product(const float* U, const float* V, int m, int r, int n, float* P,
+                         int32_t* argmax, void* stream) {
+  if (!U || !V || (!P && !argmax) || m < 1 || n < 1 || r < 1 || r > RMAX) return STMF_EINVAL;
+  HIPCHK(launch_maxplus(U, V, m, r, n, P, argmax, (hipStream_t)stream));
+  return STMF_OK;
+}
+
+size_t stmf_masked_error_workspace(int m, int n, int r) {
+  (void)r;
+  if (m < 1 || n < 1) return 0;
+  return masked_error_ws(m, n);
+}
+
+int stmf_masked_error(const float* R, const uint8_t* M, const float* U, const float* V, int m,
+                      int n, int r, double* err, double* td_col, void* ws, size_t ws_bytes,
+                      void* stream) {
+  if (!R || !M || !U || !V || !err || m < 1 || n < 1 || r < 1 || r > RMAX) return STMF_EINVAL;
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < masked_error_ws(m, n)) return STMF_ENOMEM;
+  HIPCHK(launch_masked_error(R, M, U, V, m, n, r, err, td_col, ws, (hipStream_t)stream));
+  return STMF_OK;
+}
+
+size_t stmf_update_workspace(int m, int n, int r) { return stmf_masked_error_workspace(m, n, r); }
+
+static int update_common(int op, const float* R, const uint8_t* M, float* U, float* V, int m, int n,
+                         int r, int i, int j, int k, float* Ub, float* Vb, double* err, void* ws,
+                         size_t ws_bytes, void* stream) {
+  if (!R || !M || !U || !V || !Ub || !Vb || !err || m < 1 || n < 1 || r < 1 || r > RMAX)
+    return STMF_EINVAL;
+  if (i < 0 || i >= m || j < 0 || j >= n || k < 0 || k >= r) return STMF_EINVAL;
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < masked_error_ws(m, n)) return STMF_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t obs = 0;
+  HIPCHK(hipMemcpyAsync(&obs, M + (size_t)i * n + j, 1, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (!obs) return STMF_EINVAL;
+  HIPCHK(launch_update(op, R, M, U, V, m, n, r, i, j, k, Ub, Vb, err, ws, s));
+  return STMF_OK;
+}
+
+int stmf_update_U(const float* R, const uint8_t* M, float* U, float* V, int m, int n, int r, int i,
+                  int j, int k, float* Ub, float* Vb, double* err, void* ws, size_t ws_bytes,
+                  void* stream) {
+  return update_common(0, R, M, U, V, m, n, r, i, j, k, Ub, Vb, err, ws, ws_bytes, stream);
+}
+
+int stmf_update_V(const float* R, const uint8_t* M, float* U, float* V, int m, int n, int r, int i,
+                  int j, int k, float* Ub, float* Vb, double* err, void* ws, size_t ws_bytes,
+                  void* stream) {
+  return update_common(1, R, M, U, V, m, n, r, i, j, k, Ub, Vb, err, ws, ws_bytes, stream);
+}
+
+static int resolve(const stmf_options* opt, stmf_options& o) {
+  if (opt) o = *opt; else options_default(&o);
+  return check_options(o);
+}
+
+size_t stmf_fit_workspace(int m, int n, int rank, int iters, const stmf_options* opt) {
+  stmf_options o;
+  if (resolve(opt, o) || m < 1 || n < 1 || rank < 1 || rank > RMAX || iters < 0) return 0;
+  DevProps P;
+  if (device_props(P)) return 0;
+  Layout L;
+  make_layout(m, n, rank, iters, 1, o.acol_p, L);
+  const int G = auto_group(L, P, o.group_size);
+  make_layout(m, n, rank, iters, G, o.acol_p, L);
+  return L.total;
+}
+
+int stmf_draw_init(int m, int n, int rank, uint64_t seed, const stmf_options* opt,
+                   int32_t* perm_out, float* U0_out) {
+  stmf_options o;
+  int st = resolve(opt, o);
+  if (st) return st;
+  if (m < 1 || n < 1 || rank < 1 || rank > RMAX) return STMF_EINVAL;
+  Layout L;
+  make_layout(m, n, rank, 0, 1, o.acol_p, L);
+  std::vector<int32_t> perm, cols;
+  std::vector<float> U0;
+  st = draw_setup(L, seed, o, perm, U0, cols);
+  if (st) return st;
+  if (perm_out) std::memcpy(perm_out, perm.data(), perm.size() * 4);
+  if (U0_out) {
+    if (o.init_mode == 1)
+      for (size_t q = 0; q < cols.size(); ++q) U0_out[q] = (float)cols[q];
+    else
+      std::memcpy(U0_out, U0.data(), U0.size() * 4);
+  }
+  return STMF_OK;
+}
+
+int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters, uint64_t seed,
+             float* U_out, float* V_out, double* err_traj, const stmf_options* opt,
+             stmf_fit_info* info, void* ws, size_t ws_bytes, void* stream) {
+  stmf_options o;
+  int st = resolve(opt, o);
+  if (st) return st;
+  if (!R || !M || !U_out || !V_out || m < 1 || n < 1 || rank < 1 || rank > RMAX || iters < 0)
+    return STMF_EINVAL;
+  if (o.decision_log && o.log_cap <= 0) return STMF_EINVAL;
+  DevProps P;
+  st = device_props(P);
+  if (st) return st;
+  Layout L;
+  make_layout(m, n, rank, iters, 1, o.acol_p, L);
+  const int G = auto_group(L, P, o.group_size);
+  make_layout(m, n, rank, iters, G, o.acol_p, L);
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < L.total) return STMF_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws;
+  int observed = 0;
+  st = check_inputs(R, M, L, base, o.integer_exact, s, &observed);
+  if (st) return st;
+  std::vector<int32_t> perm, cols;
+  std::vector<float> U0;
+  st = draw_setup(L, seed, o, perm, U0, cols);
+  if (st) return st;
+  st = prepare_fit(R, M, L, base, o, perm, U0, cols, s);
+  if (st) return st;
+  FitDev d = make_dev(L, base, o, observed);
+  HIPCHK(hipMemcpyAsync(base + L.dev, &d, sizeof(d), hipMemcpyHostToDevice, s));
+  st = launch_fit_kernel((const FitDev*)(base + L.dev), 1, G, G, o.max_row_visits, nullptr, s);
+  if (st) return st;
+  FitCtl c;
+  HIPCHK(hipMemcpyAsync(&c, base + L.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (c.status == STMF_ETIMEOUT) return STMF_ETIMEOUT;
+  if (c.status != 0) return STMF_EHIP;
+  st = launch_output(L, base, U_out, V_out, s);
+  if (st) return st;
+  if (err_traj)
+    HIPCHK(hipMemcpyAsync(err_traj, base + L.traj, (size_t)(iters + 1) * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    fill_info(info, c, L);
+  }
+  return STMF_OK;
+}
+
+// ---------------------------------------------------------------- batched
+struct BatchPlan {
+  std::vector<Layout> L;       // one per fit (problem-major, restart-minor)
+  std::vector<size_t> off;     // workspace offset of each fit
+  std::vector<int> prob;       // problem of each fit
+  std::vector<uint64_t> seed;  // seed of each fit
+  size_t table, queue, total;
+};
+
+static void plan_batched(const stmf_problem* probs, int nprob, int restarts, const stmf_options& o,
+                         BatchPlan& B) {
+  size_t o_ = 0;
+  for (int p = 0; p < nprob; ++p) {
+    Rng g{probs[p].seed};
+    for (int q = 0; q < restarts; ++q) {
+      Layout L;
+      make_layout(probs[p].m, probs[p].n, probs[p].rank, probs[p].iters, 1, o.acol_p, L);
+      B.L.push_back(L);
+      B.off.push_back(o_);
+      B.prob.push_back(p);
+      B.seed.push_back(restarts == 1 ? probs[p].seed : g.next());
+      o_ += L.total;
+    }
+  }
+  B.table = o_;
+  o_ += al256(B.L.size() * sizeof(FitDev));
+  B.queue = o_;
+  o_ += 256;
+  B.total = o_;
+}
+
+size_t stmf_fit_batched_workspace(const stmf_problem* probs, int nprob, int restarts,
+                                  const stmf_options* opt) {
+  stmf_options o;
+  if (resolve(opt, o) || !probs || nprob < 1 || restarts < 1) return 0;
+  for (int p = 0; p < nprob; ++p)
+    if (probs[p].m < 1 || probs[p].n < 1 || probs[p].rank < 1 || probs[p].rank > RMAX ||
+        probs[p].iters < 0)
+      return 0;
+  BatchPlan B;
+  plan_batched(probs, nprob, restarts, o, B);
+  return B.total;
+}
+
+int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts, const stmf_options* opt,
+                     stmf_fit_info* info, void* ws, size_t ws_bytes, void* stream) {
+  stmf_options o;
+  int st = resolve(opt, o);
+  if (st) return st;
+  if (!probs || nprob < 1 || restarts < 1) return STMF_EINVAL;
+  if (o.decision_log || o.perm || o.init_mode == 2 || o.max_row_visits) return STMF_EINVAL;
+  for (int p = 0; p < nprob; ++p)
+    if (!probs[p].R || !probs[p].M || !probs[p].U_out || !probs[p].V_out || probs[p].m < 1 ||
+        probs[p].n < 1 || probs[p].rank < 1 || probs[p].rank > RMAX || probs[p].iters < 0)
+      return STMF_EINVAL;
+  DevProps P;
+  st = device_props(P);
+  if (st) return st;
+  BatchPlan B;
+  plan_batched(probs, nprob, restarts, o, B);
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < B.total) return STMF_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws;
+  const int F = (int)B.L.size();
+  // input checks, one problem at a time (restarts share the input)
+  std::vector<int> observed(nprob, 0);
+  for (int p = 0; p < nprob; ++p) {
+    int first = p * restarts;
+    probs[p].status = check_inputs(probs[p].R, probs[p].M, B.L[first], base + B.off[first],
+                                   o.integer_exact, s, &observed[p]);
+  }
+  std::vector<FitDev> table;
+  std::vector<std::vector<int32_t>> perms(F), colss(F);
+  std::vector<std::vector<float>> U0s(F);
+  std::vector<int> fit_ids;
+  for (int f = 0; f < F; ++f) {
+    const int p = B.prob[f];
+    if (probs[p].status) continue;
+    const Layout& L = B.L[f];
+    char* fb = base + B.off[f];
+    int s2 = draw_setup(L, B.seed[f], o, perms[f], U0s[f], colss[f]);
+    if (!s2) s2 = prepare_fit(probs[p].R, probs[p].M, L, fb, o, perms[f], U0s[f], colss[f], s);
+    if (s2) { probs[p].status = s2; continue; }
+    fit_ids.push_back(f);
+  }
+  // longest fits first
+  std::stable_sort(fit_ids.begin(), fit_ids.end(), [&](int a, int b) {
+    const Layout& A = B.L[a];
+    const Layout& C = B.L[b];
+    return (double)A.mw * A.nw * A.r > (double)C.mw * C.nw * C.r;
+  });
+  for (int f : fit_ids) table.push_back(make_dev(B.L[f], base + B.off[f], o, observed[B.prob[f]]));
+  if (!table.empty()) {
+    HIPCHK(hipMemcpyAsync(base + B.table, table.data(), table.size() * sizeof(FitDev),
+                          hipMemcpyHostToDevice, s));
+    st = fill_u32(base + B.queue, 1, 0, s);
+    if (st) return st;
+    const int grid = std::min<int>((int)table.size(), P.coresident);
+    st = launch_fit_kernel((const FitDev*)(base + B.table), (int)table.size(), 1, grid, 0,
+                           (unsigned*)(base + B.queue), s);
+    if (st) return st;
+  }
+  HIPCHK(hipStreamSynchronize(s));  // host staging vectors go out of scope after this
+  if (info) std::memset(info, 0, sizeof(*info));
+  for (int f : fit_ids) {
+    const Layout& L = B.L[f];
+    char* fb = base + B.off[f];
+    const int p = B.prob[f];
+    const int q = f - p * restarts;
+    FitCtl c;
+    HIPCHK(hipMemcpyAsync(&c, fb + L.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (c.status) { probs[p].status = c.status == STMF_ETIMEOUT ? STMF_ETIMEOUT : STMF_EHIP; continue; }
+    float* Uo = probs[p].U_out + (size_t)q * L.m * L.r;
+    float* Vo = probs[p].V_out + (size_t)q * L.r * L.n;
+    st = launch_output(L, fb, Uo, Vo, s);
+    if (st) return st;
+    if (probs[p].err_traj)
+      hipLaunchKernelGGL(copy_f64_kernel, dim3((L.iters + 1 + 255) / 256), dim3(256), 0, s,
+                         (const double*)(fb + L.traj), probs[p].err_traj + (size_t)q * (L.iters + 1),
+                         L.iters + 1);
+    fill_info(info, c, L);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return STMF_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ serving
+// A continuous-batching engine: jobs are admitted into slots of a
+// caller-owned arena (first-fit over a free list, by footprint), each tick
+// advances every active job by a bounded number of row visits in one launch
+// (one workgroup per job, state kept in the arena between ticks), and
+// finished jobs are retired to free their memory for new admissions.
+struct stmf_engine {
+  char* arena = nullptr;
+  size_t bytes = 0;
+  int max_slots = 0;
+  stmf_options opt;
+  size_t table_off = 0, queue_off = 0, heap_off = 0;
+  struct Slot {
+    bool used = false;
+    size_t off = 0, len = 0;
+    Layout L;
+    FitDev dev;
+    std::vector<int32_t> perm, cols;
+    std::vector<float> U0;
+  };
+  std::vector<Slot> slots;
+  std::vector<std::pair<size_t, size_t>> free_list;  // (offset, length), by offset
+  std::mutex mu;
+};
+
+static bool arena_alloc(stmf_engine* e, size_t len, size_t& off) {
+  for (size_t q = 0; q < e->free_list.size(); ++q) {
+    auto& fb = e->free_list[q];
+    if (fb.second >= len) {
+      off = fb.first;
+      fb.first += len;
+      fb.second -= len;
+      if (!fb.second) e->free_list.erase(e->free_list.begin() + q);
+      return true;
+    }
+  }
+  return false;
+}
+
+static void arena_free(stmf_engine* e, size_t off, size_t len) {
+  auto& F = e->free_list;
+  auto it = std::lower_bound(F.begin(), F.end(), std::make_pair(off, (size_t)0));
+  it = F.insert(it, {off, len});
+  // merge with the next and previous blocks
+  size_t q = (size_t)(it - F.begin());
+  if (q + 1 < F.size() && F[q].first + F[q].second == F[q + 1].first) {
+    F[q].second += F[q + 1].second;
+    F.erase(F.begin() + q + 1);
+  }
+  if (q > 0 && F[q - 1].first + F[q - 1].second == F[q].first) {
+    F[q - 1].second += F[q].second;
+    F.erase(F.begin() + q);
+  }
+}
+
+extern "C" {
+
+size_t stmf_job_footprint(int m, int n, int rank, int iters) {
+  if (m < 1 || n < 1 || rank < 1 || rank > RMAX || iters < 0) return 0;
+  Layout L;
+  make_layout(m, n, rank, iters, 1, 5, L);
+  return L.total;
+}
+
+int stmf_engine_create(void* ws, size_t ws_bytes, int max_slots, const stmf_options* opt,
+                       stmf_engine** out) {
+  if (!out || max_slots < 1) return STMF_EINVAL;
+  stmf_options o;
+  int st = resolve(opt, o);
+  if (st) return st;
+  if (o.decision_log || o.perm || o.init_mode == 2 || o.max_row_visits || o.group_size > 1)
+    return STMF_EINVAL;
+  if (!ws || ((uintptr_t)ws & 255)) return STMF_ENOMEM;
+  const size_t table = al256((size_t)max_slots * sizeof(FitDev));
+  if (ws_bytes < table + 256 + 256) return STMF_ENOMEM;
+  DevProps P;
+  st = device_props(P);
+  if (st) return st;
+  stmf_engine* e = new (std::nothrow) stmf_engine();
+  if (!e) return STMF_ENOMEM;
+  e->arena = (char*)ws;
+  e->bytes = ws_bytes;
+  e->max_slots = max_slots;
+  e->opt = o;
+  e->table_off = 0;
+  e->queue_off = table;
+  e->heap_off = table + 256;
+  e->slots.resize(max_slots);
+  e->free_list.push_back({e->heap_off, (ws_bytes - e->heap_off) / 256 * 256});
+  *out = e;
+  return STMF_OK;
+}
+
+void stmf_engine_destroy(stmf_engine* e) { delete e; }
+
+int stmf_engine_admit(stmf_engine* e, const float* R, const uint8_t* M, int m, int n, int rank,
+                      int iters, uint64_t seed, int* slot, void* stream) {
+  if (!e || !R || !M || !slot || m < 1 || n < 1 || rank < 1 || rank > RMAX || iters < 0)
+    return STMF_EINVAL;
+  std::lock_guard<std::mutex> lk(e->mu);
+  int sidx = -1;
+  for (int q = 0; q < e->max_slots; ++q)
+    if (!e->slots[q].used) { sidx = q; break; }
+  if (sidx < 0) return STMF_EBUSY;
+  stmf_engine::Slot& S = e->slots[sidx];
+  make_layout(m, n, rank, iters, 1, e->opt.acol_p, S.L);
+  size_t off = 0;
+  if (!arena_alloc(e, S.L.total, off)) return STMF_EBUSY;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = e->arena + off;
+  int observed = 0;
+  int st = check_inputs(R, M, S.L, base, e->opt.integer_exact, s, &observed);
+  if (!st) st = draw_setup(S.L, seed, e->opt, S.perm, S.U0, S.cols);
+  if (!st) st = prepare_fit(R, M, S.L, base, e->opt, S.perm, S.U0, S.cols, s);
+  if (st) {
+    arena_free(e, off, S.L.total);
+    return st;
+  }
+  S.used = true;
+  S.off = off;
+  S.len = S.L.total;
+  S.dev = make_dev(S.L, base, e->opt, observed);
+  *slot = sidx;
+  return STMF_OK;
+}
+
+int stmf_batch_tick(stmf_engine* e, int max_rows, void* stream) {
+  if (!e || max_rows < 0) return STMF_EINVAL;
+  std::lock_guard<std::mutex> lk(e->mu);
+  static thread_local std::vector<FitDev> table;
+  table.clear();
+  for (auto& S : e->slots)
+    if (S.used) table.push_back(S.dev);
+  if (table.empty()) return STMF_OK;
+  DevProps P;
+  int st = device_props(P);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(e->arena + e->table_off, table.data(), table.size() * sizeof(FitDev),
+                        hipMemcpyHostToDevice, s));
+  st = fill_u32(e->arena + e->queue_off, 1, 0, s);
+  if (st) return st;
+  const int grid = std::min<int>((int)table.size(), P.coresident);
+  st = launch_fit_kernel((const FitDev*)(e->arena + e->table_off), (int)table.size(), 1, grid,
+                         max_rows, (unsigned*)(e->arena + e->queue_off), s);
+  if (st) return st;
+  // the table is read by the launch: wait for it before the host array changes
+  HIPCHK(hipStreamSynchronize(s));
+  return STMF_OK;
+}
+
+int stmf_engine_poll(stmf_engine* e, int slot, int* done, void* stream) {
+  if (!e || !done || slot < 0 || slot >= e->max_slots) return STMF_EINVAL;
+  std::lock_guard<std::mutex> lk(e->mu);
+  stmf_engine::Slot& S = e->slots[slot];
+  if (!S.used) return STMF_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  FitCtl c;
+  HIPCHK(hipMemcpyAsync(&c, e->arena + S.off + S.L.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (c.status) return c.status == STMF_ETIMEOUT ? STMF_ETIMEOUT : STMF_EHIP;
+  *done = c.phase == 2;
+  return STMF_OK;
+}
+
+int stmf_engine_retire(stmf_engine* e, int slot, float* U_out, float* V_out, double* err_traj,
+                       stmf_fit_info* info, void* stream) {
+  if (!e || slot < 0 || slot >= e->max_slots) return STMF_EINVAL;
+  std::lock_guard<std::mutex> lk(e->mu);
+  stmf_engine::Slot& S = e->slots[slot];
+  if (!S.used) return STMF_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = e->arena + S.off;
+  int st = STMF_OK;
+  if (U_out && V_out) {
+    FitCtl c;
+    HIPCHK(hipMemcpyAsync(&c, base + S.L.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (c.phase != 2) return STMF_EINVAL;
+    st = launch_output(S.L, base, U_out, V_out, s);
+    if (st) return st;
+    if (err_traj)
+      HIPCHK(hipMemcpyAsync(err_traj, base + S.L.traj, (size_t)(S.L.iters + 1) * 8,
+                            hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      fill_info(info, c, S.L);
+    }
+  }
+  arena_free(e, S.off, S.len);
+  S.used = false;
+  S.perm.clear(); S.U0.clear(); S.cols.clear();
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Internal layout shared by the HIP kernels and the host side of the library.
+// (Not part of the public ABI; the public declarations live in include/stmf.h.)
+#pragma once
+#include <stdint.h>
+
+namespace stmf {
+
+constexpr int TS = 64;          // tile side: 64 rows x 64 columns of the working matrix
+constexpr int NWAVE = 4;        // waves per workgroup
+constexpr int NTHR = 64 * NWAVE;
+constexpr int TMAX = 64;        // trials per speculative batch (upper bound)
+constexpr int TPW = TMAX / NWAVE;  // trials one wave owns in a batch
+constexpr int RMAX = 64;        // largest supported rank
+
+// Top-2 summary of a residual line: smallest value, its (lowest) index, and
+// the second smallest value (equal to m1 on ties; +inf if the line has one
+// observed cell).
+struct Top2 {
+  float m1;
+  int a1;
+  float m2;
+  int pad;
+};
+
+enum Op : int { OP_ULF = 0, OP_URF = 1, OP_NULL = 2 };
+
+struct Trial {
+  int j, k, op;
+  float val;   // the step-2 value written at (i, k) of U (F-ULF) or (k, j) of V (F-URF)
+};
+
+// Results of the input checks of a fit.
+struct CheckOut {
+  int empty_rows, empty_cols;
+  int nonfinite;   // an observed value that is not finite
+  int too_big;     // an observed |R| >= 1e30
+  int not_int24;   // an observed |R| >= 2^24
+  int observed;    // observed cells
+  int pad[2];
+};
+
+// One record per row visit (decision log).
+struct LogRec {
+  int32_t iter, row, trials, noops, j, k, op, pad;
+  double e;
+};
+
+// Control block of one fit (device memory).  Everything a resumed launch
+// needs to continue a fit lives here or in the arrays of FitDev.
+struct FitCtl {
+  double e;              // current b-norm (FP64)
+  double e_new;          // error of the trial chosen by the last batch
+  int decision;          // index of the first improving trial of the batch, -1 none
+  int status;            // 0 ok; nonzero aborts the fit
+  int phase;             // 0 needs init, 1 iterating, 2 done
+  int it;                // current pass (1-based) while iterating
+  int row;               // next working row to visit
+  int acc_in_pass;       // acceptances in the current pass
+  int ncand;             // candidates of the current row
+  int iters_done;
+  unsigned bar_count;    // group barrier
+  unsigned bar_gen;
+  unsigned queue;        // batched launches: next fit to take (only in ctl[0])
+  unsigned pad0;
+  long long trials;      // trials the method evaluates (up to the accepted one)
+  long long spec_trials; // trials evaluated including speculative ones
+  long long noops;       // trials skipped by the no-op rule
+  long long accepted;
+  long long row_visits;
+  long long batches;
+  long long cells;       // sum over evaluated trials of |Omega| (method count)
+  int nlog;
+  int pad1;
+};
+
+// Device-side descriptor of one fit.  All arrays live in the caller's
+// workspace.  Working orientation: m <= n, rows permuted.
+struct FitDev {
+  int m, n, r;           // working shape and rank
+  int ldm, ldn;          // padded extents (multiples of TS)
+  int nrt, nct;          // tile counts
+  int iters;
+  int noop_rule, count_scope;
+  int tmax;              // largest batch
+  int t0;                // first batch of a row visit
+  int log_cap;
+  int omega;             // number of observed cells
+  double eps;
+  const float* Rw;       // ldm x ldn, +inf at unobserved and padding cells
+  const float* RwT;      // ldn x ldm, the transpose
+  float* Uc;             // r x ldm: Uc[l*ldm + t] = U_tl
+  float* V;              // r x ldn: V[l*ldn + c]  = V_lc
+  double* td;            // ldn: td_col
+  double* tdpart;        // nrt x ldn
+  int* crow;             // ldm x r: argmax counts of every row
+  int* ccol;             // ldn x r: argmax counts of every column
+  Top2* colst;           // r x ldn: top-2 of R_tc - U_tk over t (per component)
+  Top2* rowst;           // r x ldm: top-2 of R_tc - V_kc over c
+  Top2* colpart;         // nrt x ldn: per row-tile partial of colst (one component)
+  Top2* rowpart;         // nct x ldm
+  int* order;            // ldn: columns by (td_col desc, index asc)
+  int* cand;             // ldn: candidate columns of the current row
+  unsigned* tvec;        // 2 x TMAX x ldmax: atomic-min targets (order-mapped floats)
+  double* epart;         // TMAX x gsize: per-workgroup partial errors
+  int* closed;           // r
+  double* traj;          // iters + 1
+  LogRec* log;           // nullable
+  FitCtl* ctl;
+  int ldmax;
+  int gsize;             // workgroups cooperating on this fit
+};
+
+}  // namespace stmf

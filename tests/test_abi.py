@@ -1,0 +1,118 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library loads, exports every function include/stmf.h declares, reports
+argument errors before touching the GPU, and its host-side random draws
+(SplitMix64 permutation and initial U) equal the oracle's independent ones.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2205_06619_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def stmf():
+    from paper_2205_06619_amd import build
+    build.build(force=False)
+    from paper_2205_06619_amd import stmf as S
+    return S
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "stmf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(stmf_\w+)\s*\(", src))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("stmf_maxplus_product", "stmf_masked_error", "stmf_update_U", "stmf_update_V",
+                 "stmf_fit", "stmf_fit_batched", "stmf_batch_tick"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(stmf):
+    for name in declared_functions():
+        assert hasattr(stmf.lib, name), name
+    assert set(stmf.EXPORTS) == set(declared_functions())
+
+
+def test_status_strings(stmf):
+    for s in range(8):
+        assert stmf.status_str(s)
+    assert stmf.lib.stmf_version().decode().count(".") == 2
+
+
+def test_argument_errors_before_any_gpu_work(stmf):
+    L = stmf.lib
+    dummy = C.c_void_p(256)
+    assert L.stmf_maxplus_product(dummy, dummy, 0, 1, 1, dummy, None, None) == stmf.STMF_EINVAL
+    assert L.stmf_maxplus_product(dummy, dummy, 1, 65, 1, dummy, None, None) == stmf.STMF_EINVAL
+    assert L.stmf_maxplus_product(None, dummy, 1, 1, 1, dummy, None, None) == stmf.STMF_EINVAL
+    # every call below fails its argument checks before any GPU work
+    need = L.stmf_masked_error_workspace(10, 10, 2)
+    assert need > 0
+    assert L.stmf_masked_error(dummy, dummy, dummy, dummy, 10, 10, 2, dummy, None,
+                               C.c_void_p(257), need, None) == stmf.STMF_ENOMEM
+    assert L.stmf_masked_error(dummy, dummy, dummy, dummy, 10, 10, 2, dummy, None,
+                               C.c_void_p(256), 8, None) == stmf.STMF_ENOMEM
+    assert L.stmf_update_U(dummy, dummy, dummy, dummy, 4, 4, 2, 4, 0, 0, dummy, dummy, dummy,
+                           C.c_void_p(256), 1 << 20, None) == stmf.STMF_EINVAL
+    assert L.stmf_update_V(dummy, dummy, dummy, dummy, 4, 4, 2, 0, 0, 2, dummy, dummy, dummy,
+                           C.c_void_p(256), 1 << 20, None) == stmf.STMF_EINVAL
+    o = stmf.options(batch_max=65)
+    assert L.stmf_fit(dummy, dummy, 4, 4, 2, 1, 0, dummy, dummy, None, C.byref(o), None,
+                      C.c_void_p(256), 1 << 30, None) == stmf.STMF_EINVAL
+    o = stmf.options()
+    assert L.stmf_fit(dummy, dummy, 4, 4, 0, 1, 0, dummy, dummy, None, C.byref(o), None,
+                      C.c_void_p(256), 1 << 30, None) == stmf.STMF_EINVAL
+    assert L.stmf_job_footprint(0, 5, 2, 1) == 0
+    assert L.stmf_job_footprint(50, 40, 2, 1) > 50 * 40 * 8
+
+
+@pytest.mark.parametrize("m,n,rank,seed", [(200, 100, 3, 0), (40, 70, 5, 11), (33, 33, 2, 7),
+                                           (1, 9, 1, 3)])
+def test_library_draws_equal_oracle_draws(stmf, m, n, rank, seed):
+    # SplitMix64 permutation then U0, implemented independently on both sides
+    perm, U0 = stmf.stmf_draw_init(m, n, rank, seed)
+    R = np.zeros((m, n), np.float32); M = np.ones((m, n), np.uint8)
+    s, operm, oU0 = oracle.draw_init(R, M, rank, seed)
+    assert s == 0
+    np.testing.assert_array_equal(perm, operm)
+    np.testing.assert_array_equal(U0.reshape(oU0.shape), oU0)
+
+
+def test_library_acol_draws_equal_oracle(stmf):
+    m, n, rank, seed = 30, 50, 4, 9
+    perm, cols = stmf.stmf_draw_init(m, n, rank, seed, init_mode=1, acol_p=5)
+    # the oracle's Random Acol consumes the same stream: permutation, then
+    # rank * p column indices; recover U0 on the oracle side and compare the
+    # averages it implies
+    R, M = synth.gene_expr(m, n, rank, 0.3, seed=1)
+    s, operm, oU0 = oracle.draw_init(R, M, rank, seed, init_mode=1, acol_p=5)
+    np.testing.assert_array_equal(perm, operm)
+    cols = cols.astype(np.int64).reshape(rank, 5)
+    Rw = R[operm]; Mw = M[operm]
+    for t in range(m):
+        for l in range(rank):
+            vals = [float(Rw[t, c]) for c in cols[l] if Mw[t, c]]
+            if vals:
+                s_ = 0.0
+                for v in vals:
+                    s_ += v
+                want = np.float32(s_ / len(vals))
+            else:
+                obs = [float(x) for x, o in zip(Rw[t], Mw[t]) if o]
+                s_ = 0.0
+                for v in obs:
+                    s_ += v
+                want = np.float32(s_ / len(obs))
+            assert oU0[t, l] == want
