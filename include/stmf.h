@@ -125,8 +125,8 @@ typedef struct {
   int integer_exact;    /* 1: STMF_ERANGE unless every observed |R| and |U0| < 2^24  */
   void* decision_log;   /* device, nullable: one stmf_log_rec per row visit          */
   int log_cap;          /* capacity of decision_log in records                       */
-  int batch_first;      /* speculative trials in the first batch of a row (default 8) */
-  int batch_max;        /* largest batch, <= 64 (default 64)                          */
+  int batch_first;      /* speculative trials in the first batch of a row (default 16) */
+  int batch_max;        /* largest batch, <= 512 (default 512)                         */
   int group_size;       /* workgroups cooperating on one fit (0 = automatic)          */
   int max_row_visits;   /* stop after this many row visits (0 = no limit)            */
 } stmf_options;
@@ -150,6 +150,11 @@ typedef struct {
   int m_work, n_work;     /* working shape (m' <= n')                               */
   int group_size;         /* workgroups used                                        */
   int nlog;               /* row visits logged (may exceed log_cap)                 */
+  long long batches;      /* speculative batches evaluated                          */
+  double phase_ms[8];     /* time of the fit kernel's phases on the group leader:
+                             candidates, batch lists, residual pass, error pass and
+                             decision, apply and refresh, bookkeeping               */
+  double kernel_ms;       /* fit kernel time, HIP events on the fit's stream        */
 } stmf_fit_info;
 
 /* Defaults for every option. */

@@ -3,7 +3,7 @@
 // host round trip per trial.
 //
 // A "group" of G workgroups owns one fit (G = 1 for the batched and serving
-// paths, G = the whole grid for one large fit).  The working matrix is cut
+// paths, up to the whole chip for one large fit).  The working matrix is cut
 // into 64 x 64 tiles; workgroup g of the group takes tiles g, g + G, ...
 //
 // Every trial of a row visit starts from the same state (a rejected F-ULF or
@@ -23,12 +23,19 @@
 //   The new product is P' = max(P without k, U''_tk + V'_kc), bit-identical
 //   to a full max over components (max is exact and order-free).
 // Every value operation is one correctly rounded FP32 operation; |R - P'| is
-// widened to FP64 and summed in a fixed order (lane, tile, workgroup), so a
-// trial's error depends only on the state and the trial.
+// widened to FP64 and summed in a fixed order (lane, tile, workgroup, chunk),
+// so a trial's error depends only on the state and the trial.
+//
+// Per row visit: batches (residual pass, group barrier, error pass, group
+// barrier with the decision taken by the last workgroup to arrive); after an
+// acceptance the refresh pass (new component written, argmax counts, td_col
+// partials, residual summaries of the component), one barrier, the summary
+// combine while one workgroup sorts the columns by td_col, one barrier.
 #include <hip/hip_runtime.h>
 #include <float.h>
 #include <stdint.h>
 
+#define STMF_FIT_KERNEL_TU
 #include "stmf_internal.h"
 
 namespace stmf {
@@ -38,6 +45,8 @@ namespace stmf {
 static constexpr float FINF = __builtin_huge_valf();
 static constexpr unsigned long long BARRIER_TIMEOUT = 400000000ull;  // 4 s at 100 MHz
 static constexpr int ST_TIMEOUT = 7;
+static constexpr int RPW = TS / NWAVE;  // tile rows (or columns) per wave
+static constexpr int CQ_CAP = NTHR + CW + 128;
 
 DEV unsigned fmap(float f) {
   unsigned u = __float_as_uint(f);
@@ -63,16 +72,50 @@ DEV Top2 top2_add(Top2 s, float v, int idx) {
   return top2_comb(s, one);
 }
 
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GA __attribute__((address_space(1)))
+#else
+#define GA
+#endif
+
 template <typename T>
-DEV T ld_atomic(const T* p) {
+DEV T ld_atomic(const GA T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Device-coherent access to data that other workgroups of the group write or
+// read during the fit (relaxed agent-scope atomics: coherent across XCDs
+// without cache maintenance).  The working matrix, which nothing writes
+// during the fit, is read with plain cached loads.
+template <typename T>
+DEV void st_coh(GA T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV Top2 ld_top2(const GA Top2* p) {
+  const GA unsigned long long* q = reinterpret_cast<const GA unsigned long long*>(p);
+  unsigned long long a = ld_atomic(q), b = ld_atomic(q + 1);
+  Top2 s;
+  s.m1 = __uint_as_float((unsigned)a);
+  s.a1 = (int)(a >> 32);
+  s.m2 = __uint_as_float((unsigned)b);
+  s.pad = 0;
+  return s;
+}
+DEV void st_top2(GA Top2* p, Top2 s) {
+  GA unsigned long long* q = reinterpret_cast<GA unsigned long long*>(p);
+  st_coh(q, (unsigned long long)__float_as_uint(s.m1) | ((unsigned long long)(unsigned)s.a1 << 32));
+  st_coh(q + 1, (unsigned long long)__float_as_uint(s.m2));
+}
+DEV void atomic_min_g(GA unsigned* p, unsigned v) {
+  __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV void atomic_add_g(GA int* p, int v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ------------------------------------------------------------ LDS layout
 struct BatchScratch {
-  float sA[TMAX][TS];        // per trial: value of the changed U column at the tile rows
-  float sB[TMAX][TS];        // per trial: value of the changed V row at the tile columns
-  double wacc[TMAX][TS];     // per trial, per lane running FP64 sums over this WG's tiles
+  float sA[TCH][TS];         // per staged trial: changed U column at the tile rows
+  float sB[TCH][TS];         // per staged trial: changed V row at the tile columns
 };
 struct RefreshScratch {
   int hc[TS][RMAX];          // argmax histogram of the tile columns
@@ -81,34 +124,68 @@ struct RefreshScratch {
   Top2 csw[NWAVE][TS];
   Top2 rsw[NWAVE][TS];
 };
+struct SortScratch {
+  double key[SORT_MAX];
+  int idx[SORT_MAX];
+};
+struct CombineScratch {
+  Top2 part[2048];           // staged partial summaries
+  double dpart[2048];        // staged td_col partials
+};
+struct ReduceScratch {
+  double v[4096];            // staged per-workgroup partial errors
+  double chunk[TMAX];        // chunk sums of the trials being reduced
+};
 struct Smem {
   union {
     BatchScratch b;
     RefreshScratch f;
+    SortScratch s;
+    CombineScratch c;
+    ReduceScratch r;
   } u;
   float Ps[TS][TS + 1];      // tile of max over l != k of U_tl + V_lc
+  float Ut[RMAX][TS];        // U of the tile rows, every component
+  float Vt[RMAX][TS];        // V of the tile columns, every component
+  float uk[TS], vk[TS];      // new component values of the tile (refresh)
+  double wsum[TMAX];         // per trial: this workgroup's partial error
   Trial trials[TMAX];
-  int noops_before[TMAX];
-  int prev_ops[TMAX];
-  int kdistinct[TMAX];
+  int noops_before[TMAX];    // no-op skips preceding each trial in the batch
+  int byk[TMAX];             // trial indices grouped by component (stable)
+  int kdistinct[RMAX];
+  int kstart[RMAX + 1];
+  float urow_i[RMAX];        // U of the visited row, every component
+  int closed_s[RMAX];        // closed flags at the start of the row visit
+  int crow_i[RMAX];          // argmax counts of the visited row
+  int cq[CQ_CAP];            // queue of candidate columns of the visited row
+  int cq_head, cq_n, ord_pos;
   int prev_nt;
   int nt;
   int nk;
   int batch_noops;
-  int cur_q, cur_op;         // cursor in the candidate list
+  int cur_op;
   int exhausted;
   int is_last;
   int status;
-  // candidate scan scratch
-  int cj[64], ck[64];
-  float cvu[64], cvv[64];
-  int cnu[64], cnv[64];
-  int scan[NTHR + 1];
+  int dec;
+  int wcount[NWAVE];
+  int wnoop[NWAVE];
+  int wcn[NWAVE];
+  int wlast[NWAVE];
+  // candidate window
+  int cj[CW], ck[CW];
+  float cvu[CW], cvv[CW];
+  int cnu[CW], cnv[CW];
+  int kbest[CW][4], kval[CW][4];
+  float vsel[CW];
 };
+
+static_assert(sizeof(Smem) <= 160 * 1024, "LDS layout exceeds a CU's 160 KB");
+static_assert(TMAX <= NTHR && 2 * CW <= NTHR && CW * 4 <= NTHR, "one thread per trial / pair");
 
 struct Grp {
   const FitDev* d;
-  FitCtl* ctl;
+  GA FitCtl* ctl;
   int g, G;
   int lane, wave, tid;
 };
@@ -121,19 +198,21 @@ struct Grp {
 // when the fit has been aborted.
 template <typename F>
 DEV bool group_sync_last(Grp& gp, Smem& S, F last_work) {
-  FitCtl* ctl = gp.ctl;
+  GA FitCtl* ctl = gp.ctl;
+  // every wave's stores (all device-coherent) are complete before arriving
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (gp.G == 1) {
     S.is_last = 1;
   } else if (gp.tid == 0) {
-    unsigned gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned old = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL,
+    unsigned gen = ld_atomic(&ctl->bar_gen);
+    unsigned old = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
     S.is_last = (old == (unsigned)gp.G - 1) ? 1 : 0;
     if (!S.is_last) {
       unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
-      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        if (__hip_atomic_load(&ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      while (ld_atomic(&ctl->bar_gen) == gen) {
+        if (ld_atomic(&ctl->status) != 0) break;
         if (__builtin_amdgcn_s_memrealtime() - t0 > BARRIER_TIMEOUT) {
           int zero = 0;
           __hip_atomic_compare_exchange_strong(&ctl->status, &zero, ST_TIMEOUT, __ATOMIC_RELAXED,
@@ -147,15 +226,16 @@ DEV bool group_sync_last(Grp& gp, Smem& S, F last_work) {
   __syncthreads();
   if (S.is_last) {
     last_work();
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (gp.G > 1 && gp.tid == 0) {
-      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      unsigned gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl->bar_gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      st_coh(&ctl->bar_count, 0u);
+      __builtin_amdgcn_s_waitcnt(0);
+      const unsigned gen = ld_atomic(&ctl->bar_gen);
+      st_coh(&ctl->bar_gen, gen + 1);
     }
   }
-  if (gp.tid == 0)
-    S.status = __hip_atomic_load(&ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (gp.tid == 0) S.status = ld_atomic(&ctl->status);
   __syncthreads();
   return S.status == 0;
 }
@@ -176,191 +256,283 @@ DEV void slice(int n, int g, int G, int& lo, int& hi) {
 // ------------------------------------------------------------ per-trial vectors
 // Row-side value of trial tr at working row t (the changed U column):
 //   F-ULF: U''_tk from the atomic-min pass; F-URF: U'_tk from the top-2 row
-//   summary; null trial: the current U_tk.
-DEV float row_side(const FitDev& d, const Trial& tr, int par, int slot, int t, int i) {
-  (void)i;
+//   summary; null trial: the current U_tk.  Padding rows: 0.
+DEV float row_side(const FitDev& d, const Trial& tr, int par, int slot, int t) {
   if (t >= d.m) return 0.0f;
   if (tr.op == OP_ULF)
     return funmap(ld_atomic(&d.tvec[((size_t)par * TMAX + slot) * d.ldmax + t]));
   if (tr.op == OP_URF) {
-    Top2 s = d.rowst[(size_t)tr.k * d.ldm + t];
+    Top2 s = ld_top2(&d.rowst[(size_t)tr.k * d.ldm + t]);
     float x = d.RwT[(size_t)tr.j * d.ldm + t] - tr.val;
     return fminf(excl(s, tr.j), x);
   }
-  return d.Uc[(size_t)tr.k * d.ldm + t];
+  return ld_atomic(&d.Uc[(size_t)tr.k * d.ldm + t]);
 }
 
 // Column-side value of trial tr at working column c (the changed V row).
 DEV float col_side(const FitDev& d, const Trial& tr, int par, int slot, int c, int i) {
   if (c >= d.n) return 0.0f;
   if (tr.op == OP_ULF) {
-    Top2 s = d.colst[(size_t)tr.k * d.ldn + c];
+    Top2 s = ld_top2(&d.colst[(size_t)tr.k * d.ldn + c]);
     float x = d.Rw[(size_t)i * d.ldn + c] - tr.val;
     return fminf(excl(s, i), x);
   }
   if (tr.op == OP_URF)
     return funmap(ld_atomic(&d.tvec[((size_t)par * TMAX + slot) * d.ldmax + c]));
-  return d.V[(size_t)tr.k * d.ldn + c];
+  return ld_atomic(&d.V[(size_t)tr.k * d.ldn + c]);
+}
+
+// U of the tile rows and V of the tile columns for every component, staged in
+// LDS in one round of independent loads.
+DEV void stage_uv(Grp& gp, Smem& S, int r0, int c0) {
+  const FitDev& d = *gp.d;
+  for (int e = gp.tid; e < d.r * TS; e += NTHR) {
+    const int l = e / TS, x = e % TS;
+    S.Ut[l][x] = ld_atomic(&d.Uc[(size_t)l * d.ldm + r0 + x]);
+    S.Vt[l][x] = ld_atomic(&d.V[(size_t)l * d.ldn + c0 + x]);
+  }
+}
+
+// Max over l != k of U_tl + V_lc for the tile from the staged U and V
+// (cooperative: wave w fills rows RPW*w .. RPW*w + RPW - 1), left in S.Ps.
+// With rank 1 the set is empty (-inf).
+DEV void compute_pnotk(Grp& gp, Smem& S, int k) {
+  const FitDev& d = *gp.d;
+  float P[RPW];
+#pragma unroll
+  for (int tt = 0; tt < RPW; ++tt) P[tt] = -FINF;
+  const int tl0 = gp.wave * RPW;
+  for (int l = 0; l < d.r; ++l) {
+    if (l == k) continue;
+    const float v = S.Vt[l][gp.lane];
+#pragma unroll
+    for (int tt = 0; tt < RPW; ++tt) P[tt] = fmaxf(P[tt], S.Ut[l][tl0 + tt] + v);
+  }
+#pragma unroll
+  for (int tt = 0; tt < RPW; ++tt) S.Ps[tl0 + tt][gp.lane] = P[tt];
 }
 
 // ------------------------------------------------------------ pass 1 of a batch
 // Second residual of every trial over this workgroup's tiles, combined across
 // tiles with an atomic min on order-preserving integer images (exact).
+// Trials are staged TCH at a time.
 DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
   const FitDev& d = *gp.d;
   const int nt = S.nt;
-  bool anyU = false, anyV = false;
-  for (int q = 0; q < nt; ++q) {
-    anyU |= S.trials[q].op == OP_ULF;
-    anyV |= S.trials[q].op == OP_URF;
-  }
   const int ntile = d.nrt * d.nct;
   for (int tile = gp.g; tile < ntile; tile += gp.G) {
     const int rt = tile / d.nct, ct = tile % d.nct;
     const int r0 = rt * TS, c0 = ct * TS;
-    __syncthreads();
-    // incremental first residuals for the tile: ULF needs V'_k. on the tile
-    // columns, URF needs U'_.k on the tile rows
-    for (int e = gp.tid; e < nt * TS; e += NTHR) {
-      int q = e / TS, x = e % TS;
-      const Trial& tr = S.trials[q];
-      if (tr.op == OP_ULF) S.u.b.sB[q][x] = col_side(d, tr, par, q, c0 + x, i);
-      else if (tr.op == OP_URF) S.u.b.sA[q][x] = row_side(d, tr, par, q, r0 + x, i);
-    }
-    __syncthreads();
-    if (anyU) {
-      // lanes over rows: U''_tk = min over the tile columns of R_tc - V'_kc
-      float Rrow[TS];
-#pragma unroll
-      for (int c = 0; c < TS; ++c) Rrow[c] = d.RwT[(size_t)(c0 + c) * d.ldm + r0 + gp.lane];
-      for (int q = gp.wave; q < nt; q += NWAVE) {
-        if (S.trials[q].op != OP_ULF) continue;
-        float x = FINF;
-#pragma unroll
-        for (int c = 0; c < TS; ++c) x = fminf(x, Rrow[c] - S.u.b.sB[q][c]);
-        if (x != FINF)
-          atomicMin(&d.tvec[((size_t)par * TMAX + q) * d.ldmax + r0 + gp.lane], fmap(x));
+    for (int cs = 0; cs < nt; cs += TCH) {
+      const int cn = nt - cs < TCH ? nt - cs : TCH;
+      __syncthreads();
+      // incremental first residuals for the tile: F-ULF needs V'_k. on the
+      // tile columns, F-URF needs U'_.k on the tile rows
+      bool anyU = false, anyV = false;
+      for (int s2 = 0; s2 < cn; ++s2) {
+        anyU |= S.trials[cs + s2].op == OP_ULF;
+        anyV |= S.trials[cs + s2].op == OP_URF;
       }
-    }
-    if (anyV) {
-      // lanes over columns: V''_kc = min over the tile rows of R_tc - U'_tk
-      float Rcol[TS];
+      for (int e = gp.tid; e < cn * TS; e += NTHR) {
+        const int sl = e / TS, x = e % TS, q = cs + sl;
+        const Trial& tr = S.trials[q];
+        if (tr.op == OP_ULF) S.u.b.sB[sl][x] = col_side(d, tr, par, q, c0 + x, i);
+        else if (tr.op == OP_URF) S.u.b.sA[sl][x] = row_side(d, tr, par, q, r0 + x);
+      }
+      __syncthreads();
+      if (anyU) {
+        // lanes over rows: U''_tk = min over the tile columns of R_tc - V'_kc
+        float Rrow[TS];
 #pragma unroll
-      for (int t = 0; t < TS; ++t) Rcol[t] = d.Rw[(size_t)(r0 + t) * d.ldn + c0 + gp.lane];
-      for (int q = gp.wave; q < nt; q += NWAVE) {
-        if (S.trials[q].op != OP_URF) continue;
-        float y = FINF;
+        for (int c = 0; c < TS; ++c) Rrow[c] = d.RwT[(size_t)(c0 + c) * d.ldm + r0 + gp.lane];
+#pragma unroll 1
+        for (int sl = gp.wave; sl < cn; sl += NWAVE) {
+          if (S.trials[cs + sl].op != OP_ULF) continue;
+          float x = FINF;
 #pragma unroll
-        for (int t = 0; t < TS; ++t) y = fminf(y, Rcol[t] - S.u.b.sA[q][t]);
-        if (y != FINF)
-          atomicMin(&d.tvec[((size_t)par * TMAX + q) * d.ldmax + c0 + gp.lane], fmap(y));
+          for (int c = 0; c < TS; ++c) x = fminf(x, Rrow[c] - S.u.b.sB[sl][c]);
+          if (x != FINF)
+            atomic_min_g(&d.tvec[((size_t)par * TMAX + cs + sl) * d.ldmax + r0 + gp.lane], fmap(x));
+        }
+      }
+      if (anyV) {
+        // lanes over columns: V''_kc = min over the tile rows of R_tc - U'_tk
+        float Rcol[TS];
+#pragma unroll
+        for (int t = 0; t < TS; ++t) Rcol[t] = d.Rw[(size_t)(r0 + t) * d.ldn + c0 + gp.lane];
+#pragma unroll 1
+        for (int sl = gp.wave; sl < cn; sl += NWAVE) {
+          if (S.trials[cs + sl].op != OP_URF) continue;
+          float y = FINF;
+#pragma unroll
+          for (int t = 0; t < TS; ++t) y = fminf(y, Rcol[t] - S.u.b.sA[sl][t]);
+          if (y != FINF)
+            atomic_min_g(&d.tvec[((size_t)par * TMAX + cs + sl) * d.ldmax + c0 + gp.lane], fmap(y));
+        }
       }
     }
   }
-}
-
-// Max over l != k of U_tl + V_lc for the tile (cooperative: wave w fills rows
-// 16w..16w+15), left in S.Ps.  With rank 1 the set is empty (-inf).
-DEV void compute_pnotk(Grp& gp, Smem& S, int r0, int c0, int k) {
-  const FitDev& d = *gp.d;
-  const int c = c0 + gp.lane;
-  float P[TS / NWAVE];
-#pragma unroll
-  for (int tt = 0; tt < TS / NWAVE; ++tt) P[tt] = -FINF;
-  const int tb = r0 + gp.wave * (TS / NWAVE);
-  for (int l = 0; l < d.r; ++l) {
-    if (l == k) continue;
-    const float v = d.V[(size_t)l * d.ldn + c];
-    const float* u = d.Uc + (size_t)l * d.ldm + tb;
-#pragma unroll
-    for (int tt = 0; tt < TS / NWAVE; ++tt) P[tt] = fmaxf(P[tt], u[tt] + v);
-  }
-#pragma unroll
-  for (int tt = 0; tt < TS / NWAVE; ++tt) S.Ps[gp.wave * (TS / NWAVE) + tt][gp.lane] = P[tt];
 }
 
 // ------------------------------------------------------------ pass 2 of a batch
-// b-norm of every trial over this workgroup's tiles.  Per lane and trial the
-// sum runs over the tile rows in four interleaved FP64 accumulators, is added
-// to a per-lane running sum in tile order, and reduced across lanes at the end.
+// b-norm of every trial over this workgroup's tiles.  Trials are grouped by
+// component k (S.byk); per tile and k the product without k is formed once.
+// Per lane and trial the sum runs over each half-tile of 32 rows in four
+// interleaved FP64 accumulators, is reduced across the lanes by a fixed
+// butterfly, and added to the workgroup's per-trial sum in tile and half
+// order.
 DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
   const FitDev& d = *gp.d;
   const int nt = S.nt;
-  for (int e = gp.tid; e < nt * TS; e += NTHR) S.u.b.wacc[e / TS][e % TS] = 0.0;
+  for (int q = gp.tid; q < nt; q += NTHR) S.wsum[q] = 0.0;
   const int ntile = d.nrt * d.nct;
   for (int tile = gp.g; tile < ntile; tile += gp.G) {
     const int rt = tile / d.nct, ct = tile % d.nct;
     const int r0 = rt * TS, c0 = ct * TS;
     __syncthreads();
-    for (int e = gp.tid; e < nt * TS; e += NTHR) {
-      int q = e / TS, x = e % TS;
-      const Trial& tr = S.trials[q];
-      S.u.b.sA[q][x] = row_side(d, tr, par, q, r0 + x, i);
-      S.u.b.sB[q][x] = col_side(d, tr, par, q, c0 + x, i);
-    }
-    float Rev[TS];
-#pragma unroll
-    for (int t = 0; t < TS; ++t) {
-      float rv = d.Rw[(size_t)(r0 + t) * d.ldn + c0 + gp.lane];
-      Rev[t] = (rv == FINF) ? FLT_MAX : rv;   // unobserved: R = P = FLT_MAX gives d = 0
-    }
+    stage_uv(gp, S, r0, c0);
+#pragma unroll 1
     for (int kq = 0; kq < S.nk; ++kq) {
       const int k = S.kdistinct[kq];
       __syncthreads();
-      compute_pnotk(gp, S, r0, c0, k);
-      __syncthreads();
-      float Pc[TS];
-#pragma unroll
-      for (int t = 0; t < TS; ++t) Pc[t] = (Rev[t] == FLT_MAX) ? FLT_MAX : S.Ps[t][gp.lane];
-      for (int q = gp.wave; q < nt; q += NWAVE) {
-        if (S.trials[q].k != k) continue;
-        const float vs = S.u.b.sB[q][gp.lane];
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll
-        for (int t = 0; t < TS; t += 4) {
-          float n0 = S.u.b.sA[q][t + 0] + vs, n1 = S.u.b.sA[q][t + 1] + vs;
-          float n2 = S.u.b.sA[q][t + 2] + vs, n3 = S.u.b.sA[q][t + 3] + vs;
-          float d0 = Rev[t + 0] - fmaxf(Pc[t + 0], n0);
-          float d1 = Rev[t + 1] - fmaxf(Pc[t + 1], n1);
-          float d2 = Rev[t + 2] - fmaxf(Pc[t + 2], n2);
-          float d3 = Rev[t + 3] - fmaxf(Pc[t + 3], n3);
-          a0 += fabs((double)d0);
-          a1 += fabs((double)d1);
-          a2 += fabs((double)d2);
-          a3 += fabs((double)d3);
+      compute_pnotk(gp, S, k);
+      const int kb = S.kstart[kq], ke = S.kstart[kq + 1];
+#pragma unroll 1
+      for (int cs = kb; cs < ke; cs += TCH) {
+        const int cn = ke - cs < TCH ? ke - cs : TCH;
+        __syncthreads();
+        for (int e = gp.tid; e < cn * TS; e += NTHR) {
+          const int sl = e / TS, x = e % TS, q = S.byk[cs + sl];
+          const Trial& tr = S.trials[q];
+          S.u.b.sA[sl][x] = row_side(d, tr, par, q, r0 + x);
+          S.u.b.sB[sl][x] = col_side(d, tr, par, q, c0 + x, i);
         }
-        S.u.b.wacc[q][gp.lane] += (a0 + a1) + (a2 + a3);
+        __syncthreads();
+        // two halves of 32 rows: R and P without k held in registers per half
+#pragma unroll 1
+        for (int h = 0; h < TS; h += TS / 2) {
+          float Rev[TS / 2], Pc[TS / 2];
+#pragma unroll
+          for (int t = 0; t < TS / 2; ++t) {
+            const float rv = d.Rw[(size_t)(r0 + h + t) * d.ldn + c0 + gp.lane];
+            // unobserved: R = P = FLT_MAX gives d = 0
+            Rev[t] = (rv == FINF) ? FLT_MAX : rv;
+            Pc[t] = __builtin_canonicalizef((rv == FINF) ? FLT_MAX : S.Ps[h + t][gp.lane]);
+          }
+#pragma unroll 1
+          for (int sl = gp.wave; sl < cn; sl += NWAVE) {
+            const float vs = S.u.b.sB[sl][gp.lane];
+            const float* sa = &S.u.b.sA[sl][h];
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+            for (int t = 0; t < TS / 2; t += 4) {
+              float n0 = sa[t + 0] + vs, n1 = sa[t + 1] + vs;
+              float n2 = sa[t + 2] + vs, n3 = sa[t + 3] + vs;
+              float d0 = Rev[t + 0] - fmaxf(Pc[t + 0], n0);
+              float d1 = Rev[t + 1] - fmaxf(Pc[t + 1], n1);
+              float d2 = Rev[t + 2] - fmaxf(Pc[t + 2], n2);
+              float d3 = Rev[t + 3] - fmaxf(Pc[t + 3], n3);
+              a0 += fabs((double)d0);
+              a1 += fabs((double)d1);
+              a2 += fabs((double)d2);
+              a3 += fabs((double)d3);
+            }
+            // lane butterfly (fixed pattern); the owning wave adds the half's sum
+            double v = (a0 + a1) + (a2 + a3);
+#pragma unroll
+            for (int sft = 32; sft >= 1; sft >>= 1) v += __shfl_xor(v, sft, 64);
+            if (gp.lane == 0) S.wsum[S.byk[cs + sl]] += v;
+          }
+        }
       }
     }
   }
   __syncthreads();
-  // lane butterfly (fixed pattern), one FP64 partial per trial and workgroup
-  for (int q = gp.wave; q < nt; q += NWAVE) {
-    double v = S.u.b.wacc[q][gp.lane];
-#pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, 64);
-    if (gp.lane == 0) d.epart[(size_t)q * d.gsize + gp.g] = v;
+  for (int q = gp.tid; q < nt; q += NTHR) st_coh(&d.epart[(size_t)q * d.gsize + gp.g], S.wsum[q]);
+}
+
+// Errors of this workgroup's slice of trials from the per-workgroup partials:
+// eight fixed chunks of consecutive workgroups, each summed in order, then a
+// fixed tree over the chunks.  The result depends only on the partials.
+DEV void reduce_errors(Grp& gp, Smem& S, int nt) {
+  const FitDev& d = *gp.d;
+  int lo, hi;
+  slice(nt, gp.g, gp.G, lo, hi);
+  const int per = (gp.G + 7) / 8;
+  // trials staged at a time: G partials each (<= 4096 doubles), 8 chunk sums
+  // each (<= TMAX doubles)
+  const int qb = 4096 / gp.G < TMAX / 8 ? 4096 / gp.G : TMAX / 8;
+  for (int q0 = lo; q0 < hi; q0 += qb) {
+    const int qn = hi - q0 < qb ? hi - q0 : qb;
+    __syncthreads();
+    for (int e = gp.tid; e < qn * gp.G; e += NTHR) {
+      const int qq = e / gp.G, g = e % gp.G;
+      S.u.r.v[e] = ld_atomic(&d.epart[(size_t)(q0 + qq) * d.gsize + g]);
+    }
+    __syncthreads();
+    for (int e = gp.tid; e < qn * 8; e += NTHR) {
+      const int qq = e >> 3, part = e & 7;
+      const int glo = part * per < gp.G ? part * per : gp.G;
+      const int ghi = glo + per < gp.G ? glo + per : gp.G;
+      double s = 0.0;
+      for (int g = glo; g < ghi; ++g) s += S.u.r.v[qq * gp.G + g];
+      S.u.r.chunk[e] = s;
+    }
+    __syncthreads();
+    for (int qq = gp.tid; qq < qn; qq += NTHR) {
+      const double* p = S.u.r.chunk + qq * 8;
+      st_coh(&d.eprime[q0 + qq], ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7])));
+    }
+  }
+}
+
+// Decision of a batch (last workgroup to arrive): the first trial whose
+// error is strictly below the current one.
+DEV void decide(Grp& gp, Smem& S, int nt, double e_cur) {
+  const FitDev& d = *gp.d;
+  if (gp.tid == 0) S.dec = 0x7fffffff;
+  __syncthreads();
+  for (int q = gp.tid; q < nt; q += NTHR)
+    if (ld_atomic(&d.eprime[q]) < e_cur) atomicMin(&S.dec, q);
+  __syncthreads();
+  if (gp.tid == 0) {
+    const int dec = S.dec == 0x7fffffff ? -1 : S.dec;
+    st_coh(&gp.ctl->decision, dec);
+    st_coh(&gp.ctl->e_new, dec >= 0 ? ld_atomic(&d.eprime[dec]) : 0.0);
+    gp.ctl->batches += 1;
   }
 }
 
 // Clear the atomic-min targets used by the previous batch (other parity).
 DEV void clear_prev(Grp& gp, Smem& S, int par_prev) {
   const FitDev& d = *gp.d;
-  for (int q = 0; q < S.prev_nt; ++q) {
-    int op = S.prev_ops[q];
-    int len = op == OP_ULF ? d.ldm : (op == OP_URF ? d.ldn : 0);
-    unsigned* v = d.tvec + ((size_t)par_prev * TMAX + q) * d.ldmax;
-    for (int x = gp.g * NTHR + gp.tid; x < len; x += gp.G * NTHR) v[x] = FMAP_INF;
-  }
+  const size_t total = (size_t)S.prev_nt * d.ldmax;
+  GA unsigned* v = d.tvec + (size_t)par_prev * TMAX * d.ldmax;
+  for (size_t e = (size_t)gp.g * NTHR + gp.tid; e < total; e += (size_t)gp.G * NTHR)
+    st_coh(&v[e], FMAP_INF);
 }
 
 // ------------------------------------------------------------ refresh
-// After an accepted update (and at initialisation): argmax counts of every
-// row and column, td_col, and the top-2 residual summaries of component k.
-DEV bool refresh(Grp& gp, Smem& S, int k, bool full) {
+// After an accepted update (acc != nullptr: component k takes the trial's
+// vectors, written here by the owner tiles) and at initialisation: argmax
+// counts of every row and column into count buffer cb, td_col partials per
+// row tile, and the top-2 residual partials of component k.  With `full` it
+// also clears the other count buffer.
+DEV void refresh_tiles(Grp& gp, Smem& S, int k, const Trial* acc, int par, int slot, int i,
+                       bool full, int cb) {
   const FitDev& d = *gp.d;
   const int ntile = d.nrt * d.nct;
-  const int rows16 = TS / NWAVE;
+  GA int* crow = d.crow + (size_t)cb * d.ldm * d.r;
+  GA int* ccol = d.ccol + (size_t)cb * d.ldn * d.r;
+  if (full) {
+    GA int* orow = d.crow + (size_t)(cb ^ 1) * d.ldm * d.r;
+    GA int* ocol = d.ccol + (size_t)(cb ^ 1) * d.ldn * d.r;
+    int lo, hi;
+    slice(d.m * d.r, gp.g, gp.G, lo, hi);
+    for (int x = lo + gp.tid; x < hi; x += NTHR) st_coh(&orow[x], 0);
+    slice(d.n * d.r, gp.g, gp.G, lo, hi);
+    for (int x = lo + gp.tid; x < hi; x += NTHR) st_coh(&ocol[x], 0);
+  }
   for (int tile = gp.g; tile < ntile; tile += gp.G) {
     const int rt = tile / d.nct, ct = tile % d.nct;
     const int r0 = rt * TS, c0 = ct * TS;
@@ -370,274 +542,490 @@ DEV bool refresh(Grp& gp, Smem& S, int k, bool full) {
         (&S.u.f.hc[0][0])[e] = 0;
         (&S.u.f.hr[0][0])[e] = 0;
       }
+    if (gp.tid < TS) {
+      const int t = r0 + gp.tid;
+      const float v = acc ? row_side(d, *acc, par, slot, t) : ld_atomic(&d.Uc[(size_t)k * d.ldm + t]);
+      S.uk[gp.tid] = v;
+      if (acc && ct == 0) st_coh(&d.Uc[(size_t)k * d.ldm + t], v);
+    } else if (gp.tid < 2 * TS) {
+      const int c = c0 + gp.tid - TS;
+      const float v = acc ? col_side(d, *acc, par, slot, c, i) : ld_atomic(&d.V[(size_t)k * d.ldn + c]);
+      S.vk[gp.tid - TS] = v;
+      if (acc && rt == 0) st_coh(&d.V[(size_t)k * d.ldn + c], v);
+    }
+    if (full) stage_uv(gp, S, r0, c0);
     __syncthreads();
     const int c = c0 + gp.lane;
-    const int tb = r0 + gp.wave * rows16;
-    float R[TS / NWAVE];
+    const int tl0 = gp.wave * RPW;
+    const int tb = r0 + tl0;
+    float R[RPW];
 #pragma unroll
-    for (int tt = 0; tt < rows16; ++tt) R[tt] = d.Rw[(size_t)(tb + tt) * d.ldn + c];
+    for (int tt = 0; tt < RPW; ++tt) R[tt] = d.Rw[(size_t)(tb + tt) * d.ldn + c];
     if (full) {
-      float P[TS / NWAVE];
-      int A[TS / NWAVE];
-      {
-        const float v = d.V[c];
+      float P[RPW];
+      int A[RPW];
 #pragma unroll
-        for (int tt = 0; tt < rows16; ++tt) { P[tt] = d.Uc[tb + tt] + v; A[tt] = 0; }
-      }
-      for (int l = 1; l < d.r; ++l) {
-        const float v = d.V[(size_t)l * d.ldn + c];
-        const float* u = d.Uc + (size_t)l * d.ldm + tb;
+      for (int tt = 0; tt < RPW; ++tt) { P[tt] = -FINF; A[tt] = 0; }
+      for (int l = 0; l < d.r; ++l) {
+        if (l == k) {
+          const float v = S.vk[gp.lane];
 #pragma unroll
-        for (int tt = 0; tt < rows16; ++tt) {
-          float x = u[tt] + v;
-          if (x > P[tt]) { P[tt] = x; A[tt] = l; }
+          for (int tt = 0; tt < RPW; ++tt) {
+            float x = S.uk[tl0 + tt] + v;
+            if (l == 0 || x > P[tt]) { P[tt] = x; A[tt] = l; }
+          }
+        } else {
+          const float v = S.Vt[l][gp.lane];
+#pragma unroll
+          for (int tt = 0; tt < RPW; ++tt) {
+            float x = S.Ut[l][tl0 + tt] + v;
+            if (l == 0 || x > P[tt]) { P[tt] = x; A[tt] = l; }
+          }
         }
       }
       double tdl = 0.0;
 #pragma unroll
-      for (int tt = 0; tt < rows16; ++tt) {
+      for (int tt = 0; tt < RPW; ++tt) {
         const int t = tb + tt;
         const bool obs = R[tt] != FINF;
         if (obs) tdl += fabs((double)(R[tt] - P[tt]));
         const bool cnt = d.count_scope ? (t < d.m && c < d.n) : obs;
         if (cnt) {
           atomicAdd(&S.u.f.hc[gp.lane][A[tt]], 1);
-          atomicAdd(&S.u.f.hr[gp.wave * rows16 + tt][A[tt]], 1);
+          atomicAdd(&S.u.f.hr[tl0 + tt][A[tt]], 1);
         }
       }
       S.u.f.tdw[gp.wave][gp.lane] = tdl;
     }
     {
       Top2 cs = top2_id();
-      const float* u = d.Uc + (size_t)k * d.ldm + tb;
 #pragma unroll
-      for (int tt = 0; tt < rows16; ++tt) cs = top2_add(cs, R[tt] - u[tt], tb + tt);
+      for (int tt = 0; tt < RPW; ++tt) cs = top2_add(cs, R[tt] - S.uk[tl0 + tt], tb + tt);
       S.u.f.csw[gp.wave][gp.lane] = cs;
     }
     {
-      // lanes over rows: row summary over this wave's 16 columns
+      // lanes over rows: row summary over this wave's columns
       const int t = r0 + gp.lane;
-      const int cb = c0 + gp.wave * rows16;
-      const float* vk = d.V + (size_t)k * d.ldn + cb;
+      const int cl0 = gp.wave * RPW;
       Top2 rs = top2_id();
 #pragma unroll
-      for (int cc = 0; cc < rows16; ++cc)
-        rs = top2_add(rs, d.RwT[(size_t)(cb + cc) * d.ldm + t] - vk[cc], cb + cc);
+      for (int cc = 0; cc < RPW; ++cc)
+        rs = top2_add(rs, d.RwT[(size_t)(c0 + cl0 + cc) * d.ldm + t] - S.vk[cl0 + cc],
+                      c0 + cl0 + cc);
       S.u.f.rsw[gp.wave][gp.lane] = rs;
     }
     __syncthreads();
     if (gp.wave == 0) {
-      Top2 cs = top2_comb(top2_comb(top2_comb(S.u.f.csw[0][gp.lane], S.u.f.csw[1][gp.lane]),
-                                    S.u.f.csw[2][gp.lane]), S.u.f.csw[3][gp.lane]);
-      d.colpart[(size_t)rt * d.ldn + c] = cs;
-      if (full)
-        d.tdpart[(size_t)rt * d.ldn + c] =
-            ((S.u.f.tdw[0][gp.lane] + S.u.f.tdw[1][gp.lane]) + S.u.f.tdw[2][gp.lane]) + S.u.f.tdw[3][gp.lane];
+      Top2 cs = S.u.f.csw[0][gp.lane];
+      for (int w = 1; w < NWAVE; ++w) cs = top2_comb(cs, S.u.f.csw[w][gp.lane]);
+      st_top2(&d.colpart[(size_t)rt * d.ldn + c], cs);
+      if (full) {
+        double s = S.u.f.tdw[0][gp.lane];
+        for (int w = 1; w < NWAVE; ++w) s += S.u.f.tdw[w][gp.lane];
+        st_coh(&d.tdpart[(size_t)rt * d.ldn + c], s);
+      }
     } else if (gp.wave == 1) {
-      Top2 rs = top2_comb(top2_comb(top2_comb(S.u.f.rsw[0][gp.lane], S.u.f.rsw[1][gp.lane]),
-                                    S.u.f.rsw[2][gp.lane]), S.u.f.rsw[3][gp.lane]);
-      d.rowpart[(size_t)ct * d.ldm + r0 + gp.lane] = rs;
+      Top2 rs = S.u.f.rsw[0][gp.lane];
+      for (int w = 1; w < NWAVE; ++w) rs = top2_comb(rs, S.u.f.rsw[w][gp.lane]);
+      st_top2(&d.rowpart[(size_t)ct * d.ldm + r0 + gp.lane], rs);
     }
     if (full) {
       for (int e = gp.tid; e < TS * d.r; e += NTHR) {
         int x = e / d.r, l = e % d.r;
         int hcv = S.u.f.hc[x][l], hrv = S.u.f.hr[x][l];
-        if (hcv && c0 + x < d.n) atomicAdd(&d.ccol[(size_t)(c0 + x) * d.r + l], hcv);
-        if (hrv && r0 + x < d.m) atomicAdd(&d.crow[(size_t)(r0 + x) * d.r + l], hrv);
+        if (hcv && c0 + x < d.n) atomic_add_g(&ccol[(size_t)(c0 + x) * d.r + l], hcv);
+        if (hrv && r0 + x < d.m) atomic_add_g(&crow[(size_t)(r0 + x) * d.r + l], hrv);
       }
     }
   }
-  if (!group_sync(gp, S)) return false;
-  // combine partials in fixed tile order
+  if (acc && gp.g == 0 && gp.tid == 0) st_coh(&d.closed[k], 1);
+}
+
+// Residual summaries of component k from the per-tile partials (fixed tile
+// order), for this workgroup's slice of columns and rows; with with_td also
+// td_col.
+DEV void combine_summaries(Grp& gp, Smem& S, int k, bool with_td) {
+  const FitDev& d = *gp.d;
+  int lo, hi;
+  // columns: chunks of columns whose (column, row tile) partials fit the buffer
+  slice(d.n, gp.g, gp.G, lo, hi);
   {
-    int lo, hi;
-    slice(d.n, gp.g, gp.G, lo, hi);
-    for (int c = lo + gp.tid; c < hi; c += NTHR) {
-      Top2 cs = top2_id();
+    const int per_chunk = 2048 / d.nrt > 0 ? 2048 / d.nrt : 1;
+    for (int c0 = lo; c0 < hi; c0 += per_chunk) {
+      const int cn = hi - c0 < per_chunk ? hi - c0 : per_chunk;
+      __syncthreads();
+      for (int e = gp.tid; e < cn * d.nrt; e += NTHR) {
+        const int cc = e / d.nrt, rt = e % d.nrt;
+        S.u.c.part[e] = ld_top2(&d.colpart[(size_t)rt * d.ldn + c0 + cc]);
+        if (with_td) S.u.c.dpart[e] = ld_atomic(&d.tdpart[(size_t)rt * d.ldn + c0 + cc]);
+      }
+      __syncthreads();
+      for (int cc = gp.tid; cc < cn; cc += NTHR) {
+        Top2 cs = top2_id();
+        double sum = 0.0;
+        for (int rt = 0; rt < d.nrt; ++rt) {
+          cs = top2_comb(cs, S.u.c.part[cc * d.nrt + rt]);
+          if (with_td) sum += S.u.c.dpart[cc * d.nrt + rt];
+        }
+        st_top2(&d.colst[(size_t)k * d.ldn + c0 + cc], cs);
+        if (with_td) st_coh(&d.td[c0 + cc], sum);
+      }
+    }
+  }
+  slice(d.m, gp.g, gp.G, lo, hi);
+  {
+    const int per_chunk = 2048 / d.nct > 0 ? 2048 / d.nct : 1;
+    for (int t0 = lo; t0 < hi; t0 += per_chunk) {
+      const int tn = hi - t0 < per_chunk ? hi - t0 : per_chunk;
+      __syncthreads();
+      for (int e = gp.tid; e < tn * d.nct; e += NTHR) {
+        const int tt = e / d.nct, ct = e % d.nct;
+        S.u.c.part[e] = ld_top2(&d.rowpart[(size_t)ct * d.ldm + t0 + tt]);
+      }
+      __syncthreads();
+      for (int tt = gp.tid; tt < tn; tt += NTHR) {
+        Top2 rs = top2_id();
+        for (int ct = 0; ct < d.nct; ++ct) rs = top2_comb(rs, S.u.c.part[tt * d.nct + ct]);
+        st_top2(&d.rowst[(size_t)k * d.ldm + t0 + tt], rs);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Column order by (td_col descending, index ascending) in one workgroup:
+// td_col from the row-tile partials (fixed order), bitonic sort in LDS.
+DEV void sort_in_workgroup(Grp& gp, Smem& S) {
+  const FitDev& d = *gp.d;
+  int N = 1;
+  while (N < d.n) N <<= 1;
+  for (int x = gp.tid; x < N; x += NTHR) {
+    if (x < d.n) {
       double s = 0.0;
-      for (int rt = 0; rt < d.nrt; ++rt) {
-        cs = top2_comb(cs, d.colpart[(size_t)rt * d.ldn + c]);
-        if (full) s += d.tdpart[(size_t)rt * d.ldn + c];
+      for (int rt0 = 0; rt0 < d.nrt; rt0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          v[u] = rt0 + u < d.nrt ? ld_atomic(&d.tdpart[(size_t)(rt0 + u) * d.ldn + x]) : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
       }
-      d.colst[(size_t)k * d.ldn + c] = cs;
-      if (full) d.td[c] = s;
-    }
-    slice(d.m, gp.g, gp.G, lo, hi);
-    for (int t = lo + gp.tid; t < hi; t += NTHR) {
-      Top2 rs = top2_id();
-      for (int ct = 0; ct < d.nct; ++ct) rs = top2_comb(rs, d.rowpart[(size_t)ct * d.ldm + t]);
-      d.rowst[(size_t)k * d.ldm + t] = rs;
+      S.u.s.key[x] = s;
+      S.u.s.idx[x] = x;
+      st_coh(&d.td[x], s);
+    } else {
+      S.u.s.key[x] = -1.0;
+      S.u.s.idx[x] = 0x7fffffff;
     }
   }
-  if (!full) return group_sync(gp, S);
+  __syncthreads();
+  for (int kk = 2; kk <= N; kk <<= 1) {
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      for (int x = gp.tid; x < N; x += NTHR) {
+        const int y = x ^ jj;
+        if (y > x) {
+          const double kx = S.u.s.key[x], ky = S.u.s.key[y];
+          const int ix = S.u.s.idx[x], iy = S.u.s.idx[y];
+          // "before": larger td first, then lower index
+          const bool y_before_x = ky > kx || (ky == kx && iy < ix);
+          const bool x_before_y = kx > ky || (kx == ky && ix < iy);
+          const bool up = (x & kk) == 0;
+          if (up ? y_before_x : x_before_y) {
+            S.u.s.key[x] = ky; S.u.s.key[y] = kx;
+            S.u.s.idx[x] = iy; S.u.s.idx[y] = ix;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int x = gp.tid; x < d.n; x += NTHR) st_coh(&d.order[x], S.u.s.idx[x]);
+}
+
+// Column order for wide matrices: every workgroup ranks its slice of columns
+// against all of td_col, staged through LDS in chunks.
+DEV void sort_by_rank(Grp& gp, Smem& S) {
+  const FitDev& d = *gp.d;
+  int lo, hi;
+  slice(d.n, gp.g, gp.G, lo, hi);
+  for (int base = lo; base < hi; base += NTHR) {
+    const int c = base + gp.tid;
+    const double key = c < hi ? ld_atomic(&d.td[c]) : 0.0;
+    int rank = 0;
+    for (int x0 = 0; x0 < d.n; x0 += SORT_MAX) {
+      const int len = d.n - x0 < SORT_MAX ? d.n - x0 : SORT_MAX;
+      __syncthreads();
+      for (int x = gp.tid; x < len; x += NTHR) S.u.s.key[x] = ld_atomic(&d.td[x0 + x]);
+      __syncthreads();
+      if (c < hi)
+        for (int x = 0; x < len; ++x) {
+          const double o = S.u.s.key[x];
+          rank += (o > key || (o == key && x0 + x < c)) ? 1 : 0;
+        }
+    }
+    if (c < hi) st_coh(&d.order[rank], c);
+  }
+}
+
+// Whole refresh: tile pass, barrier, summaries (and the sort in workgroup 0
+// for matrices up to SORT_MAX columns), barrier.
+DEV bool refresh(Grp& gp, Smem& S, int k, const Trial* acc, int par, int slot, int i, bool full,
+                 int cb) {
+  const FitDev& d = *gp.d;
+  refresh_tiles(gp, S, k, acc, par, slot, i, full, cb);
   if (!group_sync(gp, S)) return false;
-  // order of the columns by (td_col descending, index ascending), by ranking
-  {
-    int lo, hi;
-    slice(d.n, gp.g, gp.G, lo, hi);
-    for (int c0 = lo; c0 < hi; c0 += NTHR) {
-      const int c = c0 + gp.tid;
-      const double key = c < hi ? d.td[c] : 0.0;
-      int rank = 0;
-      for (int x = 0; x < d.n; ++x) {
-        const double o = d.td[x];
-        rank += (o > key || (o == key && x < c)) ? 1 : 0;
-      }
-      if (c < hi) d.order[rank] = c;
-    }
+  const bool small = d.n <= SORT_MAX;
+  combine_summaries(gp, S, k, full && !small);
+  if (full && small && gp.g == 0) {
+    __syncthreads();
+    sort_in_workgroup(gp, S);
   }
-  return group_sync(gp, S);
+  if (!group_sync(gp, S)) return false;
+  if (full && !small) {
+    sort_by_rank(gp, S);
+    if (!group_sync(gp, S)) return false;
+  }
+  return true;
 }
 
 // ------------------------------------------------------------ row visit pieces
-// Candidate list of row i (workgroup 0 of the group): observed columns in
-// the current order.
-DEV void build_candidates(Grp& gp, Smem& S, int i) {
+// Start a row visit: argmax counts, U and closed flags of row i into LDS,
+// candidate queue empty.
+DEV void row_begin(Grp& gp, Smem& S, int i, int cb) {
   const FitDev& d = *gp.d;
-  const float* Ri = d.Rw + (size_t)i * d.ldn;
-  const int per = (d.n + NTHR - 1) / NTHR;
-  const int lo = gp.tid * per;
-  int hi = lo + per;
-  if (hi > d.n) hi = d.n;
-  int cnt = 0;
-  for (int q = lo; q < hi; ++q) cnt += Ri[d.order[q]] != FINF;
-  S.scan[gp.tid] = cnt;
-  __syncthreads();
-  if (gp.tid == 0) {
-    int acc = 0;
-    for (int x = 0; x < NTHR; ++x) { int v = S.scan[x]; S.scan[x] = acc; acc += v; }
-    S.scan[NTHR] = acc;
-    gp.ctl->ncand = acc;
+  if (gp.tid < d.r) {
+    S.crow_i[gp.tid] = ld_atomic(&d.crow[((size_t)cb * d.ldm + i) * d.r + gp.tid]);
+    S.urow_i[gp.tid] = ld_atomic(&d.Uc[(size_t)gp.tid * d.ldm + i]);
+    S.closed_s[gp.tid] = ld_atomic(&d.closed[gp.tid]);
   }
+  if (gp.tid == 0) { S.cq_head = 0; S.cq_n = 0; S.ord_pos = 0; S.cur_op = 0; }
   __syncthreads();
-  int pos = S.scan[gp.tid];
-  for (int q = lo; q < hi; ++q) {
-    int c = d.order[q];
-    if (Ri[c] != FINF) d.cand[pos++] = c;
+}
+
+// Keep at least CW candidates of row i queued (observed columns in the
+// current order), unless the order is exhausted.  Every workgroup of the
+// group builds the same queue.
+DEV void refill_candidates(Grp& gp, Smem& S, int i) {
+  const FitDev& d = *gp.d;
+  const GA float* Ri = d.Rw + (size_t)i * d.ldn;
+  while (S.cq_n - S.cq_head < CW && S.ord_pos < d.n) {
+    // move the unconsumed tail to the front
+    const int keep = S.cq_n - S.cq_head;
+    int v = 0;
+    if (gp.tid < keep) v = S.cq[S.cq_head + gp.tid];
+    __syncthreads();
+    if (gp.tid < keep) S.cq[gp.tid] = v;
+    const int pos = S.ord_pos + gp.tid;
+    int j = -1;
+    if (pos < d.n) {
+      j = ld_atomic(&d.order[pos]);
+      if (Ri[j] == FINF) j = -1;
+    }
+    const unsigned long long m = __ballot(j >= 0);
+    const int below = __popcll(m & ((1ull << gp.lane) - 1ull));
+    if (gp.lane == 0) S.wcount[gp.wave] = __popcll(m);
+    __syncthreads();
+    int off = keep;
+    for (int w = 0; w < gp.wave; ++w) off += S.wcount[w];
+    if (j >= 0) S.cq[off + below] = j;
+    __syncthreads();
+    if (gp.tid == 0) {
+      int tot = keep;
+      for (int w = 0; w < NWAVE; ++w) tot += S.wcount[w];
+      S.cq_head = 0;
+      S.cq_n = tot;
+      S.ord_pos += NTHR;
+    }
+    __syncthreads();
   }
 }
 
 // Next batch of up to T trials from the cursor, in the method's order:
 // candidate by candidate, F-ULF then F-URF, skipping no-op trials.  Every
 // workgroup of the group computes the same list.
-DEV void build_batch(Grp& gp, Smem& S, int i, int T, int ncand) {
+DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb) {
   const FitDev& d = *gp.d;
+  const GA int* ccol = d.ccol + (size_t)cb * d.ldn * d.r;
   if (gp.tid == 0) { S.nt = 0; S.batch_noops = 0; }
   __syncthreads();
   while (true) {
-    const int qbase = S.cur_q;
-    if (S.nt >= T || qbase >= ncand) break;
-    if (gp.tid < 64) {
-      const int p = gp.tid, q = qbase + p;
-      if (q < ncand) {
-        const int j = d.cand[q];
-        int best = -1, k = 0;
-        for (int l = 0; l < d.r; ++l) {
-          int v = ld_atomic(&d.crow[(size_t)i * d.r + l]) + ld_atomic(&d.ccol[(size_t)j * d.r + l]);
-          if (v > best) { best = v; k = l; }
+    refill_candidates(gp, S, i);
+    const int avail0 = S.cq_n - S.cq_head;
+    if (S.nt >= T || avail0 == 0) break;
+    const int avail = avail0 < CW ? avail0 : CW;
+    // TD_A index of each candidate in the window: four threads per
+    // candidate, each over components l = sub, sub + 4, ... (their counts and
+    // V_lj loaded in one round)
+    {
+      const int p = gp.tid >> 2, sub = gp.tid & 3;
+      float vv[RMAX / 4];
+      if (p < avail) {
+        const int j = S.cq[S.cq_head + p];
+        int cnt[RMAX / 4];
+#pragma unroll
+        for (int u = 0; u < RMAX / 4; ++u) {
+          const int l = sub + 4 * u;
+          cnt[u] = l < d.r ? ld_atomic(&ccol[(size_t)j * d.r + l]) : 0;
+          vv[u] = l < d.r ? ld_atomic(&d.V[(size_t)l * d.ldn + j]) : 0.0f;
         }
-        const float Rij = d.Rw[(size_t)i * d.ldn + j];
-        const float Uik = d.Uc[(size_t)k * d.ldm + i];
-        const float Vkj = d.V[(size_t)k * d.ldn + j];
-        const float vu = Rij - Vkj, vv = Rij - Uik;
-        const bool cl = d.noop_rule && d.closed[k];
-        S.cj[p] = j; S.ck[p] = k; S.cvu[p] = vu; S.cvv[p] = vv;
-        S.cnu[p] = cl && vu == Uik;
-        S.cnv[p] = cl && vv == Vkj;
+        int best = -1, kb = 0;
+#pragma unroll
+        for (int u = 0; u < RMAX / 4; ++u) {
+          const int l = sub + 4 * u;
+          if (l < d.r) {
+            const int v = S.crow_i[l] + cnt[u];
+            if (v > best) { best = v; kb = l; }
+          }
+        }
+        S.kval[p][sub] = best;
+        S.kbest[p][sub] = kb;
       }
+      __syncthreads();
+      if (gp.tid < avail) {
+        const int q = gp.tid;
+        int best = -1, k = 0;
+        for (int u = 0; u < 4; ++u) {
+          const int v = S.kval[q][u], kb = S.kbest[q][u];
+          if (v > best || (v == best && kb < k)) { best = v; k = kb; }
+        }
+        S.ck[q] = k;
+      }
+      __syncthreads();
+      if (p < avail && (S.ck[p] & 3) == sub) {
+        const int want = S.ck[p] >> 2;
+        float v = 0.0f;
+#pragma unroll
+        for (int u = 0; u < RMAX / 4; ++u) v = u == want ? vv[u] : v;
+        S.vsel[p] = v;
+      }
+    }
+    __syncthreads();
+    if (gp.tid < avail) {
+      const int p = gp.tid;
+      const int j = S.cq[S.cq_head + p];
+      const int k = S.ck[p];
+      const float Rij = d.Rw[(size_t)i * d.ldn + j];
+      const float Uik = S.urow_i[k];
+      const float Vkj = S.vsel[p];
+      const float vu = Rij - Vkj, vv2 = Rij - Uik;
+      const bool cl = d.noop_rule && S.closed_s[k];
+      S.cj[p] = j; S.cvu[p] = vu; S.cvv[p] = vv2;
+      S.cnu[p] = cl && vu == Uik;
+      S.cnv[p] = cl && vv2 == Vkj;
+    }
+    __syncthreads();
+    // Walk the (candidate, operation) pairs of the window in order: pair
+    // x = 2p + op, starting at the cursor's operation.  A pair is consumed
+    // while fewer than T - nt trials precede it; consumed no-op pairs count as
+    // skipped trials.  Prefix counts by ballot.
+    const int nt0 = S.nt, room = T - nt0, nn0 = S.batch_noops, op0 = S.cur_op;
+    const int x = gp.tid;
+    const bool valid = x < 2 * avail && x >= op0;
+    bool noop = false;
+    if (valid) noop = (x & 1) ? S.cnv[x >> 1] : S.cnu[x >> 1];
+    const bool kept = valid && !noop;
+    const unsigned long long mk = __ballot(kept);
+    const unsigned long long mn = __ballot(valid && noop);
+    const unsigned long long below_mask = (1ull << gp.lane) - 1ull;
+    if (gp.lane == 0) { S.wcount[gp.wave] = __popcll(mk); S.wnoop[gp.wave] = __popcll(mn); }
+    __syncthreads();
+    int kept_before = __popcll(mk & below_mask), noop_before = __popcll(mn & below_mask);
+    for (int w = 0; w < gp.wave; ++w) { kept_before += S.wcount[w]; noop_before += S.wnoop[w]; }
+    const bool consumed = valid && kept_before < room;
+    if (consumed && kept) {
+      const int slot = nt0 + kept_before;
+      Trial tr;
+      tr.j = S.cj[x >> 1]; tr.k = S.ck[x >> 1]; tr.op = x & 1;
+      tr.val = (x & 1) ? S.cvv[x >> 1] : S.cvu[x >> 1];
+      S.trials[slot] = tr;
+      S.noops_before[slot] = nn0 + noop_before;
+    }
+    // the consumed pairs are a prefix of the valid ones: find the last one and
+    // count the consumed no-op pairs
+    const unsigned long long mc = __ballot(consumed);
+    const unsigned long long mcn = __ballot(consumed && noop);
+    if (gp.lane == 0) {
+      S.wlast[gp.wave] = mc ? gp.wave * 64 + 63 - __clzll(mc) : -1;
+      S.wcn[gp.wave] = __popcll(mcn);
     }
     __syncthreads();
     if (gp.tid == 0) {
-      int p = 0, op = S.cur_op;
-      int nt = S.nt, nn = S.batch_noops;
-      while (nt < T && qbase + p < ncand && p < 64) {
-        const bool noop = op == 0 ? S.cnu[p] : S.cnv[p];
-        if (noop) {
-          ++nn;
-        } else {
-          Trial tr;
-          tr.j = S.cj[p]; tr.k = S.ck[p]; tr.op = op; tr.val = op == 0 ? S.cvu[p] : S.cvv[p];
-          S.trials[nt] = tr;
-          S.noops_before[nt] = nn;
-          ++nt;
-        }
-        if (op == 0) op = 1; else { op = 0; ++p; }
+      int last = -1, kt = 0, nn = 0;
+      for (int w = 0; w < NWAVE; ++w) {
+        last = S.wlast[w] > last ? S.wlast[w] : last;
+        kt += S.wcount[w];
+        nn += S.wcn[w];
       }
-      S.nt = nt; S.batch_noops = nn;
-      S.cur_q = qbase + p; S.cur_op = op;
+      S.nt = nt0 + (kt < room ? kt : room);
+      S.batch_noops = nn0 + nn;
+      const int nxt = last + 1;       // next pair after the last consumed one
+      S.cq_head += nxt >> 1;
+      S.cur_op = nxt & 1;
     }
     __syncthreads();
   }
+  // group the trials by component (first-appearance order, stable within a
+  // group) for the error pass
   if (gp.tid == 0) {
-    S.exhausted = S.cur_q >= ncand;
     int nk = 0;
     for (int q = 0; q < S.nt; ++q) {
-      int k = S.trials[q].k, seen = 0;
-      for (int x = 0; x < nk; ++x) seen |= S.kdistinct[x] == k;
+      const int k = S.trials[q].k;
+      int seen = 0;
+      for (int y = 0; y < nk; ++y) seen |= S.kdistinct[y] == k;
       if (!seen) S.kdistinct[nk++] = k;
+      if (nk == RMAX) break;
     }
     S.nk = nk;
+    S.exhausted = (S.cq_n - S.cq_head) == 0 && S.ord_pos >= d.n;
+  }
+  __syncthreads();
+  {
+    int base = 0;
+    for (int kq = 0; kq < S.nk; ++kq) {
+      const int k = S.kdistinct[kq];
+      if (gp.tid == 0) S.kstart[kq] = base;
+      const int q = gp.tid;
+      const bool match = q < S.nt && S.trials[q].k == k;
+      const unsigned long long m = __ballot(match);
+      if (gp.lane == 0) S.wcount[gp.wave] = __popcll(m);
+      __syncthreads();
+      int pos = base + __popcll(m & ((1ull << gp.lane) - 1ull));
+      int tot = 0;
+      for (int w = 0; w < NWAVE; ++w) {
+        if (w < gp.wave) pos += S.wcount[w];
+        tot += S.wcount[w];
+      }
+      if (match) S.byk[pos] = q;
+      base += tot;
+      __syncthreads();
+    }
+    if (gp.tid == 0) S.kstart[S.nk] = base;
   }
   __syncthreads();
 }
 
-// Apply the accepted trial: U_.k and V_k. take the trial's vectors.  Also
-// clears the argmax counts for the refresh that follows.
-DEV void apply_trial(Grp& gp, Smem& S, int i, int par, int slot) {
-  const FitDev& d = *gp.d;
-  const Trial tr = S.trials[slot];
-  int lo, hi;
-  slice(d.ldm, gp.g, gp.G, lo, hi);
-  for (int t = lo + gp.tid; t < hi; t += NTHR) {
-    float v = row_side(d, tr, par, slot, t, i);
-    d.Uc[(size_t)tr.k * d.ldm + t] = v;
-  }
-  slice(d.ldn, gp.g, gp.G, lo, hi);
-  for (int c = lo + gp.tid; c < hi; c += NTHR) {
-    float v = col_side(d, tr, par, slot, c, i);
-    d.V[(size_t)tr.k * d.ldn + c] = v;
-  }
-  slice(d.m * d.r, gp.g, gp.G, lo, hi);
-  for (int x = lo + gp.tid; x < hi; x += NTHR) d.crow[x] = 0;
-  slice(d.n * d.r, gp.g, gp.G, lo, hi);
-  for (int x = lo + gp.tid; x < hi; x += NTHR) d.ccol[x] = 0;
-  if (gp.g == 0 && gp.tid == 0) d.closed[tr.k] = 1;
-}
-
-DEV void zero_counts(Grp& gp) {
-  const FitDev& d = *gp.d;
-  int lo, hi;
-  slice(d.m * d.r, gp.g, gp.G, lo, hi);
-  for (int x = lo + gp.tid; x < hi; x += NTHR) d.crow[x] = 0;
-  slice(d.n * d.r, gp.g, gp.G, lo, hi);
-  for (int x = lo + gp.tid; x < hi; x += NTHR) d.ccol[x] = 0;
-}
-
-// Evaluate the batch in S.trials: residual pass, error pass, and the
-// decision (first trial with e' < e) made by the last workgroup to arrive.
-DEV bool run_batch(Grp& gp, Smem& S, int i, int par, double e_cur) {
-  const FitDev& d = *gp.d;
+// Evaluate the batch in S.trials: residual pass, error pass, per-trial
+// reduction, and the decision (first trial with e' < e) made by the last
+// workgroup to arrive.
+template <typename Lap>
+DEV bool run_batch(Grp& gp, Smem& S, int i, int par, double e_cur, Lap& lap) {
   batch_residual_pass(gp, S, i, par);
   if (!group_sync(gp, S)) return false;
+  lap(2);
   batch_eval_pass(gp, S, i, par);
   clear_prev(gp, S, par ^ 1);
-  return group_sync_last(gp, S, [&] {
-    if (gp.tid < 64) {
-      const int q = gp.tid;
-      double s = 0.0;
-      if (q < S.nt)
-        for (int g = 0; g < gp.G; ++g) s += d.epart[(size_t)q * d.gsize + g];
-      S.u.b.wacc[0][q] = s;   // reuse as scratch
-    }
-    __syncthreads();
-    if (gp.tid == 0) {
-      int dec = -1;
-      for (int q = 0; q < S.nt; ++q)
-        if (S.u.b.wacc[0][q] < e_cur) { dec = q; break; }
-      gp.ctl->decision = dec;
-      gp.ctl->e_new = dec >= 0 ? S.u.b.wacc[0][dec] : (S.nt ? S.u.b.wacc[0][0] : 0.0);
-    }
-  });
+  if (!group_sync(gp, S)) return false;
+  reduce_errors(gp, S, S.nt);
+  const bool ok = group_sync_last(gp, S, [&] { decide(gp, S, S.nt, e_cur); });
+  lap(3);
+  return ok;
+}
+
+DEV void clear_trial_vectors(Grp& gp) {
+  const FitDev& d = *gp.d;
+  const size_t total = (size_t)2 * TMAX * d.ldmax;
+  for (size_t x = (size_t)gp.g * NTHR + gp.tid; x < total; x += (size_t)gp.G * NTHR)
+    st_coh(&d.tvec[x], FMAP_INF);
 }
 
 // Initial state: residual summaries of every component, counts, td_col,
@@ -645,33 +1033,37 @@ DEV bool run_batch(Grp& gp, Smem& S, int i, int par, double e_cur) {
 // every trial (a null trial).
 DEV bool fit_init(Grp& gp, Smem& S) {
   const FitDev& d = *gp.d;
-  // clear both parities of the trial vectors
+  clear_trial_vectors(gp);
   {
-    size_t total = (size_t)2 * TMAX * d.ldmax;
-    for (size_t x = (size_t)gp.g * NTHR + gp.tid; x < total; x += (size_t)gp.G * NTHR)
-      d.tvec[x] = FMAP_INF;
+    int lo, hi;
+    slice(2 * d.ldm * d.r, gp.g, gp.G, lo, hi);
+    for (int x = lo + gp.tid; x < hi; x += NTHR) st_coh(&d.crow[x], 0);
+    slice(2 * d.ldn * d.r, gp.g, gp.G, lo, hi);
+    for (int x = lo + gp.tid; x < hi; x += NTHR) st_coh(&d.ccol[x], 0);
   }
-  zero_counts(gp);
   if (!group_sync(gp, S)) return false;
   for (int k = 0; k < d.r; ++k)
-    if (!refresh(gp, S, k, k == d.r - 1)) return false;
+    if (!refresh(gp, S, k, nullptr, 0, 0, 0, k == d.r - 1, 0)) return false;
   if (gp.tid == 0) {
     Trial tr; tr.j = 0; tr.k = 0; tr.op = OP_NULL; tr.val = 0.0f;
-    S.trials[0] = tr; S.nt = 1; S.nk = 1; S.kdistinct[0] = 0; S.prev_nt = 0;
+    S.trials[0] = tr; S.nt = 1; S.nk = 1; S.kdistinct[0] = 0; S.kstart[0] = 0; S.kstart[1] = 1;
+    S.byk[0] = 0; S.prev_nt = 0;
   }
   __syncthreads();
   batch_eval_pass(gp, S, 0, 0);
+  if (!group_sync(gp, S)) return false;
+  reduce_errors(gp, S, 1);
   if (!group_sync_last(gp, S, [&] {
         if (gp.tid == 0) {
-          double s = 0.0;
-          for (int g = 0; g < gp.G; ++g) s += d.epart[g];
-          gp.ctl->e = s;
-          d.traj[0] = s;
-          gp.ctl->phase = d.iters > 0 ? 1 : 2;
-          gp.ctl->it = 1;
-          gp.ctl->row = 0;
-          gp.ctl->acc_in_pass = 0;
-          gp.ctl->cells = 0;
+          const double s = ld_atomic(&d.eprime[0]);
+          st_coh(&gp.ctl->e, s);
+          st_coh(&d.traj[0], s);
+          st_coh(&gp.ctl->phase, d.iters > 0 ? 1 : 2);
+          st_coh(&gp.ctl->it, 1);
+          st_coh(&gp.ctl->row, 0);
+          st_coh(&gp.ctl->acc_in_pass, 0);
+          st_coh(&gp.ctl->cells, 0ll);
+          st_coh(&gp.ctl->cbuf, 0);
         }
       }))
     return false;
@@ -682,55 +1074,58 @@ DEV bool fit_init(Grp& gp, Smem& S) {
 // limit).  All workgroups of the group execute the same control flow.
 DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
   const FitDev& d = *gp.d;
-  FitCtl* ctl = gp.ctl;
+  GA FitCtl* ctl = gp.ctl;
   if (gp.tid == 0) { S.prev_nt = 0; S.status = 0; }
   __syncthreads();
   if (ld_atomic(&ctl->phase) == 0) {
     if (!fit_init(gp, S)) return;
   } else {
     // a resumed launch: the trial vectors of both parities must start clean
-    size_t total = (size_t)2 * TMAX * d.ldmax;
-    for (size_t x = (size_t)gp.g * NTHR + gp.tid; x < total; x += (size_t)gp.G * NTHR)
-      d.tvec[x] = FMAP_INF;
+    clear_trial_vectors(gp);
     if (!group_sync(gp, S)) return;
   }
   double e_cur = ld_atomic(&ctl->e);
   int it = ld_atomic(&ctl->it), row = ld_atomic(&ctl->row);
   int acc_pass = ld_atomic(&ctl->acc_in_pass);
   int phase = ld_atomic(&ctl->phase);
+  int cb = ld_atomic(&ctl->cbuf);
   int rows_done = 0;
   int par = 0;
+  // leader-side phase timers: 0 row start, 1 batch list, 2 residual pass,
+  // 3 error pass and decision, 4 refresh, 5 bookkeeping
+  long long ticks[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned long long tmark = __builtin_amdgcn_s_memrealtime();
+  auto lap = [&](int which) {
+    unsigned long long now = __builtin_amdgcn_s_memrealtime();
+    ticks[which] += (long long)(now - tmark);
+    tmark = now;
+  };
   while (phase == 1) {
     if (max_rows > 0 && rows_done >= max_rows) break;
     const int i = row;
-    if (gp.g == 0) build_candidates(gp, S, i);
-    if (!group_sync(gp, S)) return;
-    const int ncand = ld_atomic(&ctl->ncand);
-    if (gp.tid == 0) { S.cur_q = 0; S.cur_op = 0; }
-    __syncthreads();
+    row_begin(gp, S, i, cb);
+    lap(0);
     int T = d.t0;
     long long row_trials = 0, row_noops = 0, row_spec = 0;
     int acc_j = -1, acc_k = -1, acc_op = -1;
     while (true) {
-      build_batch(gp, S, i, T, ncand);
+      build_batch(gp, S, i, T, cb);
+      lap(1);
       const int nt = S.nt;
       if (nt == 0) { row_noops += S.batch_noops; break; }
-      if (!run_batch(gp, S, i, par, e_cur)) return;
+      if (!run_batch(gp, S, i, par, e_cur, lap)) return;
       const int dec = ld_atomic(&ctl->decision);
       row_spec += nt;
-      if (gp.tid == 0) {
-        S.prev_nt = nt;
-        for (int q = 0; q < nt; ++q) S.prev_ops[q] = S.trials[q].op;
-      }
+      if (gp.tid == 0) S.prev_nt = nt;
       if (dec >= 0) {
         row_trials += dec + 1;
         row_noops += S.noops_before[dec];
         const Trial tr = S.trials[dec];
         acc_j = tr.j; acc_k = tr.k; acc_op = tr.op;
         e_cur = ld_atomic(&ctl->e_new);
-        apply_trial(gp, S, i, par, dec);
-        if (!group_sync(gp, S)) return;
-        if (!refresh(gp, S, tr.k, true)) return;
+        if (!refresh(gp, S, tr.k, &tr, par, dec, i, true, cb ^ 1)) return;
+        cb ^= 1;
+        lap(4);
         par ^= 1;
         break;
       }
@@ -760,9 +1155,9 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
     ++row;
     ++rows_done;
     if (row == d.m) {
-      if (gp.g == 0 && gp.tid == 0) d.traj[it] = e_cur;
+      if (gp.g == 0 && gp.tid == 0) st_coh(&d.traj[it], e_cur);
       const bool fixed = acc_pass == 0;
-      const bool small = d.eps > 0.0 && (d.traj[it - 1] - e_cur) < d.eps;
+      const bool small = d.eps > 0.0 && (ld_atomic(&d.traj[it - 1]) - e_cur) < d.eps;
       if (fixed || small || it == d.iters) {
         if (gp.g == 0 && gp.tid == 0)
           for (int q = it + 1; q <= d.iters; ++q) d.traj[q] = e_cur;
@@ -775,13 +1170,17 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
     }
     if (gp.g == 0 && gp.tid == 0) {
       ctl->it = it; ctl->row = row; ctl->acc_in_pass = acc_pass; ctl->phase = phase;
+      ctl->cbuf = cb;
     }
+    lap(5);
   }
+  if (gp.g == 0 && gp.tid == 0)
+    for (int q = 0; q < 8; ++q) ctl->phase_ticks[q] += ticks[q];
   group_sync(gp, S);
 }
 
-// One fit per group of gsize workgroups.  With nfits > 1 every group takes
-// fits from a queue (ctl of fit 0 holds the counter).
+// One fit per group of gsize workgroups.  With nfits > 1 every workgroup
+// takes fits from a queue, one workgroup per fit.
 __global__ void __launch_bounds__(NTHR) fit_kernel(const FitDev* __restrict__ fits, int nfits,
                                                    int gsize, int max_rows,
                                                    unsigned* __restrict__ queue) {
@@ -799,7 +1198,6 @@ __global__ void __launch_bounds__(NTHR) fit_kernel(const FitDev* __restrict__ fi
     if (ld_atomic(&gp.ctl->phase) != 2) fit_run(gp, S, max_rows);
     return;
   }
-  // queue of fits, one workgroup per fit
   __shared__ int fid_s;
   while (true) {
     if (gp.tid == 0) fid_s = (int)atomicAdd(queue, 1u);

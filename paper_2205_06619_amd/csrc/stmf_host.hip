@@ -106,7 +106,7 @@ void options_default(stmf_options* o) {
   o->init_hi = 100.0f;
   o->acol_p = 5;
   o->noop_rule = 1;
-  o->batch_first = 8;
+  o->batch_first = 16;
   o->batch_max = TMAX;
 }
 
@@ -127,8 +127,8 @@ struct Layout {
   int m, n, r, iters;
   int mw, nw, ldm, ldn, nrt, nct, ldmax, G, acol_p;
   int transposed;
-  size_t Rw, RwT, Uc, V, td, tdpart, crow, ccol, colst, rowst, colpart, rowpart, order, cand,
-      tvec, epart, closed, traj, ctl, dev, perm, stage, check, rowc, colc;
+  size_t Rw, RwT, Uc, V, td, tdpart, crow, ccol, colst, rowst, colpart, rowpart, order,
+      tvec, epart, eprime, closed, traj, ctl, dev, perm, stage, check, rowc, colc;
   size_t total;
 };
 
@@ -150,16 +150,16 @@ static void make_layout(int m, int n, int r, int iters, int G, int acol_p, Layou
   L.V = take((size_t)r * L.ldn * 4);
   L.td = take((size_t)L.ldn * 8);
   L.tdpart = take((size_t)L.nrt * L.ldn * 8);
-  L.crow = take((size_t)L.ldm * r * 4);
-  L.ccol = take((size_t)L.ldn * r * 4);
+  L.crow = take((size_t)2 * L.ldm * r * 4);
+  L.ccol = take((size_t)2 * L.ldn * r * 4);
   L.colst = take((size_t)r * L.ldn * sizeof(Top2));
   L.rowst = take((size_t)r * L.ldm * sizeof(Top2));
   L.colpart = take((size_t)L.nrt * L.ldn * sizeof(Top2));
   L.rowpart = take((size_t)L.nct * L.ldm * sizeof(Top2));
   L.order = take((size_t)L.ldn * 4);
-  L.cand = take((size_t)L.ldn * 4);
   L.tvec = take((size_t)2 * TMAX * L.ldmax * 4);
   L.epart = take((size_t)TMAX * G * 8);
+  L.eprime = take((size_t)TMAX * 8);
   L.closed = take((size_t)r * 4);
   L.traj = take((size_t)(iters + 1) * 8);
   L.ctl = take(sizeof(FitCtl));
@@ -197,9 +197,9 @@ static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int o
   d.colpart = (Top2*)(base + L.colpart);
   d.rowpart = (Top2*)(base + L.rowpart);
   d.order = (int*)(base + L.order);
-  d.cand = (int*)(base + L.cand);
   d.tvec = (unsigned*)(base + L.tvec);
   d.epart = (double*)(base + L.epart);
+  d.eprime = (double*)(base + L.eprime);
   d.closed = (int*)(base + L.closed);
   d.traj = (double*)(base + L.traj);
   d.log = (LogRec*)o.decision_log;
@@ -357,6 +357,8 @@ static void fill_info(stmf_fit_info* info, const FitCtl& c, const Layout& L) {
   info->n_work = L.nw;
   info->group_size = L.G;
   info->nlog += c.nlog;
+  info->batches += c.batches;
+  for (int q = 0; q < 8; ++q) info->phase_ms[q] += (double)c.phase_ticks[q] * 1e-5;
 }
 
 static int auto_group(const Layout& L, const DevProps& P, int requested) {
@@ -515,11 +517,20 @@ int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters
   if (st) return st;
   FitDev d = make_dev(L, base, o, observed);
   HIPCHK(hipMemcpyAsync(base + L.dev, &d, sizeof(d), hipMemcpyHostToDevice, s));
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  HIPCHK(hipEventCreate(&ev0));
+  HIPCHK(hipEventCreate(&ev1));
+  HIPCHK(hipEventRecord(ev0, s));
   st = launch_fit_kernel((const FitDev*)(base + L.dev), 1, G, G, o.max_row_visits, nullptr, s);
-  if (st) return st;
+  if (st) { hipEventDestroy(ev0); hipEventDestroy(ev1); return st; }
+  HIPCHK(hipEventRecord(ev1, s));
   FitCtl c;
   HIPCHK(hipMemcpyAsync(&c, base + L.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  float kms = 0.0f;
+  hipEventElapsedTime(&kms, ev0, ev1);
+  hipEventDestroy(ev0);
+  hipEventDestroy(ev1);
   if (c.status == STMF_ETIMEOUT) return STMF_ETIMEOUT;
   if (c.status != 0) return STMF_EHIP;
   st = launch_output(L, base, U_out, V_out, s);
@@ -530,6 +541,7 @@ int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters
   if (info) {
     std::memset(info, 0, sizeof(*info));
     fill_info(info, c, L);
+    info->kernel_ms = kms;
   }
   return STMF_OK;
 }

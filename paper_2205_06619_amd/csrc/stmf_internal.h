@@ -3,14 +3,25 @@
 #pragma once
 #include <stdint.h>
 
+// The fit kernel's device code sees the workspace arrays of a fit as
+// global-address-space pointers (plain global loads instead of flat ones);
+// every other translation unit sees plain pointers.  The layout is the same.
+#if defined(__HIP_DEVICE_COMPILE__) && defined(STMF_FIT_KERNEL_TU)
+#define STMF_G(T) __attribute__((address_space(1))) T*
+#else
+#define STMF_G(T) T*
+#endif
+
 namespace stmf {
 
 constexpr int TS = 64;          // tile side: 64 rows x 64 columns of the working matrix
-constexpr int NWAVE = 4;        // waves per workgroup
+constexpr int NWAVE = 8;        // waves per workgroup
 constexpr int NTHR = 64 * NWAVE;
-constexpr int TMAX = 64;        // trials per speculative batch (upper bound)
-constexpr int TPW = TMAX / NWAVE;  // trials one wave owns in a batch
+constexpr int TMAX = 512;       // trials per speculative batch (upper bound)
+constexpr int TCH = 64;         // trials staged in LDS at a time
+constexpr int CW = 128;         // candidate columns examined at a time
 constexpr int RMAX = 64;        // largest supported rank
+constexpr int SORT_MAX = 4096;  // widest matrix sorted in one workgroup's LDS
 
 // Top-2 summary of a residual line: smallest value, its (lowest) index, and
 // the second smallest value (equal to m1 on ties; +inf if the line has one
@@ -70,7 +81,8 @@ struct FitCtl {
   long long batches;
   long long cells;       // sum over evaluated trials of |Omega| (method count)
   int nlog;
-  int pad1;
+  int cbuf;              // which of the two argmax-count buffers is current
+  long long phase_ticks[8];  // leader's wall time per phase (100 MHz ticks)
 };
 
 // Device-side descriptor of one fit.  All arrays live in the caller's
@@ -86,26 +98,26 @@ struct FitDev {
   int log_cap;
   int omega;             // number of observed cells
   double eps;
-  const float* Rw;       // ldm x ldn, +inf at unobserved and padding cells
-  const float* RwT;      // ldn x ldm, the transpose
-  float* Uc;             // r x ldm: Uc[l*ldm + t] = U_tl
-  float* V;              // r x ldn: V[l*ldn + c]  = V_lc
-  double* td;            // ldn: td_col
-  double* tdpart;        // nrt x ldn
-  int* crow;             // ldm x r: argmax counts of every row
-  int* ccol;             // ldn x r: argmax counts of every column
-  Top2* colst;           // r x ldn: top-2 of R_tc - U_tk over t (per component)
-  Top2* rowst;           // r x ldm: top-2 of R_tc - V_kc over c
-  Top2* colpart;         // nrt x ldn: per row-tile partial of colst (one component)
-  Top2* rowpart;         // nct x ldm
-  int* order;            // ldn: columns by (td_col desc, index asc)
-  int* cand;             // ldn: candidate columns of the current row
-  unsigned* tvec;        // 2 x TMAX x ldmax: atomic-min targets (order-mapped floats)
-  double* epart;         // TMAX x gsize: per-workgroup partial errors
-  int* closed;           // r
-  double* traj;          // iters + 1
-  LogRec* log;           // nullable
-  FitCtl* ctl;
+  STMF_G(const float) Rw;    // ldm x ldn, +inf at unobserved and padding cells
+  STMF_G(const float) RwT;   // ldn x ldm, the transpose
+  STMF_G(float) Uc;          // r x ldm: Uc[l*ldm + t] = U_tl
+  STMF_G(float) V;           // r x ldn: V[l*ldn + c]  = V_lc
+  STMF_G(double) td;         // ldn: td_col
+  STMF_G(double) tdpart;     // nrt x ldn
+  STMF_G(int) crow;          // 2 x ldm x r: argmax counts of every row (two buffers)
+  STMF_G(int) ccol;          // 2 x ldn x r: argmax counts of every column (two buffers)
+  STMF_G(Top2) colst;        // r x ldn: top-2 of R_tc - U_tk over t (per component)
+  STMF_G(Top2) rowst;        // r x ldm: top-2 of R_tc - V_kc over c
+  STMF_G(Top2) colpart;      // nrt x ldn: per row-tile partial of colst (one component)
+  STMF_G(Top2) rowpart;      // nct x ldm
+  STMF_G(int) order;         // ldn: columns by (td_col desc, index asc)
+  STMF_G(unsigned) tvec;     // 2 x TMAX x ldmax: atomic-min targets (order-mapped floats)
+  STMF_G(double) epart;      // TMAX x gsize: per-workgroup partial errors
+  STMF_G(double) eprime;     // TMAX: error of every trial of the batch
+  STMF_G(int) closed;        // r
+  STMF_G(double) traj;       // iters + 1
+  STMF_G(LogRec) log;        // nullable
+  STMF_G(FitCtl) ctl;
   int ldmax;
   int gsize;             // workgroups cooperating on this fit
 };

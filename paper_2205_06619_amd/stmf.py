@@ -53,10 +53,13 @@ class FitInfo(C.Structure):
         ("accepted", C.c_longlong), ("row_visits", C.c_longlong), ("cells", C.c_longlong),
         ("iters_done", C.c_int), ("transposed", C.c_int), ("m_work", C.c_int),
         ("n_work", C.c_int), ("group_size", C.c_int), ("nlog", C.c_int),
+        ("batches", C.c_longlong), ("phase_ms", C.c_double * 8), ("kernel_ms", C.c_double),
     ]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["phase_ms"] = list(self.phase_ms)
+        return d
 
 
 class Problem(C.Structure):
