@@ -112,10 +112,25 @@ DEV void atomic_add_g(GA int* p, int v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Exact max and min of the value path.  No NaN ever enters it (missing cells
+// are +inf sentinels, or FLT_MAX in the error pass), so IEEE maximum/minimum
+// equal max/min here; unlike fmaxf/fminf they need no input canonicalisation
+// and pair up into the three-operand instructions.
+DEV float vmax(float a, float b) { return __builtin_elementwise_maximum(a, b); }
+DEV float vmin(float a, float b) { return __builtin_elementwise_minimum(a, b); }
+
 // ------------------------------------------------------------ LDS layout
-struct BatchScratch {
+struct EvalVectors {
   float sA[TCH][TS];         // per staged trial: changed U column at the tile rows
   float sB[TCH][TS];         // per staged trial: changed V row at the tile columns
+};
+struct BatchScratch {
+  union {
+    EvalVectors e;           // error pass
+    float sX[2 * TCH][TS];   // residual pass: the one vector each trial needs
+  } v;
+  double epl[TCH][2][TS / 2];  // error pass: per staged trial, row half and lane
+                               // pair, partial error
 };
 struct RefreshScratch {
   int hc[TS][RMAX];          // argmax histogram of the tile columns
@@ -151,9 +166,14 @@ struct Smem {
   double wsum[TMAX];         // per trial: this workgroup's partial error
   Trial trials[TMAX];
   int noops_before[TMAX];    // no-op skips preceding each trial in the batch
-  int byk[TMAX];             // trial indices grouped by component (stable)
-  int kdistinct[RMAX];
-  int kstart[RMAX + 1];
+  int byk[TMAX];             // trial indices grouped by (component, operation)
+  int gstart[2 * RMAX + 1];  // group g: byk[gstart[g] .. gstart[g + 1])
+  int ng;                    // groups of the batch
+  int nop[2];                // F-ULF and F-URF trials of the batch
+  int wk[NWAVE][2 * RMAX];   // per wave and group key: trial count, then offset
+  float Ri[TS];              // R of the visited row at the tile columns
+  float colbase[TS];         // F-ULF: column residual of U_.k without row i
+  Top2 rtop[TS];             // F-URF: row residual summaries of component k
   float urow_i[RMAX];        // U of the visited row, every component
   int closed_s[RMAX];        // closed flags at the start of the row visit
   int crow_i[RMAX];          // argmax counts of the visited row
@@ -161,7 +181,6 @@ struct Smem {
   int cq_head, cq_n, ord_pos;
   int prev_nt;
   int nt;
-  int nk;
   int batch_noops;
   int cur_op;
   int exhausted;
@@ -182,6 +201,8 @@ struct Smem {
 
 static_assert(sizeof(Smem) <= 160 * 1024, "LDS layout exceeds a CU's 160 KB");
 static_assert(TMAX <= NTHR && 2 * CW <= NTHR && CW * 4 <= NTHR, "one thread per trial / pair");
+static_assert(RMAX == 64, "one lane per component (two group keys) in the batch grouping");
+static_assert(TCH * 8 == NTHR, "eight threads per staged trial in the error reduction");
 
 struct Grp {
   const FitDev* d;
@@ -306,68 +327,147 @@ DEV void compute_pnotk(Grp& gp, Smem& S, int k) {
     if (l == k) continue;
     const float v = S.Vt[l][gp.lane];
 #pragma unroll
-    for (int tt = 0; tt < RPW; ++tt) P[tt] = fmaxf(P[tt], S.Ut[l][tl0 + tt] + v);
+    for (int tt = 0; tt < RPW; ++tt) P[tt] = vmax(P[tt], S.Ut[l][tl0 + tt] + v);
   }
 #pragma unroll
   for (int tt = 0; tt < RPW; ++tt) S.Ps[tl0 + tt][gp.lane] = P[tt];
 }
 
+// ------------------------------------------------------------ trial staging
+// The first residual of a trial, restricted to a tile, from data staged once
+// per tile and component (every trial of a batch shares the visited row i):
+//   F-ULF, tile column x: V'_kc = min(excl(colst_kc, i), R_ic - u)
+//   F-URF, tile row x:    U'_tk = min(excl(rowst_kt, j), R_tj - v)
+// Padding rows and columns take 0.
+DEV void stage_ri(Grp& gp, Smem& S, int i, int c0) {
+  const FitDev& d = *gp.d;
+  if (gp.tid < TS) S.Ri[gp.tid] = d.Rw[(size_t)i * d.ldn + c0 + gp.tid];
+}
+DEV void stage_comp(Grp& gp, Smem& S, int op, int k, int r0, int c0, int i) {
+  const FitDev& d = *gp.d;
+  if (gp.tid < TS) {
+    if (op == OP_ULF) S.colbase[gp.tid] = excl(ld_top2(&d.colst[(size_t)k * d.ldn + c0 + gp.tid]), i);
+    else if (op == OP_URF) S.rtop[gp.tid] = ld_top2(&d.rowst[(size_t)k * d.ldm + r0 + gp.tid]);
+  }
+}
+
+// Vectors of the cn trials byk[cs ..] at the tile: wave w stages trials w,
+// w + NWAVE, ... (lane = tile row or column), NE at most; every global load
+// is issued before any element is written to LDS.
+template <int NE>
+DEV void stage_ulf_cols(Grp& gp, Smem& S, int cs, int cn, int c0, float (*out)[TS]) {
+  const FitDev& d = *gp.d;
+  const int x = gp.lane;
+  const bool in = c0 + x < d.n;
+  const float cb = S.colbase[x], ri = S.Ri[x];
+#pragma unroll
+  for (int m = 0; m < NE; ++m) {
+    const int sl = gp.wave + m * NWAVE;
+    if (sl < cn) out[sl][x] = in ? vmin(cb, ri - S.trials[S.byk[cs + sl]].val) : 0.0f;
+  }
+}
+template <int NE>
+DEV void stage_urf_rows(Grp& gp, Smem& S, int cs, int cn, int r0, float (*out)[TS]) {
+  const FitDev& d = *gp.d;
+  const int x = gp.lane;
+  float raw[NE];
+#pragma unroll
+  for (int m = 0; m < NE; ++m) {
+    const int sl = gp.wave + m * NWAVE;
+    if (sl < cn) raw[m] = d.RwT[(size_t)S.trials[S.byk[cs + sl]].j * d.ldm + r0 + x];
+  }
+  const bool in = r0 + x < d.m;
+  const Top2 rt = S.rtop[x];
+#pragma unroll
+  for (int m = 0; m < NE; ++m) {
+    const int sl = gp.wave + m * NWAVE;
+    if (sl < cn) {
+      const Trial& tr = S.trials[S.byk[cs + sl]];
+      out[sl][x] = in ? vmin(excl(rt, tr.j), raw[m] - tr.val) : 0.0f;
+    }
+  }
+}
+// Second residuals of the staged trials (the atomic-min targets) at working
+// indices base + lane, valid below lim.
+template <int NE>
+DEV void stage_second(Grp& gp, Smem& S, int par, int cs, int cn, int base, int lim, float (*out)[TS]) {
+  const FitDev& d = *gp.d;
+  const int x = gp.lane;
+  unsigned raw[NE];
+#pragma unroll
+  for (int m = 0; m < NE; ++m) {
+    const int sl = gp.wave + m * NWAVE;
+    if (sl < cn) raw[m] = ld_atomic(&d.tvec[((size_t)par * TMAX + S.byk[cs + sl]) * d.ldmax + base + x]);
+  }
+  const bool in = base + x < lim;
+#pragma unroll
+  for (int m = 0; m < NE; ++m) {
+    const int sl = gp.wave + m * NWAVE;
+    if (sl < cn) out[sl][x] = in ? funmap(raw[m]) : 0.0f;
+  }
+}
+
 // ------------------------------------------------------------ pass 1 of a batch
 // Second residual of every trial over this workgroup's tiles, combined across
-// tiles with an atomic min on order-preserving integer images (exact).
-// Trials are staged TCH at a time.
+// tiles with an atomic min on order-preserving integer images (exact).  The
+// F-ULF trials come first (lanes over the tile rows, the tile's R rows in
+// registers), then the F-URF trials (lanes over the tile columns); each trial
+// stages the one first-residual vector it needs, 2 * TCH trials at a time.
 DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
   const FitDev& d = *gp.d;
-  const int nt = S.nt;
   const int ntile = d.nrt * d.nct;
+  constexpr int NE = 2 * TCH / NWAVE;
   for (int tile = gp.g; tile < ntile; tile += gp.G) {
     const int rt = tile / d.nct, ct = tile % d.nct;
     const int r0 = rt * TS, c0 = ct * TS;
-    for (int cs = 0; cs < nt; cs += TCH) {
-      const int cn = nt - cs < TCH ? nt - cs : TCH;
-      __syncthreads();
-      // incremental first residuals for the tile: F-ULF needs V'_k. on the
-      // tile columns, F-URF needs U'_.k on the tile rows
-      bool anyU = false, anyV = false;
-      for (int s2 = 0; s2 < cn; ++s2) {
-        anyU |= S.trials[cs + s2].op == OP_ULF;
-        anyV |= S.trials[cs + s2].op == OP_URF;
-      }
-      for (int e = gp.tid; e < cn * TS; e += NTHR) {
-        const int sl = e / TS, x = e % TS, q = cs + sl;
-        const Trial& tr = S.trials[q];
-        if (tr.op == OP_ULF) S.u.b.sB[sl][x] = col_side(d, tr, par, q, c0 + x, i);
-        else if (tr.op == OP_URF) S.u.b.sA[sl][x] = row_side(d, tr, par, q, r0 + x);
-      }
-      __syncthreads();
-      if (anyU) {
-        // lanes over rows: U''_tk = min over the tile columns of R_tc - V'_kc
-        float Rrow[TS];
-#pragma unroll
-        for (int c = 0; c < TS; ++c) Rrow[c] = d.RwT[(size_t)(c0 + c) * d.ldm + r0 + gp.lane];
+    __syncthreads();
+    stage_ri(gp, S, i, c0);
 #pragma unroll 1
-        for (int sl = gp.wave; sl < cn; sl += NWAVE) {
-          if (S.trials[cs + sl].op != OP_ULF) continue;
-          float x = FINF;
+    for (int side = 0; side < 2; ++side) {
+      // side 0, F-ULF: U''_tk = min over the tile columns of R_tc - V'_kc
+      // side 1, F-URF: V''_kc = min over the tile rows of R_tc - U'_tk
+      if (S.nop[side] == 0) continue;
+      const GA float* rb = side ? d.Rw + (size_t)r0 * d.ldn + c0 + gp.lane
+                                : d.RwT + (size_t)c0 * d.ldm + r0 + gp.lane;
+      const size_t rs = side ? (size_t)d.ldn : (size_t)d.ldm;
+      float Rv[TS];
 #pragma unroll
-          for (int c = 0; c < TS; ++c) x = fminf(x, Rrow[c] - S.u.b.sB[sl][c]);
-          if (x != FINF)
-            atomic_min_g(&d.tvec[((size_t)par * TMAX + cs + sl) * d.ldmax + r0 + gp.lane], fmap(x));
-        }
-      }
-      if (anyV) {
-        // lanes over columns: V''_kc = min over the tile rows of R_tc - U'_tk
-        float Rcol[TS];
-#pragma unroll
-        for (int t = 0; t < TS; ++t) Rcol[t] = d.Rw[(size_t)(r0 + t) * d.ldn + c0 + gp.lane];
+      for (int x = 0; x < TS; ++x) Rv[x] = rb[x * rs];
+      const int own = (side ? c0 : r0) + gp.lane;
 #pragma unroll 1
-        for (int sl = gp.wave; sl < cn; sl += NWAVE) {
-          if (S.trials[cs + sl].op != OP_URF) continue;
-          float y = FINF;
+      for (int g = 0; g < S.ng; ++g) {
+        const int gb = S.gstart[g], ge = S.gstart[g + 1];
+        const Trial t0 = S.trials[S.byk[gb]];
+        if (t0.op != side) continue;
+        __syncthreads();
+        stage_comp(gp, S, side, t0.k, r0, c0, i);
+#pragma unroll 1
+        for (int cs = gb; cs < ge; cs += 2 * TCH) {
+          const int cn = ge - cs < 2 * TCH ? ge - cs : 2 * TCH;
+          __syncthreads();
+          if (side) stage_urf_rows<NE>(gp, S, cs, cn, r0, S.u.b.v.sX);
+          else stage_ulf_cols<NE>(gp, S, cs, cn, c0, S.u.b.v.sX);
+          __syncthreads();
+#pragma unroll 1
+          for (int sl = gp.wave; sl < cn; sl += NWAVE) {
+            const float4* sx = reinterpret_cast<const float4*>(S.u.b.v.sX[sl]);
+            float x0 = FINF, x1 = FINF, x2 = FINF, x3 = FINF;
 #pragma unroll
-          for (int t = 0; t < TS; ++t) y = fminf(y, Rcol[t] - S.u.b.sA[sl][t]);
-          if (y != FINF)
-            atomic_min_g(&d.tvec[((size_t)par * TMAX + cs + sl) * d.ldmax + c0 + gp.lane], fmap(y));
+            for (int c4 = 0; c4 < TS / 4; c4 += 2) {
+              const float4 s = sx[c4], s2 = sx[c4 + 1];
+              const int c = 4 * c4;
+              x0 = vmin(vmin(x0, Rv[c + 0] - s.x), Rv[c + 1] - s.y);
+              x1 = vmin(vmin(x1, Rv[c + 2] - s.z), Rv[c + 3] - s.w);
+              x2 = vmin(vmin(x2, Rv[c + 4] - s2.x), Rv[c + 5] - s2.y);
+              x3 = vmin(vmin(x3, Rv[c + 6] - s2.z), Rv[c + 7] - s2.w);
+            }
+            const float x = vmin(vmin(x0, x1), vmin(x2, x3));
+            // +inf: no observed cell of this row (column) in the tile
+            if (x != FINF) {
+              const int q = S.byk[cs + sl];
+              atomic_min_g(&d.tvec[((size_t)par * TMAX + q) * d.ldmax + own], fmap(x));
+            }
+          }
         }
       }
     }
@@ -375,74 +475,115 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
 }
 
 // ------------------------------------------------------------ pass 2 of a batch
-// b-norm of every trial over this workgroup's tiles.  Trials are grouped by
-// component k (S.byk); per tile and k the product without k is formed once.
-// Per lane and trial the sum runs over each half-tile of 32 rows in four
-// interleaved FP64 accumulators, is reduced across the lanes by a fixed
-// butterfly, and added to the workgroup's per-trial sum in tile and half
-// order.
+// b-norm of every trial over this workgroup's tiles.  Trials come in groups of
+// one component and operation (S.byk); per tile and component the product
+// without k is formed once.  Wave w takes the tile rows of half w & 1 (lane =
+// tile column) for the staged trials (w >> 1), (w >> 1) + 4, ..., holding that
+// half's R and product without k in registers.  Per lane and trial the
+// half-column sum runs over its 32 rows in four interleaved FP64
+// accumulators; lane pairs are added, and the 64 pair sums of a trial are
+// added in a fixed tree; the tile's sum is added to the workgroup's per-trial
+// sum in tile order.
+DEV double pair_sum(double v) {
+  // lanes 2m and 2m + 1 exchange (quad permutation 1, 0, 3, 2) and add: both
+  // get the same sum
+  const unsigned long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return v + __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
   const FitDev& d = *gp.d;
   const int nt = S.nt;
+  constexpr int NE = TCH / NWAVE;
   for (int q = gp.tid; q < nt; q += NTHR) S.wsum[q] = 0.0;
   const int ntile = d.nrt * d.nct;
+  const int half = gp.wave & 1, h0 = half * (TS / 2);
   for (int tile = gp.g; tile < ntile; tile += gp.G) {
     const int rt = tile / d.nct, ct = tile % d.nct;
     const int r0 = rt * TS, c0 = ct * TS;
     __syncthreads();
     stage_uv(gp, S, r0, c0);
+    stage_ri(gp, S, i, c0);
+    // an unobserved cell takes R = P = FLT_MAX, which contributes |d| = 0
+    float Rev[TS / 2], Pc[TS / 2];
+    unsigned obs = 0;
+#pragma unroll
+    for (int t = 0; t < TS / 2; ++t) {
+      const float rv = d.Rw[(size_t)(r0 + h0 + t) * d.ldn + c0 + gp.lane];
+      const bool o = rv != FINF;
+      obs |= (unsigned)o << t;
+      Rev[t] = o ? rv : FLT_MAX;
+    }
+    int kcur = -1;
 #pragma unroll 1
-    for (int kq = 0; kq < S.nk; ++kq) {
-      const int k = S.kdistinct[kq];
+    for (int g = 0; g < S.ng; ++g) {
+      const int gb = S.gstart[g], ge = S.gstart[g + 1];
+      const Trial t0 = S.trials[S.byk[gb]];
       __syncthreads();
-      compute_pnotk(gp, S, k);
-      const int kb = S.kstart[kq], ke = S.kstart[kq + 1];
-#pragma unroll 1
-      for (int cs = kb; cs < ke; cs += TCH) {
-        const int cn = ke - cs < TCH ? ke - cs : TCH;
+      if (t0.k != kcur) {
+        compute_pnotk(gp, S, t0.k);
         __syncthreads();
-        for (int e = gp.tid; e < cn * TS; e += NTHR) {
-          const int sl = e / TS, x = e % TS, q = S.byk[cs + sl];
-          const Trial& tr = S.trials[q];
-          S.u.b.sA[sl][x] = row_side(d, tr, par, q, r0 + x);
-          S.u.b.sB[sl][x] = col_side(d, tr, par, q, c0 + x, i);
+#pragma unroll
+        for (int t = 0; t < TS / 2; ++t) Pc[t] = ((obs >> t) & 1u) ? S.Ps[h0 + t][gp.lane] : FLT_MAX;
+        kcur = t0.k;
+      }
+      stage_comp(gp, S, t0.op, t0.k, r0, c0, i);
+#pragma unroll 1
+      for (int cs = gb; cs < ge; cs += TCH) {
+        const int cn = ge - cs < TCH ? ge - cs : TCH;
+        __syncthreads();
+        if (t0.op == OP_ULF) {
+          stage_second<NE>(gp, S, par, cs, cn, r0, d.m, S.u.b.v.e.sA);
+          stage_ulf_cols<NE>(gp, S, cs, cn, c0, S.u.b.v.e.sB);
+        } else if (t0.op == OP_URF) {
+          stage_urf_rows<NE>(gp, S, cs, cn, r0, S.u.b.v.e.sA);
+          stage_second<NE>(gp, S, par, cs, cn, c0, d.n, S.u.b.v.e.sB);
+        } else {
+          // the null trial: the current component
+          for (int e = gp.tid; e < cn * TS; e += NTHR) {
+            const int sl = e / TS, x = e % TS;
+            S.u.b.v.e.sA[sl][x] = r0 + x < d.m ? ld_atomic(&d.Uc[(size_t)t0.k * d.ldm + r0 + x]) : 0.0f;
+            S.u.b.v.e.sB[sl][x] = c0 + x < d.n ? ld_atomic(&d.V[(size_t)t0.k * d.ldn + c0 + x]) : 0.0f;
+          }
         }
         __syncthreads();
-        // two halves of 32 rows: R and P without k held in registers per half
 #pragma unroll 1
-        for (int h = 0; h < TS; h += TS / 2) {
-          float Rev[TS / 2], Pc[TS / 2];
+        for (int sl = gp.wave >> 1; sl < cn; sl += NWAVE / 2) {
+          const float vs = S.u.b.v.e.sB[sl][gp.lane];
+          const float4* sa = reinterpret_cast<const float4*>(&S.u.b.v.e.sA[sl][h0]);
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
-          for (int t = 0; t < TS / 2; ++t) {
-            const float rv = d.Rw[(size_t)(r0 + h + t) * d.ldn + c0 + gp.lane];
-            // unobserved: R = P = FLT_MAX gives d = 0
-            Rev[t] = (rv == FINF) ? FLT_MAX : rv;
-            Pc[t] = __builtin_canonicalizef((rv == FINF) ? FLT_MAX : S.Ps[h + t][gp.lane]);
+          for (int t4 = 0; t4 < TS / 8; ++t4) {
+            const float4 s = sa[t4];
+            const int t = 4 * t4;
+            const float d0 = Rev[t + 0] - vmax(Pc[t + 0], s.x + vs);
+            const float d1 = Rev[t + 1] - vmax(Pc[t + 1], s.y + vs);
+            const float d2 = Rev[t + 2] - vmax(Pc[t + 2], s.z + vs);
+            const float d3 = Rev[t + 3] - vmax(Pc[t + 3], s.w + vs);
+            a0 += fabs((double)d0);
+            a1 += fabs((double)d1);
+            a2 += fabs((double)d2);
+            a3 += fabs((double)d3);
           }
-#pragma unroll 1
-          for (int sl = gp.wave; sl < cn; sl += NWAVE) {
-            const float vs = S.u.b.sB[sl][gp.lane];
-            const float* sa = &S.u.b.sA[sl][h];
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll
-            for (int t = 0; t < TS / 2; t += 4) {
-              float n0 = sa[t + 0] + vs, n1 = sa[t + 1] + vs;
-              float n2 = sa[t + 2] + vs, n3 = sa[t + 3] + vs;
-              float d0 = Rev[t + 0] - fmaxf(Pc[t + 0], n0);
-              float d1 = Rev[t + 1] - fmaxf(Pc[t + 1], n1);
-              float d2 = Rev[t + 2] - fmaxf(Pc[t + 2], n2);
-              float d3 = Rev[t + 3] - fmaxf(Pc[t + 3], n3);
-              a0 += fabs((double)d0);
-              a1 += fabs((double)d1);
-              a2 += fabs((double)d2);
-              a3 += fabs((double)d3);
-            }
-            // lane butterfly (fixed pattern); the owning wave adds the half's sum
-            double v = (a0 + a1) + (a2 + a3);
-#pragma unroll
-            for (int sft = 32; sft >= 1; sft >>= 1) v += __shfl_xor(v, sft, 64);
-            if (gp.lane == 0) S.wsum[S.byk[cs + sl]] += v;
+          const double v = pair_sum((a0 + a1) + (a2 + a3));
+          if ((gp.lane & 1) == 0) S.u.b.epl[sl][half][gp.lane >> 1] = v;
+        }
+        __syncthreads();
+        // per staged trial: eight threads add eight pair sums each (half 0
+        // first), then a fixed butterfly over the eight (all get the same sum)
+        {
+          const int sl = gp.tid >> 3, sub = gp.tid & 7;
+          double s = 0.0;
+          if (sl < cn) {
+            const double* p = &S.u.b.epl[sl][sub >> 2][(sub & 3) * 8];
+            s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
           }
+          s += __shfl_xor(s, 1, 64);
+          s += __shfl_xor(s, 2, 64);
+          s += __shfl_xor(s, 4, 64);
+          if (sl < cn && sub == 0) S.wsum[S.byk[cs + sl]] += s;
         }
       }
     }
@@ -964,42 +1105,67 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb) {
     }
     __syncthreads();
   }
-  // group the trials by component (first-appearance order, stable within a
-  // group) for the error pass
-  if (gp.tid == 0) {
-    int nk = 0;
-    for (int q = 0; q < S.nt; ++q) {
-      const int k = S.trials[q].k;
-      int seen = 0;
-      for (int y = 0; y < nk; ++y) seen |= S.kdistinct[y] == k;
-      if (!seen) S.kdistinct[nk++] = k;
-      if (nk == RMAX) break;
-    }
-    S.nk = nk;
-    S.exhausted = (S.cq_n - S.cq_head) == 0 && S.ord_pos >= d.n;
-  }
-  __syncthreads();
+  if (gp.tid == 0) S.exhausted = (S.cq_n - S.cq_head) == 0 && S.ord_pos >= d.n;
+  // Group the trials for the two passes by key 2k + op (component-major,
+  // F-ULF before F-URF, stable within a group).  One thread per trial; ranks
+  // within a wave by ballot, offsets from per-wave counts by key.
   {
-    int base = 0;
-    for (int kq = 0; kq < S.nk; ++kq) {
-      const int k = S.kdistinct[kq];
-      if (gp.tid == 0) S.kstart[kq] = base;
-      const int q = gp.tid;
-      const bool match = q < S.nt && S.trials[q].k == k;
-      const unsigned long long m = __ballot(match);
-      if (gp.lane == 0) S.wcount[gp.wave] = __popcll(m);
-      __syncthreads();
-      int pos = base + __popcll(m & ((1ull << gp.lane) - 1ull));
-      int tot = 0;
-      for (int w = 0; w < NWAVE; ++w) {
-        if (w < gp.wave) pos += S.wcount[w];
-        tot += S.wcount[w];
+    const int q = gp.tid;
+    const bool valid = q < S.nt;
+    const int key = valid ? 2 * S.trials[q].k + S.trials[q].op : -1;
+    const unsigned long long below = (1ull << gp.lane) - 1ull;
+    int rank = 0, c0 = 0, c1 = 0;  // rank among the wave's trials of the key;
+                                   // lane l: the wave's trials of keys 2l, 2l+1
+    unsigned long long rem = __ballot(valid);
+    while (rem) {
+      const int kl = __shfl(key, __ffsll((long long)rem) - 1, 64);
+      const unsigned long long m = __ballot(valid && key == kl);
+      if (valid && key == kl) rank = __popcll(m & below);
+      if (gp.lane == (kl >> 1)) {
+        if (kl & 1) c1 = __popcll(m); else c0 = __popcll(m);
       }
-      if (match) S.byk[pos] = q;
-      base += tot;
-      __syncthreads();
+      rem &= ~m;
     }
-    if (gp.tid == 0) S.kstart[S.nk] = base;
+    S.wk[gp.wave][2 * gp.lane] = c0;
+    S.wk[gp.wave][2 * gp.lane + 1] = c1;
+    __syncthreads();
+    if (gp.wave == 0) {
+      // lane l: keys 2l and 2l + 1.  Group starts by an exclusive scan over
+      // the keys, then the start of every wave's share of each key.
+      int t0 = 0, t1 = 0;
+      for (int w = 0; w < NWAVE; ++w) { t0 += S.wk[w][2 * gp.lane]; t1 += S.wk[w][2 * gp.lane + 1]; }
+      // trials in the low bits, non-empty groups from bit 16
+      const int mine = (t0 + t1) | (((t0 > 0) + (t1 > 0)) << 16);
+      int incl = mine;
+      for (int sft = 1; sft < 64; sft <<= 1) {
+        const int v = __shfl_up(incl, sft, 64);
+        if (gp.lane >= sft) incl += v;
+      }
+      const int excl_sum = incl - mine;
+      int run = excl_sum & 0xFFFF, gpos = excl_sum >> 16;
+      if (t0 > 0) S.gstart[gpos++] = run;
+      if (t1 > 0) S.gstart[gpos] = run + t0;
+      if (gp.lane == 63) { S.ng = incl >> 16; S.gstart[incl >> 16] = incl & 0xFFFF; }
+      int r1 = run + t0;
+      for (int w = 0; w < NWAVE; ++w) {
+        const int a = S.wk[w][2 * gp.lane], b = S.wk[w][2 * gp.lane + 1];
+        S.wk[w][2 * gp.lane] = run;
+        S.wk[w][2 * gp.lane + 1] = r1;
+        run += a;
+        r1 += b;
+      }
+    }
+    // operation counts (the ballot is taken by the whole wave)
+    const unsigned long long mu = __ballot(valid && (key & 1) == 0);
+    if (gp.lane == 0) S.wcount[gp.wave] = __popcll(mu);
+    __syncthreads();
+    if (valid) S.byk[S.wk[gp.wave][key] + rank] = q;
+    if (gp.tid == 0) {
+      int nu = 0;
+      for (int w = 0; w < NWAVE; ++w) nu += S.wcount[w];
+      S.nop[0] = nu;
+      S.nop[1] = S.nt - nu;
+    }
   }
   __syncthreads();
 }
@@ -1046,7 +1212,7 @@ DEV bool fit_init(Grp& gp, Smem& S) {
     if (!refresh(gp, S, k, nullptr, 0, 0, 0, k == d.r - 1, 0)) return false;
   if (gp.tid == 0) {
     Trial tr; tr.j = 0; tr.k = 0; tr.op = OP_NULL; tr.val = 0.0f;
-    S.trials[0] = tr; S.nt = 1; S.nk = 1; S.kdistinct[0] = 0; S.kstart[0] = 0; S.kstart[1] = 1;
+    S.trials[0] = tr; S.nt = 1; S.ng = 1; S.gstart[0] = 0; S.gstart[1] = 1;
     S.byk[0] = 0; S.prev_nt = 0;
   }
   __syncthreads();
@@ -1184,7 +1350,7 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
 __global__ void __launch_bounds__(NTHR) fit_kernel(const FitDev* __restrict__ fits, int nfits,
                                                    int gsize, int max_rows,
                                                    unsigned* __restrict__ queue) {
-  extern __shared__ char smem_raw[];
+  extern __shared__ __align__(16) char smem_raw[];
   Smem& S = *reinterpret_cast<Smem*>(smem_raw);
   Grp gp;
   gp.tid = threadIdx.x;
