@@ -125,7 +125,8 @@ typedef struct {
   int integer_exact;    /* 1: STMF_ERANGE unless every observed |R| and |U0| < 2^24  */
   void* decision_log;   /* device, nullable: one stmf_log_rec per row visit          */
   int log_cap;          /* capacity of decision_log in records                       */
-  int batch_first;      /* speculative trials in the first batch of a row (default 16) */
+  int batch_first;      /* speculative trials in the first batch of a row; 0 (default):
+                           512 / tiles per workgroup, a power of two, at least 4  */
   int batch_max;        /* largest batch, <= 512 (default 512)                         */
   int group_size;       /* workgroups cooperating on one fit (0 = automatic)          */
   int max_row_visits;   /* stop after this many row visits (0 = no limit)            */
@@ -151,9 +152,10 @@ typedef struct {
   int group_size;         /* workgroups used                                        */
   int nlog;               /* row visits logged (may exceed log_cap)                 */
   long long batches;      /* speculative batches evaluated                          */
-  double phase_ms[8];     /* time of the fit kernel's phases on the group leader:
-                             candidates, batch lists, residual pass, error pass and
-                             decision, apply and refresh, bookkeeping               */
+  double phase_ms[8];     /* time of the fit kernel's phases on the group leader,
+                             by index: 0 row start, 1 batch lists, 2 residual pass,
+                             3 error reduction and decision, 4 apply and refresh,
+                             5 bookkeeping, 6 error pass, 7 unused                  */
   double kernel_ms;       /* fit kernel time, HIP events on the fit's stream        */
 } stmf_fit_info;
 
@@ -208,10 +210,11 @@ size_t stmf_fit_batched_workspace(const stmf_problem* probs, int nprob, int rest
                                   const stmf_options* opt);
 
 /* Many independent fits in one persistent launch (one workgroup per fit,
- * longest fits first).  Restart q of problem p uses seed
- * SplitMix64(probs[p].seed) output q.  Synchronous.  info (host, nullable)
- * gets the summed counters.  Results equal stmf_fit with the same seed and
- * group_size 1. */
+ * longest fits first).  With one restart a problem's fit uses its seed; with
+ * several, restart q uses output q of SplitMix64 seeded with the problem's
+ * seed.  Synchronous.  info (host, nullable) gets the summed counters.
+ * Results equal stmf_fit with the same seed and group_size 1.  Options
+ * decision_log, perm, init_mode 2 and max_row_visits are rejected. */
 int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts,
                      const stmf_options* opt, stmf_fit_info* info, void* ws,
                      size_t ws_bytes, void* stream);

@@ -1181,6 +1181,7 @@ DEV bool run_batch(Grp& gp, Smem& S, int i, int par, double e_cur, Lap& lap) {
   batch_eval_pass(gp, S, i, par);
   clear_prev(gp, S, par ^ 1);
   if (!group_sync(gp, S)) return false;
+  lap(6);
   reduce_errors(gp, S, S.nt);
   const bool ok = group_sync_last(gp, S, [&] { decide(gp, S, S.nt, e_cur); });
   lap(3);
@@ -1258,7 +1259,7 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
   int rows_done = 0;
   int par = 0;
   // leader-side phase timers: 0 row start, 1 batch list, 2 residual pass,
-  // 3 error pass and decision, 4 refresh, 5 bookkeeping
+  // 6 error pass, 3 error reduction and decision, 4 refresh, 5 bookkeeping
   long long ticks[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   unsigned long long tmark = __builtin_amdgcn_s_memrealtime();
   auto lap = [&](int which) {

@@ -106,7 +106,7 @@ void options_default(stmf_options* o) {
   o->init_hi = 100.0f;
   o->acol_p = 5;
   o->noop_rule = 1;
-  o->batch_first = 16;
+  o->batch_first = 0;
   o->batch_max = TMAX;
 }
 
@@ -116,7 +116,7 @@ static int check_options(const stmf_options& o) {
   if (o.init_mode == 0 && !(o.init_hi >= o.init_lo)) return STMF_EINVAL;
   if (o.init_mode == 1 && o.acol_p < 1) return STMF_EINVAL;
   if (o.count_scope < 0 || o.count_scope > 1) return STMF_EINVAL;
-  if (o.batch_first < 1 || o.batch_max < 1 || o.batch_max > TMAX) return STMF_EINVAL;
+  if (o.batch_first < 0 || o.batch_max < 1 || o.batch_max > TMAX) return STMF_EINVAL;
   if (o.group_size < 0 || o.log_cap < 0 || o.max_row_visits < 0) return STMF_EINVAL;
   if (!(o.eps >= 0.0)) return STMF_EINVAL;
   return STMF_OK;
@@ -172,6 +172,19 @@ static void make_layout(int m, int n, int r, int iters, int G, int acol_p, Layou
   L.total = o;
 }
 
+// First batch of a row visit when the caller leaves it to the library: a
+// batch costs a fixed latency (barriers, staging) plus a per-trial part that
+// grows with the tiles each workgroup sweeps, so the first batch shrinks as
+// the workgroups' share of tiles grows: 512 / tiles per workgroup, a power of
+// two, at least 4.
+static int auto_batch_first(const Layout& L) {
+  const int tiles = L.nrt * L.nct;
+  const int per = (tiles + L.G - 1) / L.G;
+  int t = 4;
+  while (t * 2 <= TMAX / per && t * 2 <= TMAX) t *= 2;
+  return t;
+}
+
 static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int observed) {
   FitDev d;
   std::memset(&d, 0, sizeof(d));
@@ -180,7 +193,7 @@ static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int o
   d.iters = L.iters;
   d.noop_rule = o.noop_rule; d.count_scope = o.count_scope;
   d.tmax = o.batch_max;
-  d.t0 = std::min(o.batch_first, o.batch_max);
+  d.t0 = std::min(o.batch_first > 0 ? o.batch_first : auto_batch_first(L), o.batch_max);
   d.log_cap = o.decision_log ? o.log_cap : 0;
   d.eps = o.eps;
   d.omega = observed;
@@ -522,15 +535,15 @@ int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters
   HIPCHK(hipEventCreate(&ev1));
   HIPCHK(hipEventRecord(ev0, s));
   st = launch_fit_kernel((const FitDev*)(base + L.dev), 1, G, G, o.max_row_visits, nullptr, s);
-  if (st) { hipEventDestroy(ev0); hipEventDestroy(ev1); return st; }
+  if (st) { (void)hipEventDestroy(ev0); (void)hipEventDestroy(ev1); return st; }
   HIPCHK(hipEventRecord(ev1, s));
   FitCtl c;
   HIPCHK(hipMemcpyAsync(&c, base + L.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   float kms = 0.0f;
-  hipEventElapsedTime(&kms, ev0, ev1);
-  hipEventDestroy(ev0);
-  hipEventDestroy(ev1);
+  if (hipEventElapsedTime(&kms, ev0, ev1) != hipSuccess) kms = 0.0f;
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
   if (c.status == STMF_ETIMEOUT) return STMF_ETIMEOUT;
   if (c.status != 0) return STMF_EHIP;
   st = launch_output(L, base, U_out, V_out, s);

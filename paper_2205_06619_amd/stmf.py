@@ -328,3 +328,80 @@ def stmf_fit_batched(problems: Sequence[dict], restarts=1, opt: Optional[Options
                               ws.numel(), _stream(stream)), "stmf_fit_batched")
     statuses = [arr[p].status for p in range(len(problems))]
     return outs, statuses, info.as_dict()
+
+
+# ------------------------------------------------------------------ serving
+def stmf_job_footprint(m, n, rank, iters) -> int:
+    """Arena bytes one job of this shape holds from admission to retirement."""
+    return int(lib.stmf_job_footprint(m, n, rank, iters))
+
+
+class Engine:
+    """Handle of a continuous-batching engine (stmf_engine_create) and the
+    arena tensor it lives in."""
+
+    def __init__(self, handle, arena, max_slots, opt):
+        self.handle = handle
+        self.arena = arena
+        self.max_slots = max_slots
+        self.opt = opt
+        self.shapes = {}  # slot -> (m, n, rank, iters)
+
+
+def stmf_engine_create(arena_bytes: int, max_slots: int, opt: Optional[Options] = None,
+                       device=None, **kw) -> Engine:
+    """An engine over a fresh device arena of arena_bytes."""
+    opt = _opts(opt, kw)
+    arena = workspace(arena_bytes, device)
+    h = C.c_void_p()
+    _chk(lib.stmf_engine_create(_ptr(arena), arena.numel(), max_slots, C.byref(opt), C.byref(h)),
+         "stmf_engine_create")
+    return Engine(h, arena, max_slots, opt)
+
+
+def stmf_engine_destroy(eng: Engine):
+    if eng.handle:
+        lib.stmf_engine_destroy(eng.handle)
+        eng.handle = None
+
+
+def stmf_engine_admit(eng: Engine, R, M, rank, iters, seed=0, stream=None) -> Optional[int]:
+    """Admit a job; returns its slot, or None when no slot or arena room is
+    free (STMF_EBUSY).  Other errors raise."""
+    torch = _torch()
+    m, n = R.shape
+    _check(R, torch.float32, (m, n), "R"); _check(M, torch.uint8, (m, n), "M")
+    slot = C.c_int(-1)
+    s = lib.stmf_engine_admit(eng.handle, _ptr(R), _ptr(M), m, n, rank, iters, C.c_uint64(seed),
+                              C.byref(slot), _stream(stream))
+    if s == STMF_EBUSY:
+        return None
+    _chk(s, "stmf_engine_admit")
+    eng.shapes[slot.value] = (m, n, rank, iters)
+    return slot.value
+
+
+def stmf_batch_tick(eng: Engine, max_rows: int, stream=None):
+    """Advance every resident job by at most max_rows row visits (one launch)."""
+    _chk(lib.stmf_batch_tick(eng.handle, max_rows, _stream(stream)), "stmf_batch_tick")
+
+
+def stmf_engine_poll(eng: Engine, slot: int, stream=None) -> bool:
+    done = C.c_int(0)
+    _chk(lib.stmf_engine_poll(eng.handle, slot, C.byref(done), _stream(stream)), "stmf_engine_poll")
+    return bool(done.value)
+
+
+def stmf_engine_retire(eng: Engine, slot: int, stream=None) -> FitResult:
+    """Results of a finished job (U, V on the device, host trajectory); frees
+    its slot and arena memory."""
+    torch = _torch()
+    m, n, rank, iters = eng.shapes[slot]
+    U = torch.empty((m, rank), dtype=torch.float32, device=eng.arena.device)
+    V = torch.empty((rank, n), dtype=torch.float32, device=eng.arena.device)
+    traj = np.zeros(iters + 1, np.float64)
+    info = FitInfo()
+    _chk(lib.stmf_engine_retire(eng.handle, slot, _ptr(U), _ptr(V), traj.ctypes.data_as(C.c_void_p),
+                                C.byref(info), _stream(stream)), "stmf_engine_retire")
+    del eng.shapes[slot]
+    return FitResult(U, V, traj, info.as_dict())

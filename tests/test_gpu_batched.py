@@ -1,0 +1,115 @@
+"""GPU tests of the batched path (stmf_fit_batched): many fits of uneven shape
+and several restarts in one persistent launch.  Batching changes where a fit
+runs, never its arithmetic: every fit equals stmf_fit alone with
+group_size=1 and the restart's seed, bit for bit (integer and real data),
+and on integer data equals the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2205_06619_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2205_06619_amd import stmf
+    return stmf
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _problems(integer, count, seed):
+    return synth.batched_problems(count, seed=seed, integer=integer, m_range=(12, 110),
+                                  n_range=(12, 150), r_range=(2, 5), miss_range=(0.2, 0.6))
+
+
+def _restart_seeds(seed, restarts):
+    # one restart: the problem's seed; several: SplitMix64 outputs of it
+    if restarts == 1:
+        return [seed]
+    return [int(x) for x in oracle.splitmix64(seed, restarts)]
+
+
+def _dev(probs, iters):
+    return [dict(R=_t(p.R), M=_t(p.M), rank=p.rank, iters=iters, seed=1000 + p.pid) for p in probs]
+
+
+@pytest.mark.parametrize("integer", [True, False])
+def test_batched_equals_plain_group1(S, integer):
+    print(f"batched vs plain integer={integer}", flush=True)
+    probs = _problems(integer, 6, seed=40 + int(integer))
+    iters, restarts = 3, 2
+    dev = _dev(probs, iters)
+    outs, statuses, info = S.stmf_fit_batched(dev, restarts=restarts)
+    assert statuses == [0] * len(probs)
+    total_trials = 0
+    for p, d, (U, V, T) in zip(probs, dev, outs):
+        for q, sd in enumerate(_restart_seeds(d["seed"], restarts)):
+            g = S.stmf_fit(d["R"], d["M"], p.rank, iters, seed=sd, group_size=1)
+            total_trials += g.info["trials"]
+            np.testing.assert_array_equal(U[q].cpu().numpy(), g.U.cpu().numpy())
+            np.testing.assert_array_equal(V[q].cpu().numpy(), g.V.cpu().numpy())
+            np.testing.assert_array_equal(T[q].cpu().numpy(), g.traj)
+    assert info["trials"] == total_trials
+
+
+def test_batched_integer_matches_oracle(S):
+    print("batched integer vs oracle", flush=True)
+    probs = _problems(True, 4, seed=47)
+    iters, restarts = 2, 2
+    dev = _dev(probs, iters)
+    outs, statuses, _ = S.stmf_fit_batched(dev, restarts=restarts, integer_exact=1)
+    assert statuses == [0] * len(probs)
+    for p, d, (U, V, T) in zip(probs, dev, outs):
+        for q, sd in enumerate(_restart_seeds(d["seed"], restarts)):
+            o = oracle.fit(p.R, p.M, p.rank, iters, seed=sd, prec="f32")
+            assert o.status == 0
+            np.testing.assert_array_equal(U[q].cpu().numpy(), o.U)
+            np.testing.assert_array_equal(V[q].cpu().numpy(), o.V)
+            np.testing.assert_array_equal(T[q].cpu().numpy(), o.traj)
+
+
+def test_batched_single_restart_uses_problem_seed(S):
+    print("batched one restart", flush=True)
+    probs = _problems(True, 3, seed=49)
+    dev = _dev(probs, 2)
+    outs, statuses, _ = S.stmf_fit_batched(dev, restarts=1)
+    assert statuses == [0, 0, 0]
+    for p, d, (U, V, T) in zip(probs, dev, outs):
+        g = S.stmf_fit(d["R"], d["M"], p.rank, 2, seed=d["seed"], group_size=1)
+        np.testing.assert_array_equal(U[0].cpu().numpy(), g.U.cpu().numpy())
+        np.testing.assert_array_equal(T[0].cpu().numpy(), g.traj)
+
+
+def test_batched_bad_problem_is_isolated(S):
+    print("batched bad problem", flush=True)
+    probs = _problems(True, 3, seed=48)
+    dev = _dev(probs, 2)
+    Mbad = probs[1].M.copy()
+    Mbad[0, :] = 0  # an empty row
+    dev[1]["M"] = _t(Mbad)
+    outs, statuses, _ = S.stmf_fit_batched(dev, restarts=2)
+    assert statuses[1] == S.STMF_EEMPTY_LINE
+    assert statuses[0] == 0 and statuses[2] == 0
+    for idx in (0, 2):
+        p, d = probs[idx], dev[idx]
+        sd = _restart_seeds(d["seed"], 2)[1]
+        g = S.stmf_fit(d["R"], d["M"], p.rank, 2, seed=sd, group_size=1)
+        np.testing.assert_array_equal(outs[idx][0][1].cpu().numpy(), g.U.cpu().numpy())
+
+
+def test_batched_rejects_bad_arguments(S):
+    print("batched arguments", flush=True)
+    probs = _problems(True, 1, seed=50)
+    dev = _dev(probs, 1)
+    with pytest.raises(S.StmfError):
+        S.stmf_fit_batched(dev, restarts=0)
+    with pytest.raises(S.StmfError):
+        S.stmf_fit_batched(dev, restarts=1, max_row_visits=3)

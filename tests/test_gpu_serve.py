@@ -1,0 +1,142 @@
+"""GPU tests of serving: the continuous-batching engine (admit / tick / poll /
+retire) and the serving loop over it.  A job's arithmetic never depends on
+which other jobs share its launches or when it was admitted: each result
+equals stmf_fit alone with group_size=1 and the same seed, bit for bit, on
+real-valued data."""
+import numpy as np
+import pytest
+
+from paper_2205_06619_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2205_06619_amd import stmf
+    return stmf
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _jobs(seed, count):
+    probs = synth.batched_problems(count, seed=seed, integer=False, m_range=(16, 90),
+                                   n_range=(16, 140), r_range=(2, 4), miss_range=(0.2, 0.6))
+    return [dict(R=_t(p.R), M=_t(p.M), rank=p.rank, iters=3, seed=700 + p.pid) for p in probs]
+
+
+def _alone(S, j):
+    return S.stmf_fit(j["R"], j["M"], j["rank"], j["iters"], seed=j["seed"], group_size=1)
+
+
+def _same(res, ref):
+    np.testing.assert_array_equal(res.U.cpu().numpy(), ref.U.cpu().numpy())
+    np.testing.assert_array_equal(res.V.cpu().numpy(), ref.V.cpu().numpy())
+    np.testing.assert_array_equal(res.traj, ref.traj)
+
+
+def _drain(S, eng, slots, rows, limit=10000):
+    out = {}
+    for _ in range(limit):
+        if len(out) == len(slots):
+            return out
+        S.stmf_batch_tick(eng, rows)
+        for s in slots:
+            if s not in out and S.stmf_engine_poll(eng, s):
+                out[s] = S.stmf_engine_retire(eng, s)
+    raise AssertionError("jobs did not finish")
+
+
+def test_engine_results_equal_plain(S):
+    print("engine vs plain", flush=True)
+    jobs = _jobs(60, 4)
+    eng = S.stmf_engine_create(256 << 20, 8)
+    try:
+        slots = [S.stmf_engine_admit(eng, j["R"], j["M"], j["rank"], j["iters"], j["seed"]) for j in jobs]
+        assert None not in slots and len(set(slots)) == len(slots)
+        res = _drain(S, eng, slots, rows=5)
+    finally:
+        S.stmf_engine_destroy(eng)
+    for j, s in zip(jobs, slots):
+        _same(res[s], _alone(S, j))
+
+
+def test_engine_alone_vs_mix(S):
+    print("engine alone vs mix", flush=True)
+    jobs = _jobs(61, 4)
+    x = jobs[0]
+    eng = S.stmf_engine_create(256 << 20, 8)
+    try:
+        sx = S.stmf_engine_admit(eng, x["R"], x["M"], x["rank"], x["iters"], x["seed"])
+        alone = _drain(S, eng, [sx], rows=3)[sx]
+        # the same job admitted into a running mix, after two ticks of the others
+        others = [S.stmf_engine_admit(eng, j["R"], j["M"], j["rank"], j["iters"], j["seed"])
+                  for j in jobs[1:]]
+        S.stmf_batch_tick(eng, 2)
+        S.stmf_batch_tick(eng, 2)
+        sx2 = S.stmf_engine_admit(eng, x["R"], x["M"], x["rank"], x["iters"], x["seed"])
+        mix = _drain(S, eng, others + [sx2], rows=3)
+    finally:
+        S.stmf_engine_destroy(eng)
+    _same(mix[sx2], alone)
+    _same(alone, _alone(S, x))
+    for j, s in zip(jobs[1:], others):
+        _same(mix[s], _alone(S, j))
+
+
+def test_engine_admission_by_footprint(S):
+    print("engine admission", flush=True)
+    j = _jobs(62, 1)[0]
+    m, n = j["R"].shape
+    fp = S.stmf_job_footprint(m, n, j["rank"], j["iters"])
+    assert fp > 0
+    # room for one job, not two
+    eng = S.stmf_engine_create(65536 + fp + fp // 2, 4)
+    try:
+        s1 = S.stmf_engine_admit(eng, j["R"], j["M"], j["rank"], j["iters"], j["seed"])
+        assert s1 is not None
+        assert S.stmf_engine_admit(eng, j["R"], j["M"], j["rank"], j["iters"], j["seed"]) is None
+        r1 = _drain(S, eng, [s1], rows=4)[s1]
+        s2 = S.stmf_engine_admit(eng, j["R"], j["M"], j["rank"], j["iters"], j["seed"])
+        assert s2 is not None
+        r2 = _drain(S, eng, [s2], rows=4)[s2]
+    finally:
+        S.stmf_engine_destroy(eng)
+    _same(r1, r2)
+
+
+def test_engine_slot_limit(S):
+    print("engine slots", flush=True)
+    jobs = _jobs(63, 3)
+    eng = S.stmf_engine_create(256 << 20, 2)
+    try:
+        a = S.stmf_engine_admit(eng, jobs[0]["R"], jobs[0]["M"], jobs[0]["rank"], 2, 1)
+        b = S.stmf_engine_admit(eng, jobs[1]["R"], jobs[1]["M"], jobs[1]["rank"], 2, 2)
+        assert a is not None and b is not None
+        assert S.stmf_engine_admit(eng, jobs[2]["R"], jobs[2]["M"], jobs[2]["rank"], 2, 3) is None
+        _drain(S, eng, [a, b], rows=50)
+    finally:
+        S.stmf_engine_destroy(eng)
+
+
+def test_serve_loop_results_match_alone(S):
+    print("serve loop", flush=True)
+    from paper_2205_06619_amd import serve
+    jobs = serve.synthetic_jobs(8, rate_per_s=200.0, seed=64, m_range=(16, 80), n_range=(16, 120),
+                                r_range=(2, 4), miss_range=(0.2, 0.6), iters=3)
+    backend = serve.EngineBackend(256 << 20, 8)
+    try:
+        st = serve.Server(backend, rows_per_tick=4).run(jobs)
+    finally:
+        backend.close()
+    assert st.jobs == 8 and 0 < st.p50_ms <= st.p99_ms
+    assert st.max_resident >= 1 and st.ticks >= 1
+    for j in jobs:
+        assert j.finished >= j.arrival
+        ref = S.stmf_fit(j.R, j.M, j.rank, j.iters, seed=j.seed, group_size=1)
+        _same(j.result, ref)
