@@ -47,6 +47,7 @@ static constexpr unsigned long long BARRIER_TIMEOUT = 400000000ull;  // 4 s at 1
 static constexpr int ST_TIMEOUT = 7;
 static constexpr int RPW = TS / NWAVE;  // tile rows (or columns) per wave
 static constexpr int CQ_CAP = NTHR + CW + 128;
+static constexpr int KB = 8;            // components whose summaries are staged together
 
 DEV unsigned fmap(float f) {
   unsigned u = __float_as_uint(f);
@@ -129,8 +130,8 @@ struct BatchScratch {
     EvalVectors e;           // error pass
     float sX[2 * TCH][TS];   // residual pass: the one vector each trial needs
   } v;
-  double epl[TCH][2][TS / 2];  // error pass: per staged trial, row half and lane
-                               // pair, partial error
+  double epl[TCH][2][TS / 4];  // error pass: per staged trial, row half and lane
+                               // quad, partial error
 };
 struct RefreshScratch {
   int hc[TS][RMAX];          // argmax histogram of the tile columns
@@ -166,14 +167,14 @@ struct Smem {
   double wsum[TMAX];         // per trial: this workgroup's partial error
   Trial trials[TMAX];
   int noops_before[TMAX];    // no-op skips preceding each trial in the batch
-  int byk[TMAX];             // trial indices grouped by (component, operation)
-  int gstart[2 * RMAX + 1];  // group g: byk[gstart[g] .. gstart[g + 1])
-  int ng;                    // groups of the batch
-  int nop[2];                // F-ULF and F-URF trials of the batch
-  int wk[NWAVE][2 * RMAX];   // per wave and group key: trial count, then offset
+  int byk[TMAX];             // trial indices by key op * RMAX + k (stable)
+  int kst[2 * RMAX + 1];     // key q: byk[kst[q] .. kst[q + 1])
+  int wk[NWAVE][2 * RMAX];   // per wave and key: trial count, then offset
   float Ri[TS];              // R of the visited row at the tile columns
-  float colbase[TS];         // F-ULF: column residual of U_.k without row i
-  Top2 rtop[TS];             // F-URF: row residual summaries of component k
+  // summaries of a block of up to KB components (kb0, kb0 + 1, ...) at the tile
+  float colb[KB][TS];        // F-ULF: column residual without row i, excl(colst_kc, i)
+  float rm1[KB][TS], rm2[KB][TS];
+  int ra1[KB][TS];           // F-URF: row residual summaries (m1, a1, m2) of the tile rows
   float urow_i[RMAX];        // U of the visited row, every component
   int closed_s[RMAX];        // closed flags at the start of the row visit
   int crow_i[RMAX];          // argmax counts of the visited row
@@ -203,6 +204,7 @@ static_assert(sizeof(Smem) <= 160 * 1024, "LDS layout exceeds a CU's 160 KB");
 static_assert(TMAX <= NTHR && 2 * CW <= NTHR && CW * 4 <= NTHR, "one thread per trial / pair");
 static_assert(RMAX == 64, "one lane per component (two group keys) in the batch grouping");
 static_assert(TCH * 8 == NTHR, "eight threads per staged trial in the error reduction");
+static_assert(KB * TS == NTHR, "one thread per staged summary");
 
 struct Grp {
   const FitDev* d;
@@ -335,7 +337,8 @@ DEV void compute_pnotk(Grp& gp, Smem& S, int k) {
 
 // ------------------------------------------------------------ trial staging
 // The first residual of a trial, restricted to a tile, from data staged once
-// per tile and component (every trial of a batch shares the visited row i):
+// per tile and block of components (every trial of a batch shares the
+// visited row i):
 //   F-ULF, tile column x: V'_kc = min(excl(colst_kc, i), R_ic - u)
 //   F-URF, tile row x:    U'_tk = min(excl(rowst_kt, j), R_tj - v)
 // Padding rows and columns take 0.
@@ -343,80 +346,49 @@ DEV void stage_ri(Grp& gp, Smem& S, int i, int c0) {
   const FitDev& d = *gp.d;
   if (gp.tid < TS) S.Ri[gp.tid] = d.Rw[(size_t)i * d.ldn + c0 + gp.tid];
 }
-DEV void stage_comp(Grp& gp, Smem& S, int op, int k, int r0, int c0, int i) {
-  const FitDev& d = *gp.d;
-  if (gp.tid < TS) {
-    if (op == OP_ULF) S.colbase[gp.tid] = excl(ld_top2(&d.colst[(size_t)k * d.ldn + c0 + gp.tid]), i);
-    else if (op == OP_URF) S.rtop[gp.tid] = ld_top2(&d.rowst[(size_t)k * d.ldm + r0 + gp.tid]);
-  }
-}
 
-// Vectors of the cn trials byk[cs ..] at the tile: wave w stages trials w,
-// w + NWAVE, ... (lane = tile row or column), NE at most; every global load
-// is issued before any element is written to LDS.
-template <int NE>
-DEV void stage_ulf_cols(Grp& gp, Smem& S, int cs, int cn, int c0, float (*out)[TS]) {
+// Summaries of components kb0 .. kb0 + nb - 1 (nb <= KB) at the tile, one
+// thread per component and tile index, all loads in one round: the column
+// summaries without row i (cols) and the row summaries (rows).
+DEV void stage_block(Grp& gp, Smem& S, int kb0, int nb, bool cols, bool rows, int r0, int c0,
+                     int i) {
   const FitDev& d = *gp.d;
-  const int x = gp.lane;
-  const bool in = c0 + x < d.n;
-  const float cb = S.colbase[x], ri = S.Ri[x];
-#pragma unroll
-  for (int m = 0; m < NE; ++m) {
-    const int sl = gp.wave + m * NWAVE;
-    if (sl < cn) out[sl][x] = in ? vmin(cb, ri - S.trials[S.byk[cs + sl]].val) : 0.0f;
-  }
-}
-template <int NE>
-DEV void stage_urf_rows(Grp& gp, Smem& S, int cs, int cn, int r0, float (*out)[TS]) {
-  const FitDev& d = *gp.d;
-  const int x = gp.lane;
-  float raw[NE];
-#pragma unroll
-  for (int m = 0; m < NE; ++m) {
-    const int sl = gp.wave + m * NWAVE;
-    if (sl < cn) raw[m] = d.RwT[(size_t)S.trials[S.byk[cs + sl]].j * d.ldm + r0 + x];
-  }
-  const bool in = r0 + x < d.m;
-  const Top2 rt = S.rtop[x];
-#pragma unroll
-  for (int m = 0; m < NE; ++m) {
-    const int sl = gp.wave + m * NWAVE;
-    if (sl < cn) {
-      const Trial& tr = S.trials[S.byk[cs + sl]];
-      out[sl][x] = in ? vmin(excl(rt, tr.j), raw[m] - tr.val) : 0.0f;
+  const int b = gp.tid / TS, x = gp.tid % TS;
+  if (b < nb) {
+    if (cols) S.colb[b][x] = excl(ld_top2(&d.colst[(size_t)(kb0 + b) * d.ldn + c0 + x]), i);
+    if (rows) {
+      const Top2 t = ld_top2(&d.rowst[(size_t)(kb0 + b) * d.ldm + r0 + x]);
+      S.rm1[b][x] = t.m1;
+      S.ra1[b][x] = t.a1;
+      S.rm2[b][x] = t.m2;
     }
   }
 }
-// Second residuals of the staged trials (the atomic-min targets) at working
-// indices base + lane, valid below lim.
-template <int NE>
-DEV void stage_second(Grp& gp, Smem& S, int par, int cs, int cn, int base, int lim, float (*out)[TS]) {
-  const FitDev& d = *gp.d;
-  const int x = gp.lane;
-  unsigned raw[NE];
-#pragma unroll
-  for (int m = 0; m < NE; ++m) {
-    const int sl = gp.wave + m * NWAVE;
-    if (sl < cn) raw[m] = ld_atomic(&d.tvec[((size_t)par * TMAX + S.byk[cs + sl]) * d.ldmax + base + x]);
-  }
-  const bool in = base + x < lim;
-#pragma unroll
-  for (int m = 0; m < NE; ++m) {
-    const int sl = gp.wave + m * NWAVE;
-    if (sl < cn) out[sl][x] = in ? funmap(raw[m]) : 0.0f;
-  }
+
+// Position p of a trial list made of two byk ranges [a0, a0 + n0) and
+// [a1, ...): the trial index.
+DEV int list_at(const Smem& S, int p, int a0, int n0, int a1) {
+  return S.byk[p < n0 ? a0 + p : a1 + p - n0];
+}
+
+// Second residual of trial q (its atomic-min target) at working index idx.
+DEV unsigned ld_second(const FitDev& d, int par, int q, int idx) {
+  return ld_atomic(&d.tvec[((size_t)par * TMAX + q) * d.ldmax + idx]);
 }
 
 // ------------------------------------------------------------ pass 1 of a batch
 // Second residual of every trial over this workgroup's tiles, combined across
 // tiles with an atomic min on order-preserving integer images (exact).  The
 // F-ULF trials come first (lanes over the tile rows, the tile's R rows in
-// registers), then the F-URF trials (lanes over the tile columns); each trial
-// stages the one first-residual vector it needs, 2 * TCH trials at a time.
+// registers), then the F-URF trials (lanes over the tile columns).  Per block
+// of components the summaries are staged once; each trial then stages the
+// one first-residual vector it needs, 2 * TCH trials at a time (wave w takes
+// trials w, w + NWAVE, ...), every global load issued before any is used.
 DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
   const FitDev& d = *gp.d;
   const int ntile = d.nrt * d.nct;
   constexpr int NE = 2 * TCH / NWAVE;
+  const int x = gp.lane;
   for (int tile = gp.g; tile < ntile; tile += gp.G) {
     const int rt = tile / d.nct, ct = tile % d.nct;
     const int r0 = rt * TS, c0 = ct * TS;
@@ -426,27 +398,54 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
     for (int side = 0; side < 2; ++side) {
       // side 0, F-ULF: U''_tk = min over the tile columns of R_tc - V'_kc
       // side 1, F-URF: V''_kc = min over the tile rows of R_tc - U'_tk
-      if (S.nop[side] == 0) continue;
+      if (S.kst[side * RMAX + d.r] == S.kst[side * RMAX]) continue;
       const GA float* rb = side ? d.Rw + (size_t)r0 * d.ldn + c0 + gp.lane
                                 : d.RwT + (size_t)c0 * d.ldm + r0 + gp.lane;
       const size_t rs = side ? (size_t)d.ldn : (size_t)d.ldm;
       float Rv[TS];
 #pragma unroll
-      for (int x = 0; x < TS; ++x) Rv[x] = rb[x * rs];
+      for (int y = 0; y < TS; ++y) Rv[y] = rb[y * rs];
       const int own = (side ? c0 : r0) + gp.lane;
+      const bool in = side ? r0 + x < d.m : c0 + x < d.n;
 #pragma unroll 1
-      for (int g = 0; g < S.ng; ++g) {
-        const int gb = S.gstart[g], ge = S.gstart[g + 1];
-        const Trial t0 = S.trials[S.byk[gb]];
-        if (t0.op != side) continue;
+      for (int kb0 = 0; kb0 < d.r; kb0 += KB) {
+        const int nb = d.r - kb0 < KB ? d.r - kb0 : KB;
+        const int lo = S.kst[side * RMAX + kb0], hi = S.kst[side * RMAX + kb0 + nb];
+        if (lo == hi) continue;
         __syncthreads();
-        stage_comp(gp, S, side, t0.k, r0, c0, i);
+        stage_block(gp, S, kb0, nb, side == 0, side == 1, r0, c0, i);
 #pragma unroll 1
-        for (int cs = gb; cs < ge; cs += 2 * TCH) {
-          const int cn = ge - cs < 2 * TCH ? ge - cs : 2 * TCH;
+        for (int cs = lo; cs < hi; cs += 2 * TCH) {
+          const int cn = hi - cs < 2 * TCH ? hi - cs : 2 * TCH;
           __syncthreads();
-          if (side) stage_urf_rows<NE>(gp, S, cs, cn, r0, S.u.b.v.sX);
-          else stage_ulf_cols<NE>(gp, S, cs, cn, c0, S.u.b.v.sX);
+          if (side == 0) {
+            const float ri = S.Ri[x];
+#pragma unroll
+            for (int m = 0; m < NE; ++m) {
+              const int sl = gp.wave + m * NWAVE;
+              if (sl < cn) {
+                const Trial& tr = S.trials[S.byk[cs + sl]];
+                S.u.b.v.sX[sl][x] = in ? vmin(S.colb[tr.k - kb0][x], ri - tr.val) : 0.0f;
+              }
+            }
+          } else {
+            float raw[NE];
+#pragma unroll
+            for (int m = 0; m < NE; ++m) {
+              const int sl = gp.wave + m * NWAVE;
+              if (sl < cn) raw[m] = d.RwT[(size_t)S.trials[S.byk[cs + sl]].j * d.ldm + r0 + x];
+            }
+#pragma unroll
+            for (int m = 0; m < NE; ++m) {
+              const int sl = gp.wave + m * NWAVE;
+              if (sl < cn) {
+                const Trial& tr = S.trials[S.byk[cs + sl]];
+                const int b = tr.k - kb0;
+                const float ex = S.ra1[b][x] == tr.j ? S.rm2[b][x] : S.rm1[b][x];
+                S.u.b.v.sX[sl][x] = in ? vmin(ex, raw[m] - tr.val) : 0.0f;
+              }
+            }
+          }
           __syncthreads();
 #pragma unroll 1
           for (int sl = gp.wave; sl < cn; sl += NWAVE) {
@@ -461,12 +460,10 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
               x2 = vmin(vmin(x2, Rv[c + 4] - s2.x), Rv[c + 5] - s2.y);
               x3 = vmin(vmin(x3, Rv[c + 6] - s2.z), Rv[c + 7] - s2.w);
             }
-            const float x = vmin(vmin(x0, x1), vmin(x2, x3));
+            const float xm = vmin(vmin(x0, x1), vmin(x2, x3));
             // +inf: no observed cell of this row (column) in the tile
-            if (x != FINF) {
-              const int q = S.byk[cs + sl];
-              atomic_min_g(&d.tvec[((size_t)par * TMAX + q) * d.ldmax + own], fmap(x));
-            }
+            if (xm != FINF)
+              atomic_min_g(&d.tvec[((size_t)par * TMAX + S.byk[cs + sl]) * d.ldmax + own], fmap(xm));
           }
         }
       }
@@ -475,23 +472,26 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
 }
 
 // ------------------------------------------------------------ pass 2 of a batch
-// b-norm of every trial over this workgroup's tiles.  Trials come in groups of
-// one component and operation (S.byk); per tile and component the product
-// without k is formed once.  Wave w takes the tile rows of half w & 1 (lane =
-// tile column) for the staged trials (w >> 1), (w >> 1) + 4, ..., holding that
-// half's R and product without k in registers.  Per lane and trial the
-// half-column sum runs over its 32 rows in four interleaved FP64
-// accumulators; lane pairs are added, and the 64 pair sums of a trial are
-// added in a fixed tree; the tile's sum is added to the workgroup's per-trial
-// sum in tile order.
-DEV double pair_sum(double v) {
-  // lanes 2m and 2m + 1 exchange (quad permutation 1, 0, 3, 2) and add: both
-  // get the same sum
-  const unsigned long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0xB1, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0xB1, 0xF, 0xF, false);
-  return v + __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+// b-norm of every trial over this workgroup's tiles, component by component
+// (the F-ULF and F-URF trials of component k together); per tile and
+// component the product without k is formed once.  Wave w takes the tile
+// rows of half w & 1 (lane = tile column) for the staged trials (w >> 1),
+// (w >> 1) + 4, ..., holding that half's R and product without k in
+// registers.  Per lane and trial the half-column sum runs over its 32 rows in
+// four interleaved FP64 accumulators; lane quads are added, and the 32 quad
+// sums of a trial are added in a fixed tree; the tile's sum is added to the
+// workgroup's per-trial sum in tile order.
+// One quad-permutation exchange (DPP control CTRL) of a double, added.
+template <int CTRL>
+DEV double dpp_add(double a) {
+  const unsigned long long b = __double_as_longlong(a);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return a + __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
+// Lanes exchange within quads (permutations 1, 0, 3, 2 then 2, 3, 0, 1) and
+// add: the four lanes end with the same sum.
+DEV double quad_sum(double v) { return dpp_add<0x4E>(dpp_add<0xB1>(v)); }
 
 DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
   const FitDev& d = *gp.d;
@@ -500,9 +500,11 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
   for (int q = gp.tid; q < nt; q += NTHR) S.wsum[q] = 0.0;
   const int ntile = d.nrt * d.nct;
   const int half = gp.wave & 1, h0 = half * (TS / 2);
+  const int x = gp.lane;
   for (int tile = gp.g; tile < ntile; tile += gp.G) {
     const int rt = tile / d.nct, ct = tile % d.nct;
     const int r0 = rt * TS, c0 = ct * TS;
+    const bool rin = r0 + x < d.m, cin = c0 + x < d.n;
     __syncthreads();
     stage_uv(gp, S, r0, c0);
     stage_ri(gp, S, i, c0);
@@ -516,36 +518,69 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
       obs |= (unsigned)o << t;
       Rev[t] = o ? rv : FLT_MAX;
     }
-    int kcur = -1;
+    int kb0 = -KB;
 #pragma unroll 1
-    for (int g = 0; g < S.ng; ++g) {
-      const int gb = S.gstart[g], ge = S.gstart[g + 1];
-      const Trial t0 = S.trials[S.byk[gb]];
+    for (int k = 0; k < d.r; ++k) {
+      const int a0 = S.kst[k], n0 = S.kst[k + 1] - a0;
+      const int a1 = S.kst[RMAX + k], n1 = S.kst[RMAX + k + 1] - a1;
+      const int ntk = n0 + n1;
+      if (ntk == 0) continue;
       __syncthreads();
-      if (t0.k != kcur) {
-        compute_pnotk(gp, S, t0.k);
-        __syncthreads();
-#pragma unroll
-        for (int t = 0; t < TS / 2; ++t) Pc[t] = ((obs >> t) & 1u) ? S.Ps[h0 + t][gp.lane] : FLT_MAX;
-        kcur = t0.k;
+      if (k >= kb0 + KB) {
+        kb0 = k;
+        stage_block(gp, S, kb0, d.r - kb0 < KB ? d.r - kb0 : KB, true, true, r0, c0, i);
       }
-      stage_comp(gp, S, t0.op, t0.k, r0, c0, i);
+      compute_pnotk(gp, S, k);
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < TS / 2; ++t) Pc[t] = ((obs >> t) & 1u) ? S.Ps[h0 + t][gp.lane] : FLT_MAX;
+      const int b = k - kb0;
 #pragma unroll 1
-      for (int cs = gb; cs < ge; cs += TCH) {
-        const int cn = ge - cs < TCH ? ge - cs : TCH;
+      for (int cs = 0; cs < ntk; cs += TCH) {
+        const int cn = ntk - cs < TCH ? ntk - cs : TCH;
         __syncthreads();
-        if (t0.op == OP_ULF) {
-          stage_second<NE>(gp, S, par, cs, cn, r0, d.m, S.u.b.v.e.sA);
-          stage_ulf_cols<NE>(gp, S, cs, cn, c0, S.u.b.v.e.sB);
-        } else if (t0.op == OP_URF) {
-          stage_urf_rows<NE>(gp, S, cs, cn, r0, S.u.b.v.e.sA);
-          stage_second<NE>(gp, S, par, cs, cn, c0, d.n, S.u.b.v.e.sB);
+        if (S.trials[list_at(S, cs, a0, n0, a1)].op == OP_NULL) {
+          // the null trial (always alone): the current component
+          if (gp.wave == 0) {
+            S.u.b.v.e.sA[0][x] = rin ? ld_atomic(&d.Uc[(size_t)k * d.ldm + r0 + x]) : 0.0f;
+            S.u.b.v.e.sB[0][x] = cin ? ld_atomic(&d.V[(size_t)k * d.ldn + c0 + x]) : 0.0f;
+          }
         } else {
-          // the null trial: the current component
-          for (int e = gp.tid; e < cn * TS; e += NTHR) {
-            const int sl = e / TS, x = e % TS;
-            S.u.b.v.e.sA[sl][x] = r0 + x < d.m ? ld_atomic(&d.Uc[(size_t)t0.k * d.ldm + r0 + x]) : 0.0f;
-            S.u.b.v.e.sB[sl][x] = c0 + x < d.n ? ld_atomic(&d.V[(size_t)t0.k * d.ldn + c0 + x]) : 0.0f;
+          // the trial's two vectors: the first residual from the staged
+          // summaries, the second from the residual pass (loads first)
+          float rawA[NE];
+          unsigned rawB[NE];
+#pragma unroll
+          for (int m = 0; m < NE; ++m) {
+            const int sl = gp.wave + m * NWAVE;
+            if (sl < cn) {
+              const int q = list_at(S, cs + sl, a0, n0, a1);
+              const Trial& tr = S.trials[q];
+              if (tr.op == OP_ULF) {
+                rawB[m] = ld_second(d, par, q, r0 + x);
+              } else {
+                rawA[m] = d.RwT[(size_t)tr.j * d.ldm + r0 + x];
+                rawB[m] = ld_second(d, par, q, c0 + x);
+              }
+            }
+          }
+#pragma unroll
+          for (int m = 0; m < NE; ++m) {
+            const int sl = gp.wave + m * NWAVE;
+            if (sl < cn) {
+              const Trial& tr = S.trials[list_at(S, cs + sl, a0, n0, a1)];
+              float va, vb;
+              if (tr.op == OP_ULF) {
+                va = funmap(rawB[m]);
+                vb = vmin(S.colb[b][x], S.Ri[x] - tr.val);
+              } else {
+                const float ex = S.ra1[b][x] == tr.j ? S.rm2[b][x] : S.rm1[b][x];
+                va = vmin(ex, rawA[m] - tr.val);
+                vb = funmap(rawB[m]);
+              }
+              S.u.b.v.e.sA[sl][x] = rin ? va : 0.0f;
+              S.u.b.v.e.sB[sl][x] = cin ? vb : 0.0f;
+            }
           }
         }
         __syncthreads();
@@ -553,7 +588,7 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
         for (int sl = gp.wave >> 1; sl < cn; sl += NWAVE / 2) {
           const float vs = S.u.b.v.e.sB[sl][gp.lane];
           const float4* sa = reinterpret_cast<const float4*>(&S.u.b.v.e.sA[sl][h0]);
-          double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+          double e0 = 0.0, e1 = 0.0, e2 = 0.0, e3 = 0.0;
 #pragma unroll
           for (int t4 = 0; t4 < TS / 8; ++t4) {
             const float4 s = sa[t4];
@@ -562,28 +597,28 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
             const float d1 = Rev[t + 1] - vmax(Pc[t + 1], s.y + vs);
             const float d2 = Rev[t + 2] - vmax(Pc[t + 2], s.z + vs);
             const float d3 = Rev[t + 3] - vmax(Pc[t + 3], s.w + vs);
-            a0 += fabs((double)d0);
-            a1 += fabs((double)d1);
-            a2 += fabs((double)d2);
-            a3 += fabs((double)d3);
+            e0 += fabs((double)d0);
+            e1 += fabs((double)d1);
+            e2 += fabs((double)d2);
+            e3 += fabs((double)d3);
           }
-          const double v = pair_sum((a0 + a1) + (a2 + a3));
-          if ((gp.lane & 1) == 0) S.u.b.epl[sl][half][gp.lane >> 1] = v;
+          const double v = quad_sum((e0 + e1) + (e2 + e3));
+          if ((gp.lane & 3) == 0) S.u.b.epl[sl][half][gp.lane >> 2] = v;
         }
         __syncthreads();
-        // per staged trial: eight threads add eight pair sums each (half 0
+        // per staged trial: eight threads add four quad sums each (half 0
         // first), then a fixed butterfly over the eight (all get the same sum)
         {
           const int sl = gp.tid >> 3, sub = gp.tid & 7;
           double s = 0.0;
           if (sl < cn) {
-            const double* p = &S.u.b.epl[sl][sub >> 2][(sub & 3) * 8];
-            s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+            const double* p = &S.u.b.epl[sl][sub >> 2][(sub & 3) * 4];
+            s = (p[0] + p[1]) + (p[2] + p[3]);
           }
           s += __shfl_xor(s, 1, 64);
           s += __shfl_xor(s, 2, 64);
           s += __shfl_xor(s, 4, 64);
-          if (sl < cn && sub == 0) S.wsum[S.byk[cs + sl]] += s;
+          if (sl < cn && sub == 0) S.wsum[list_at(S, cs + sl, a0, n0, a1)] += s;
         }
       }
     }
@@ -1106,66 +1141,55 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb) {
     __syncthreads();
   }
   if (gp.tid == 0) S.exhausted = (S.cq_n - S.cq_head) == 0 && S.ord_pos >= d.n;
-  // Group the trials for the two passes by key 2k + op (component-major,
-  // F-ULF before F-URF, stable within a group).  One thread per trial; ranks
-  // within a wave by ballot, offsets from per-wave counts by key.
+  // Group the trials for the two passes by key op * RMAX + k (operation-
+  // major, then component, stable within a key): S.byk and the key ranges
+  // S.kst.  One thread per trial; ranks within a wave by ballot, offsets from
+  // per-wave counts by key.
   {
     const int q = gp.tid;
     const bool valid = q < S.nt;
-    const int key = valid ? 2 * S.trials[q].k + S.trials[q].op : -1;
+    const int key = valid ? S.trials[q].op * RMAX + S.trials[q].k : -1;
     const unsigned long long below = (1ull << gp.lane) - 1ull;
     int rank = 0, c0 = 0, c1 = 0;  // rank among the wave's trials of the key;
-                                   // lane l: the wave's trials of keys 2l, 2l+1
+                                   // lane l: the wave's trials of keys l, RMAX + l
     unsigned long long rem = __ballot(valid);
     while (rem) {
       const int kl = __shfl(key, __ffsll((long long)rem) - 1, 64);
       const unsigned long long m = __ballot(valid && key == kl);
       if (valid && key == kl) rank = __popcll(m & below);
-      if (gp.lane == (kl >> 1)) {
-        if (kl & 1) c1 = __popcll(m); else c0 = __popcll(m);
+      if (gp.lane == kl % RMAX) {
+        if (kl >= RMAX) c1 = __popcll(m); else c0 = __popcll(m);
       }
       rem &= ~m;
     }
-    S.wk[gp.wave][2 * gp.lane] = c0;
-    S.wk[gp.wave][2 * gp.lane + 1] = c1;
+    S.wk[gp.wave][gp.lane] = c0;
+    S.wk[gp.wave][RMAX + gp.lane] = c1;
     __syncthreads();
     if (gp.wave == 0) {
-      // lane l: keys 2l and 2l + 1.  Group starts by an exclusive scan over
-      // the keys, then the start of every wave's share of each key.
+      // lane l: keys l and RMAX + l.  Key starts by exclusive scans over the
+      // keys (F-ULF keys first), then the start of every wave's share.
       int t0 = 0, t1 = 0;
-      for (int w = 0; w < NWAVE; ++w) { t0 += S.wk[w][2 * gp.lane]; t1 += S.wk[w][2 * gp.lane + 1]; }
-      // trials in the low bits, non-empty groups from bit 16
-      const int mine = (t0 + t1) | (((t0 > 0) + (t1 > 0)) << 16);
-      int incl = mine;
+      for (int w = 0; w < NWAVE; ++w) { t0 += S.wk[w][gp.lane]; t1 += S.wk[w][RMAX + gp.lane]; }
+      int i0 = t0, i1 = t1;
       for (int sft = 1; sft < 64; sft <<= 1) {
-        const int v = __shfl_up(incl, sft, 64);
-        if (gp.lane >= sft) incl += v;
+        const int v0 = __shfl_up(i0, sft, 64), v1 = __shfl_up(i1, sft, 64);
+        if (gp.lane >= sft) { i0 += v0; i1 += v1; }
       }
-      const int excl_sum = incl - mine;
-      int run = excl_sum & 0xFFFF, gpos = excl_sum >> 16;
-      if (t0 > 0) S.gstart[gpos++] = run;
-      if (t1 > 0) S.gstart[gpos] = run + t0;
-      if (gp.lane == 63) { S.ng = incl >> 16; S.gstart[incl >> 16] = incl & 0xFFFF; }
-      int r1 = run + t0;
+      const int nulf = __shfl(i0, 63, 64);
+      int run0 = i0 - t0, run1 = nulf + i1 - t1;
+      S.kst[gp.lane] = run0;
+      S.kst[RMAX + gp.lane] = run1;
+      if (gp.lane == 63) S.kst[2 * RMAX] = nulf + i1;
       for (int w = 0; w < NWAVE; ++w) {
-        const int a = S.wk[w][2 * gp.lane], b = S.wk[w][2 * gp.lane + 1];
-        S.wk[w][2 * gp.lane] = run;
-        S.wk[w][2 * gp.lane + 1] = r1;
-        run += a;
-        r1 += b;
+        const int a = S.wk[w][gp.lane], b = S.wk[w][RMAX + gp.lane];
+        S.wk[w][gp.lane] = run0;
+        S.wk[w][RMAX + gp.lane] = run1;
+        run0 += a;
+        run1 += b;
       }
     }
-    // operation counts (the ballot is taken by the whole wave)
-    const unsigned long long mu = __ballot(valid && (key & 1) == 0);
-    if (gp.lane == 0) S.wcount[gp.wave] = __popcll(mu);
     __syncthreads();
     if (valid) S.byk[S.wk[gp.wave][key] + rank] = q;
-    if (gp.tid == 0) {
-      int nu = 0;
-      for (int w = 0; w < NWAVE; ++w) nu += S.wcount[w];
-      S.nop[0] = nu;
-      S.nop[1] = S.nt - nu;
-    }
   }
   __syncthreads();
 }
@@ -1213,7 +1237,8 @@ DEV bool fit_init(Grp& gp, Smem& S) {
     if (!refresh(gp, S, k, nullptr, 0, 0, 0, k == d.r - 1, 0)) return false;
   if (gp.tid == 0) {
     Trial tr; tr.j = 0; tr.k = 0; tr.op = OP_NULL; tr.val = 0.0f;
-    S.trials[0] = tr; S.nt = 1; S.ng = 1; S.gstart[0] = 0; S.gstart[1] = 1;
+    S.trials[0] = tr; S.nt = 1;
+    for (int q = 0; q <= 2 * RMAX; ++q) S.kst[q] = q == 0 ? 0 : 1;  // key 0: the null trial
     S.byk[0] = 0; S.prev_nt = 0;
   }
   __syncthreads();
