@@ -130,8 +130,8 @@ struct BatchScratch {
     EvalVectors e;           // error pass
     float sX[2 * TCH][TS];   // residual pass: the one vector each trial needs
   } v;
-  double epl[TCH][2][TS / 4];  // error pass: per staged trial, row half and lane
-                               // quad, partial error
+  double epl[TCH][2][4];     // error pass: per staged trial, row half and 16-lane
+                             // row, partial error
 };
 struct RefreshScratch {
   int hc[TS][RMAX];          // argmax histogram of the tile columns
@@ -203,7 +203,7 @@ struct Smem {
 static_assert(sizeof(Smem) <= 160 * 1024, "LDS layout exceeds a CU's 160 KB");
 static_assert(TMAX <= NTHR && 2 * CW <= NTHR && CW * 4 <= NTHR, "one thread per trial / pair");
 static_assert(RMAX == 64, "one lane per component (two group keys) in the batch grouping");
-static_assert(TCH * 8 == NTHR, "eight threads per staged trial in the error reduction");
+static_assert(TCH <= NTHR, "one thread per staged trial in the error reduction");
 static_assert(KB * TS == NTHR, "one thread per staged summary");
 
 struct Grp {
@@ -308,11 +308,17 @@ DEV float col_side(const FitDev& d, const Trial& tr, int par, int slot, int c, i
 // U of the tile rows and V of the tile columns for every component, staged in
 // LDS in one round of independent loads.
 DEV void stage_uv(Grp& gp, Smem& S, int r0, int c0) {
+  // descriptor fields are read once: a device-coherent access makes the
+  // compiler reload anything it would read from memory after it
   const FitDev& d = *gp.d;
-  for (int e = gp.tid; e < d.r * TS; e += NTHR) {
+  const auto Uc = d.Uc;
+  const auto V = d.V;
+  const size_t ldm = d.ldm, ldn = d.ldn;
+  const int ne = d.r * TS;
+  for (int e = gp.tid; e < ne; e += NTHR) {
     const int l = e / TS, x = e % TS;
-    S.Ut[l][x] = ld_atomic(&d.Uc[(size_t)l * d.ldm + r0 + x]);
-    S.Vt[l][x] = ld_atomic(&d.V[(size_t)l * d.ldn + c0 + x]);
+    S.Ut[l][x] = ld_atomic(&Uc[l * ldm + r0 + x]);
+    S.Vt[l][x] = ld_atomic(&V[l * ldn + c0 + x]);
   }
 }
 
@@ -353,11 +359,14 @@ DEV void stage_ri(Grp& gp, Smem& S, int i, int c0) {
 DEV void stage_block(Grp& gp, Smem& S, int kb0, int nb, bool cols, bool rows, int r0, int c0,
                      int i) {
   const FitDev& d = *gp.d;
+  const auto colst = d.colst;
+  const auto rowst = d.rowst;
+  const size_t ldm = d.ldm, ldn = d.ldn;
   const int b = gp.tid / TS, x = gp.tid % TS;
   if (b < nb) {
-    if (cols) S.colb[b][x] = excl(ld_top2(&d.colst[(size_t)(kb0 + b) * d.ldn + c0 + x]), i);
+    if (cols) S.colb[b][x] = excl(ld_top2(&colst[(kb0 + b) * ldn + c0 + x]), i);
     if (rows) {
-      const Top2 t = ld_top2(&d.rowst[(size_t)(kb0 + b) * d.ldm + r0 + x]);
+      const Top2 t = ld_top2(&rowst[(kb0 + b) * ldm + r0 + x]);
       S.rm1[b][x] = t.m1;
       S.ra1[b][x] = t.a1;
       S.rm2[b][x] = t.m2;
@@ -371,10 +380,43 @@ DEV int list_at(const Smem& S, int p, int a0, int n0, int a1) {
   return S.byk[p < n0 ? a0 + p : a1 + p - n0];
 }
 
-// Second residual of trial q (its atomic-min target) at working index idx.
-DEV unsigned ld_second(const FitDev& d, int par, int q, int idx) {
-  return ld_atomic(&d.tvec[((size_t)par * TMAX + q) * d.ldmax + idx]);
+// A wave's trials of a chunk, one per lane: lane l < NE holds the trial at
+// chunk position w + NWAVE * l (slot q = -1 past the chunk's end).  Fetched
+// in one round of LDS reads; the per-trial steps take the fields by
+// v_readlane (wave-uniform scalars).
+struct WaveTrials {
+  int q, j, k, op;
+  float val;
+};
+// Chunk positions cs .. cs + cn - 1 of the trial list made of the byk ranges
+// [a0, a0 + n0) and [a1, ...).
+template <int NE>
+DEV WaveTrials wave_trials(const Grp& gp, const Smem& S, int cs, int cn, int a0, int n0, int a1) {
+  WaveTrials w;
+  w.q = -1; w.j = 0; w.k = 0; w.op = OP_NULL; w.val = 0.0f;
+  const int sl = gp.wave + NWAVE * gp.lane;
+  if (gp.lane < NE && sl < cn) {
+    w.q = list_at(S, cs + sl, a0, n0, a1);
+    const Trial tr = S.trials[w.q];
+    w.j = tr.j; w.k = tr.k; w.op = tr.op; w.val = tr.val;
+  }
+  return w;
 }
+// The same for the byk range [base, base + cn).
+template <int NE>
+DEV WaveTrials wave_trials_range(const Grp& gp, const Smem& S, int base, int cn) {
+  WaveTrials w;
+  w.q = -1; w.j = 0; w.k = 0; w.op = OP_NULL; w.val = 0.0f;
+  const int sl = gp.wave + NWAVE * gp.lane;
+  if (gp.lane < NE && sl < cn) {
+    w.q = S.byk[base + sl];
+    const Trial tr = S.trials[w.q];
+    w.j = tr.j; w.k = tr.k; w.op = tr.op; w.val = tr.val;
+  }
+  return w;
+}
+DEV int lane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+DEV float lane_f(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
 
 // ------------------------------------------------------------ pass 1 of a batch
 // Second residual of every trial over this workgroup's tiles, combined across
@@ -386,11 +428,17 @@ DEV unsigned ld_second(const FitDev& d, int par, int q, int idx) {
 // trials w, w + NWAVE, ...), every global load issued before any is used.
 DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
   const FitDev& d = *gp.d;
+  // descriptor fields, read once (the atomics below would force reloads)
+  const auto Rw = d.Rw;
+  const auto RwT = d.RwT;
+  const auto tv = d.tvec + (size_t)par * TMAX * d.ldmax;
+  const size_t ldx = d.ldmax, ldm = d.ldm, ldn = d.ldn;
+  const int dm = d.m, dn = d.n, dr = d.r, nct = d.nct;
   const int ntile = d.nrt * d.nct;
   constexpr int NE = 2 * TCH / NWAVE;
   const int x = gp.lane;
   for (int tile = gp.g; tile < ntile; tile += gp.G) {
-    const int rt = tile / d.nct, ct = tile % d.nct;
+    const int rt = tile / nct, ct = tile % nct;
     const int r0 = rt * TS, c0 = ct * TS;
     __syncthreads();
     stage_ri(gp, S, i, c0);
@@ -398,18 +446,17 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
     for (int side = 0; side < 2; ++side) {
       // side 0, F-ULF: U''_tk = min over the tile columns of R_tc - V'_kc
       // side 1, F-URF: V''_kc = min over the tile rows of R_tc - U'_tk
-      if (S.kst[side * RMAX + d.r] == S.kst[side * RMAX]) continue;
-      const GA float* rb = side ? d.Rw + (size_t)r0 * d.ldn + c0 + gp.lane
-                                : d.RwT + (size_t)c0 * d.ldm + r0 + gp.lane;
-      const size_t rs = side ? (size_t)d.ldn : (size_t)d.ldm;
+      if (S.kst[side * RMAX + dr] == S.kst[side * RMAX]) continue;
+      const GA float* rb = side ? Rw + r0 * ldn + c0 + gp.lane : RwT + c0 * ldm + r0 + gp.lane;
+      const size_t rs = side ? ldn : ldm;
       float Rv[TS];
 #pragma unroll
       for (int y = 0; y < TS; ++y) Rv[y] = rb[y * rs];
       const int own = (side ? c0 : r0) + gp.lane;
-      const bool in = side ? r0 + x < d.m : c0 + x < d.n;
+      const bool in = side ? r0 + x < dm : c0 + x < dn;
 #pragma unroll 1
-      for (int kb0 = 0; kb0 < d.r; kb0 += KB) {
-        const int nb = d.r - kb0 < KB ? d.r - kb0 : KB;
+      for (int kb0 = 0; kb0 < dr; kb0 += KB) {
+        const int nb = dr - kb0 < KB ? dr - kb0 : KB;
         const int lo = S.kst[side * RMAX + kb0], hi = S.kst[side * RMAX + kb0 + nb];
         if (lo == hi) continue;
         __syncthreads();
@@ -418,6 +465,7 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
         for (int cs = lo; cs < hi; cs += 2 * TCH) {
           const int cn = hi - cs < 2 * TCH ? hi - cs : 2 * TCH;
           __syncthreads();
+          const WaveTrials w = wave_trials_range<NE>(gp, S, cs, cn);
           if (side == 0) {
             const float ri = S.Ri[x];
 #pragma unroll
@@ -433,16 +481,15 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
 #pragma unroll
             for (int m = 0; m < NE; ++m) {
               const int sl = gp.wave + m * NWAVE;
-              if (sl < cn) raw[m] = d.RwT[(size_t)S.trials[S.byk[cs + sl]].j * d.ldm + r0 + x];
+              if (sl < cn) raw[m] = RwT[lane_i(w.j, m) * ldm + r0 + x];
             }
 #pragma unroll
             for (int m = 0; m < NE; ++m) {
               const int sl = gp.wave + m * NWAVE;
               if (sl < cn) {
-                const Trial& tr = S.trials[S.byk[cs + sl]];
-                const int b = tr.k - kb0;
-                const float ex = S.ra1[b][x] == tr.j ? S.rm2[b][x] : S.rm1[b][x];
-                S.u.b.v.sX[sl][x] = in ? vmin(ex, raw[m] - tr.val) : 0.0f;
+                const int b = lane_i(w.k, m) - kb0;
+                const float ex = S.ra1[b][x] == lane_i(w.j, m) ? S.rm2[b][x] : S.rm1[b][x];
+                S.u.b.v.sX[sl][x] = in ? vmin(ex, raw[m] - lane_f(w.val, m)) : 0.0f;
               }
             }
           }
@@ -462,8 +509,7 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
             }
             const float xm = vmin(vmin(x0, x1), vmin(x2, x3));
             // +inf: no observed cell of this row (column) in the tile
-            if (xm != FINF)
-              atomic_min_g(&d.tvec[((size_t)par * TMAX + S.byk[cs + sl]) * d.ldmax + own], fmap(xm));
+            if (xm != FINF) atomic_min_g(&tv[S.byk[cs + sl] * ldx + own], fmap(xm));
           }
         }
       }
@@ -478,10 +524,16 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
 // rows of half w & 1 (lane = tile column) for the staged trials (w >> 1),
 // (w >> 1) + 4, ..., holding that half's R and product without k in
 // registers.  Per lane and trial the half-column sum runs over its 32 rows in
-// four interleaved FP64 accumulators; lane quads are added, and the 32 quad
-// sums of a trial are added in a fixed tree; the tile's sum is added to the
-// workgroup's per-trial sum in tile order.
-// One quad-permutation exchange (DPP control CTRL) of a double, added.
+// four interleaved FP64 accumulators; the lanes of each 16-lane row are then
+// added by DPP steps in a fixed pattern, and one thread per trial adds the
+// eight row sums (half 0 first) in a fixed order; the tile's sum is added to
+// the workgroup's per-trial sum in tile order.
+//
+// Chunks of up to TCH trials are software-pipelined: while chunk c is
+// evaluated, the global loads of chunk c + 1 are in flight, and chunk c's
+// lane sums are reduced while chunk c + 1 is being staged.
+
+// One DPP exchange (control CTRL) of a double, added.
 template <int CTRL>
 DEV double dpp_add(double a) {
   const unsigned long long b = __double_as_longlong(a);
@@ -489,22 +541,120 @@ DEV double dpp_add(double a) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
   return a + __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
-// Lanes exchange within quads (permutations 1, 0, 3, 2 then 2, 3, 0, 1) and
-// add: the four lanes end with the same sum.
-DEV double quad_sum(double v) { return dpp_add<0x4E>(dpp_add<0xB1>(v)); }
+// Sum over a 16-lane row, in lane 16 * row: quad exchanges (permutations
+// 1, 0, 3, 2 and 2, 3, 0, 1), then rotations of the row by 4 and by 8.
+DEV double row_sum(double v) {
+  return dpp_add<0x128>(dpp_add<0x124>(dpp_add<0x4E>(dpp_add<0xB1>(v))));
+}
+
+// A chunk of a batch's trial list: component k's trials [cs, cs + cn) of
+// the two byk ranges [a0, a0 + n0) (F-ULF) and [a1, a1 + n1) (F-URF).
+struct Chunk {
+  int k, cs, cn, a0, n0, a1;
+};
+// The chunk at or after component k, position cs; k == r when none is left.
+DEV Chunk chunk_at(const Smem& S, int r, int k, int cs) {
+  Chunk c;
+  for (; k < r; ++k, cs = 0) {
+    const int a0 = S.kst[k], n0 = S.kst[k + 1] - a0;
+    const int a1 = S.kst[RMAX + k], n1 = S.kst[RMAX + k + 1] - a1;
+    if (cs < n0 + n1) {
+      c.k = k; c.cs = cs; c.cn = n0 + n1 - cs < TCH ? n0 + n1 - cs : TCH;
+      c.a0 = a0; c.n0 = n0; c.a1 = a1;
+      return c;
+    }
+  }
+  c.k = r; c.cs = 0; c.cn = 0; c.a0 = c.n0 = c.a1 = 0;
+  return c;
+}
+
+// Global loads of a chunk's trials (wave w: trials w, w + NWAVE, ...):
+// F-ULF: the second residual at the tile rows; F-URF: R's column j at the
+// tile rows and the second residual at the tile columns.
+template <int NE>
+DEV void chunk_loads(Grp& gp, const WaveTrials& w, const Chunk& c, int par, int r0, int c0,
+                     float (&rawA)[NE], unsigned (&rawB)[NE]) {
+  const FitDev& d = *gp.d;
+  const auto tv = d.tvec + (size_t)par * TMAX * d.ldmax;
+  const auto RwT = d.RwT;
+  const size_t ldx = d.ldmax, ldm = d.ldm;
+  const int x = gp.lane;
+#pragma unroll
+  for (int m = 0; m < NE; ++m) {
+    if (gp.wave + m * NWAVE < c.cn) {
+      const int q = lane_i(w.q, m), op = lane_i(w.op, m);
+      if (op == OP_ULF) {
+        rawB[m] = ld_atomic(&tv[q * ldx + r0 + x]);
+      } else if (op == OP_URF) {
+        rawA[m] = RwT[lane_i(w.j, m) * ldm + r0 + x];
+        rawB[m] = ld_atomic(&tv[q * ldx + c0 + x]);
+      }
+    }
+  }
+}
+
+// The trials' two vectors into LDS: the first residual from the staged
+// summaries (block b of the component), the second from the loads.  The null
+// trial of the initial evaluation (always alone) takes the current component.
+template <int NE>
+DEV void chunk_stage(Grp& gp, Smem& S, const WaveTrials& w, const Chunk& c, int b, int r0, int c0,
+                     const float (&rawA)[NE], const unsigned (&rawB)[NE]) {
+  const FitDev& d = *gp.d;
+  const int x = gp.lane;
+  const bool rin = r0 + x < d.m, cin = c0 + x < d.n;
+  if (S.trials[list_at(S, c.cs, c.a0, c.n0, c.a1)].op == OP_NULL) {
+    if (gp.wave == 0) {
+      S.u.b.v.e.sA[0][x] = rin ? ld_atomic(&d.Uc[(size_t)c.k * d.ldm + r0 + x]) : 0.0f;
+      S.u.b.v.e.sB[0][x] = cin ? ld_atomic(&d.V[(size_t)c.k * d.ldn + c0 + x]) : 0.0f;
+    }
+    return;
+  }
+  const float cb = S.colb[b][x], ri = S.Ri[x];
+  const float m1 = S.rm1[b][x], m2 = S.rm2[b][x];
+  const int a1 = S.ra1[b][x];
+#pragma unroll
+  for (int m = 0; m < NE; ++m) {
+    const int sl = gp.wave + m * NWAVE;
+    if (sl < c.cn) {
+      const float val = lane_f(w.val, m);
+      float va, vb;
+      if (lane_i(w.op, m) == OP_ULF) {
+        va = funmap(rawB[m]);
+        vb = vmin(cb, ri - val);
+      } else {
+        va = vmin(a1 == lane_i(w.j, m) ? m2 : m1, rawA[m] - val);
+        vb = funmap(rawB[m]);
+      }
+      S.u.b.v.e.sA[sl][x] = rin ? va : 0.0f;
+      S.u.b.v.e.sB[sl][x] = cin ? vb : 0.0f;
+    }
+  }
+}
+
+// Per trial of an evaluated chunk: the eight row sums (half 0 first) in a
+// fixed order, added to this workgroup's partial error of the trial.
+DEV void chunk_reduce(Grp& gp, Smem& S, const Chunk& c) {
+  if (gp.tid < c.cn) {
+    const double* p = &S.u.b.epl[gp.tid][0][0];
+    const double s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+    S.wsum[list_at(S, c.cs + gp.tid, c.a0, c.n0, c.a1)] += s;
+  }
+}
 
 DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
   const FitDev& d = *gp.d;
+  const auto Rw = d.Rw;
+  const auto epart = d.epart;
+  const size_t ldn = d.ldn, gs = d.gsize;
+  const int dr = d.r, nct = d.nct;
   const int nt = S.nt;
   constexpr int NE = TCH / NWAVE;
   for (int q = gp.tid; q < nt; q += NTHR) S.wsum[q] = 0.0;
   const int ntile = d.nrt * d.nct;
   const int half = gp.wave & 1, h0 = half * (TS / 2);
-  const int x = gp.lane;
   for (int tile = gp.g; tile < ntile; tile += gp.G) {
-    const int rt = tile / d.nct, ct = tile % d.nct;
+    const int rt = tile / nct, ct = tile % nct;
     const int r0 = rt * TS, c0 = ct * TS;
-    const bool rin = r0 + x < d.m, cin = c0 + x < d.n;
     __syncthreads();
     stage_uv(gp, S, r0, c0);
     stage_ri(gp, S, i, c0);
@@ -513,118 +663,69 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
     unsigned obs = 0;
 #pragma unroll
     for (int t = 0; t < TS / 2; ++t) {
-      const float rv = d.Rw[(size_t)(r0 + h0 + t) * d.ldn + c0 + gp.lane];
+      const float rv = Rw[(r0 + h0 + t) * ldn + c0 + gp.lane];
       const bool o = rv != FINF;
       obs |= (unsigned)o << t;
       Rev[t] = o ? rv : FLT_MAX;
     }
-    int kb0 = -KB;
+    float rawA[NE];
+    unsigned rawB[NE];
+    Chunk cur = chunk_at(S, dr, 0, 0), prev;
+    prev.cn = 0;
+    WaveTrials wcur = wave_trials<NE>(gp, S, cur.cs, cur.cn, cur.a0, cur.n0, cur.a1);
+    chunk_loads<NE>(gp, wcur, cur, par, r0, c0, rawA, rawB);
+    int kb0 = -KB, kcur = -1;
 #pragma unroll 1
-    for (int k = 0; k < d.r; ++k) {
-      const int a0 = S.kst[k], n0 = S.kst[k + 1] - a0;
-      const int a1 = S.kst[RMAX + k], n1 = S.kst[RMAX + k + 1] - a1;
-      const int ntk = n0 + n1;
-      if (ntk == 0) continue;
-      __syncthreads();
-      if (k >= kb0 + KB) {
-        kb0 = k;
-        stage_block(gp, S, kb0, d.r - kb0 < KB ? d.r - kb0 : KB, true, true, r0, c0, i);
+    while (cur.k < dr) {
+      if (cur.k != kcur) {
+        __syncthreads();
+        if (cur.k >= kb0 + KB) {
+          kb0 = cur.k;
+          stage_block(gp, S, kb0, dr - kb0 < KB ? dr - kb0 : KB, true, true, r0, c0, i);
+        }
+        compute_pnotk(gp, S, cur.k);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < TS / 2; ++t) Pc[t] = ((obs >> t) & 1u) ? S.Ps[h0 + t][gp.lane] : FLT_MAX;
+        kcur = cur.k;
       }
-      compute_pnotk(gp, S, k);
       __syncthreads();
-#pragma unroll
-      for (int t = 0; t < TS / 2; ++t) Pc[t] = ((obs >> t) & 1u) ? S.Ps[h0 + t][gp.lane] : FLT_MAX;
-      const int b = k - kb0;
+      chunk_stage<NE>(gp, S, wcur, cur, cur.k - kb0, r0, c0, rawA, rawB);
+      chunk_reduce(gp, S, prev);
+      const Chunk next = chunk_at(S, dr, cur.k, cur.cs + TCH);
+      const WaveTrials wnext = wave_trials<NE>(gp, S, next.cs, next.cn, next.a0, next.n0, next.a1);
+      chunk_loads<NE>(gp, wnext, next, par, r0, c0, rawA, rawB);
+      __syncthreads();
 #pragma unroll 1
-      for (int cs = 0; cs < ntk; cs += TCH) {
-        const int cn = ntk - cs < TCH ? ntk - cs : TCH;
-        __syncthreads();
-        if (S.trials[list_at(S, cs, a0, n0, a1)].op == OP_NULL) {
-          // the null trial (always alone): the current component
-          if (gp.wave == 0) {
-            S.u.b.v.e.sA[0][x] = rin ? ld_atomic(&d.Uc[(size_t)k * d.ldm + r0 + x]) : 0.0f;
-            S.u.b.v.e.sB[0][x] = cin ? ld_atomic(&d.V[(size_t)k * d.ldn + c0 + x]) : 0.0f;
-          }
-        } else {
-          // the trial's two vectors: the first residual from the staged
-          // summaries, the second from the residual pass (loads first)
-          float rawA[NE];
-          unsigned rawB[NE];
+      for (int sl = gp.wave >> 1; sl < cur.cn; sl += NWAVE / 2) {
+        const float vs = S.u.b.v.e.sB[sl][gp.lane];
+        const float4* sa = reinterpret_cast<const float4*>(&S.u.b.v.e.sA[sl][h0]);
+        double e0 = 0.0, e1 = 0.0, e2 = 0.0, e3 = 0.0;
 #pragma unroll
-          for (int m = 0; m < NE; ++m) {
-            const int sl = gp.wave + m * NWAVE;
-            if (sl < cn) {
-              const int q = list_at(S, cs + sl, a0, n0, a1);
-              const Trial& tr = S.trials[q];
-              if (tr.op == OP_ULF) {
-                rawB[m] = ld_second(d, par, q, r0 + x);
-              } else {
-                rawA[m] = d.RwT[(size_t)tr.j * d.ldm + r0 + x];
-                rawB[m] = ld_second(d, par, q, c0 + x);
-              }
-            }
-          }
-#pragma unroll
-          for (int m = 0; m < NE; ++m) {
-            const int sl = gp.wave + m * NWAVE;
-            if (sl < cn) {
-              const Trial& tr = S.trials[list_at(S, cs + sl, a0, n0, a1)];
-              float va, vb;
-              if (tr.op == OP_ULF) {
-                va = funmap(rawB[m]);
-                vb = vmin(S.colb[b][x], S.Ri[x] - tr.val);
-              } else {
-                const float ex = S.ra1[b][x] == tr.j ? S.rm2[b][x] : S.rm1[b][x];
-                va = vmin(ex, rawA[m] - tr.val);
-                vb = funmap(rawB[m]);
-              }
-              S.u.b.v.e.sA[sl][x] = rin ? va : 0.0f;
-              S.u.b.v.e.sB[sl][x] = cin ? vb : 0.0f;
-            }
-          }
+        for (int t4 = 0; t4 < TS / 8; ++t4) {
+          const float4 s = sa[t4];
+          const int t = 4 * t4;
+          const float d0 = Rev[t + 0] - vmax(Pc[t + 0], s.x + vs);
+          const float d1 = Rev[t + 1] - vmax(Pc[t + 1], s.y + vs);
+          const float d2 = Rev[t + 2] - vmax(Pc[t + 2], s.z + vs);
+          const float d3 = Rev[t + 3] - vmax(Pc[t + 3], s.w + vs);
+          e0 += fabs((double)d0);
+          e1 += fabs((double)d1);
+          e2 += fabs((double)d2);
+          e3 += fabs((double)d3);
         }
-        __syncthreads();
-#pragma unroll 1
-        for (int sl = gp.wave >> 1; sl < cn; sl += NWAVE / 2) {
-          const float vs = S.u.b.v.e.sB[sl][gp.lane];
-          const float4* sa = reinterpret_cast<const float4*>(&S.u.b.v.e.sA[sl][h0]);
-          double e0 = 0.0, e1 = 0.0, e2 = 0.0, e3 = 0.0;
-#pragma unroll
-          for (int t4 = 0; t4 < TS / 8; ++t4) {
-            const float4 s = sa[t4];
-            const int t = 4 * t4;
-            const float d0 = Rev[t + 0] - vmax(Pc[t + 0], s.x + vs);
-            const float d1 = Rev[t + 1] - vmax(Pc[t + 1], s.y + vs);
-            const float d2 = Rev[t + 2] - vmax(Pc[t + 2], s.z + vs);
-            const float d3 = Rev[t + 3] - vmax(Pc[t + 3], s.w + vs);
-            e0 += fabs((double)d0);
-            e1 += fabs((double)d1);
-            e2 += fabs((double)d2);
-            e3 += fabs((double)d3);
-          }
-          const double v = quad_sum((e0 + e1) + (e2 + e3));
-          if ((gp.lane & 3) == 0) S.u.b.epl[sl][half][gp.lane >> 2] = v;
-        }
-        __syncthreads();
-        // per staged trial: eight threads add four quad sums each (half 0
-        // first), then a fixed butterfly over the eight (all get the same sum)
-        {
-          const int sl = gp.tid >> 3, sub = gp.tid & 7;
-          double s = 0.0;
-          if (sl < cn) {
-            const double* p = &S.u.b.epl[sl][sub >> 2][(sub & 3) * 4];
-            s = (p[0] + p[1]) + (p[2] + p[3]);
-          }
-          s += __shfl_xor(s, 1, 64);
-          s += __shfl_xor(s, 2, 64);
-          s += __shfl_xor(s, 4, 64);
-          if (sl < cn && sub == 0) S.wsum[list_at(S, cs + sl, a0, n0, a1)] += s;
-        }
+        const double v = row_sum((e0 + e1) + (e2 + e3));
+        if ((gp.lane & 15) == 0) S.u.b.epl[sl][half][gp.lane >> 4] = v;
       }
+      prev = cur;
+      cur = next;
+      wcur = wnext;
     }
+    __syncthreads();
+    chunk_reduce(gp, S, prev);
   }
   __syncthreads();
-  for (int q = gp.tid; q < nt; q += NTHR) st_coh(&d.epart[(size_t)q * d.gsize + gp.g], S.wsum[q]);
+  for (int q = gp.tid; q < nt; q += NTHR) st_coh(&epart[q * gs + gp.g], S.wsum[q]);
 }
 
 // Errors of this workgroup's slice of trials from the per-workgroup partials:
@@ -632,6 +733,9 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
 // fixed tree over the chunks.  The result depends only on the partials.
 DEV void reduce_errors(Grp& gp, Smem& S, int nt) {
   const FitDev& d = *gp.d;
+  const auto epart = d.epart;
+  const auto eprime = d.eprime;
+  const size_t gs = d.gsize;
   int lo, hi;
   slice(nt, gp.g, gp.G, lo, hi);
   const int per = (gp.G + 7) / 8;
@@ -643,7 +747,7 @@ DEV void reduce_errors(Grp& gp, Smem& S, int nt) {
     __syncthreads();
     for (int e = gp.tid; e < qn * gp.G; e += NTHR) {
       const int qq = e / gp.G, g = e % gp.G;
-      S.u.r.v[e] = ld_atomic(&d.epart[(size_t)(q0 + qq) * d.gsize + g]);
+      S.u.r.v[e] = ld_atomic(&epart[(q0 + qq) * gs + g]);
     }
     __syncthreads();
     for (int e = gp.tid; e < qn * 8; e += NTHR) {
@@ -657,7 +761,7 @@ DEV void reduce_errors(Grp& gp, Smem& S, int nt) {
     __syncthreads();
     for (int qq = gp.tid; qq < qn; qq += NTHR) {
       const double* p = S.u.r.chunk + qq * 8;
-      st_coh(&d.eprime[q0 + qq], ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7])));
+      st_coh(&eprime[q0 + qq], ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7])));
     }
   }
 }
@@ -665,16 +769,16 @@ DEV void reduce_errors(Grp& gp, Smem& S, int nt) {
 // Decision of a batch (last workgroup to arrive): the first trial whose
 // error is strictly below the current one.
 DEV void decide(Grp& gp, Smem& S, int nt, double e_cur) {
-  const FitDev& d = *gp.d;
+  const auto eprime = gp.d->eprime;
   if (gp.tid == 0) S.dec = 0x7fffffff;
   __syncthreads();
   for (int q = gp.tid; q < nt; q += NTHR)
-    if (ld_atomic(&d.eprime[q]) < e_cur) atomicMin(&S.dec, q);
+    if (ld_atomic(&eprime[q]) < e_cur) atomicMin(&S.dec, q);
   __syncthreads();
   if (gp.tid == 0) {
     const int dec = S.dec == 0x7fffffff ? -1 : S.dec;
     st_coh(&gp.ctl->decision, dec);
-    st_coh(&gp.ctl->e_new, dec >= 0 ? ld_atomic(&d.eprime[dec]) : 0.0);
+    st_coh(&gp.ctl->e_new, dec >= 0 ? ld_atomic(&eprime[dec]) : 0.0);
     gp.ctl->batches += 1;
   }
 }
