@@ -127,7 +127,9 @@ typedef struct {
   int log_cap;          /* capacity of decision_log in records                       */
   int batch_first;      /* speculative trials in the first batch of a row; 0 (default):
                            512 / tiles per workgroup, a power of two, at least 4  */
-  int batch_max;        /* largest batch, <= 512 (default 512)                         */
+  int batch_max;        /* largest batch, <= 512; 0 (default): 2048 / tiles per
+                           workgroup, a power of two in [64, 512].  The trial
+                           buffers of the workspace are sized by it              */
   int group_size;       /* workgroups cooperating on one fit (0 = automatic)          */
   int max_row_visits;   /* stop after this many row visits (0 = no limit)            */
 } stmf_options;
@@ -230,7 +232,8 @@ int stmf_engine_create(void* ws, size_t ws_bytes, int max_slots,
                        const stmf_options* opt, stmf_engine** out);
 void stmf_engine_destroy(stmf_engine* eng);
 
-/* Arena bytes one job of this shape needs (admission footprint). */
+/* Arena bytes one job of this shape needs (admission footprint), with the
+ * default options (acol_p 5, batch_max 0). */
 size_t stmf_job_footprint(int m, int n, int rank, int iters);
 
 /* Admit a job: copies R/M (device) into the arena and initialises the fit.

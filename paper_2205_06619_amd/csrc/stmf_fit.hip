@@ -169,12 +169,13 @@ struct Smem {
   int noops_before[TMAX];    // no-op skips preceding each trial in the batch
   int byk[TMAX];             // trial indices by key op * RMAX + k (stable)
   int kst[2 * RMAX + 1];     // key q: byk[kst[q] .. kst[q + 1])
+  int kcnt[2 * RMAX];        // per key: trial count, then the next free position
   int wk[NWAVE][2 * RMAX];   // per wave and key: trial count, then offset
   float Ri[TS];              // R of the visited row at the tile columns
   // summaries of a block of up to KB components (kb0, kb0 + 1, ...) at the tile
   float colb[KB][TS];        // F-ULF: column residual without row i, excl(colst_kc, i)
-  float rm1[KB][TS], rm2[KB][TS];
-  int ra1[KB][TS];           // F-URF: row residual summaries (m1, a1, m2) of the tile rows
+  float2 rmm[KB][TS];        // F-URF: row residual summaries of the tile rows: (m1, m2)
+  int ra1[KB][TS];           // and a1 (both values are read and one is selected)
   float urow_i[RMAX];        // U of the visited row, every component
   int closed_s[RMAX];        // closed flags at the start of the row visit
   int crow_i[RMAX];          // argmax counts of the visited row
@@ -201,7 +202,7 @@ struct Smem {
 };
 
 static_assert(sizeof(Smem) <= 160 * 1024, "LDS layout exceeds a CU's 160 KB");
-static_assert(TMAX <= NTHR && 2 * CW <= NTHR && CW * 4 <= NTHR, "one thread per trial / pair");
+static_assert(2 * CW <= NTHR && CW * 4 <= NTHR, "one thread per candidate pair");
 static_assert(RMAX == 64, "one lane per component (two group keys) in the batch grouping");
 static_assert(TCH <= NTHR, "one thread per staged trial in the error reduction");
 static_assert(KB * TS == NTHR, "one thread per staged summary");
@@ -283,7 +284,7 @@ DEV void slice(int n, int g, int G, int& lo, int& hi) {
 DEV float row_side(const FitDev& d, const Trial& tr, int par, int slot, int t) {
   if (t >= d.m) return 0.0f;
   if (tr.op == OP_ULF)
-    return funmap(ld_atomic(&d.tvec[((size_t)par * TMAX + slot) * d.ldmax + t]));
+    return funmap(ld_atomic(&d.tvec[((size_t)par * d.tmax + slot) * d.ldmax + t]));
   if (tr.op == OP_URF) {
     Top2 s = ld_top2(&d.rowst[(size_t)tr.k * d.ldm + t]);
     float x = d.RwT[(size_t)tr.j * d.ldm + t] - tr.val;
@@ -301,7 +302,7 @@ DEV float col_side(const FitDev& d, const Trial& tr, int par, int slot, int c, i
     return fminf(excl(s, i), x);
   }
   if (tr.op == OP_URF)
-    return funmap(ld_atomic(&d.tvec[((size_t)par * TMAX + slot) * d.ldmax + c]));
+    return funmap(ld_atomic(&d.tvec[((size_t)par * d.tmax + slot) * d.ldmax + c]));
   return ld_atomic(&d.V[(size_t)tr.k * d.ldn + c]);
 }
 
@@ -367,9 +368,8 @@ DEV void stage_block(Grp& gp, Smem& S, int kb0, int nb, bool cols, bool rows, in
     if (cols) S.colb[b][x] = excl(ld_top2(&colst[(kb0 + b) * ldn + c0 + x]), i);
     if (rows) {
       const Top2 t = ld_top2(&rowst[(kb0 + b) * ldm + r0 + x]);
-      S.rm1[b][x] = t.m1;
+      S.rmm[b][x] = make_float2(t.m1, t.m2);
       S.ra1[b][x] = t.a1;
-      S.rm2[b][x] = t.m2;
     }
   }
 }
@@ -431,7 +431,7 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
   // descriptor fields, read once (the atomics below would force reloads)
   const auto Rw = d.Rw;
   const auto RwT = d.RwT;
-  const auto tv = d.tvec + (size_t)par * TMAX * d.ldmax;
+  const auto tv = d.tvec + (size_t)par * d.tmax * d.ldmax;
   const size_t ldx = d.ldmax, ldm = d.ldm, ldn = d.ldn;
   const int dm = d.m, dn = d.n, dr = d.r, nct = d.nct;
   const int ntile = d.nrt * d.nct;
@@ -488,7 +488,8 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
               const int sl = gp.wave + m * NWAVE;
               if (sl < cn) {
                 const int b = lane_i(w.k, m) - kb0;
-                const float ex = S.ra1[b][x] == lane_i(w.j, m) ? S.rm2[b][x] : S.rm1[b][x];
+                const float2 mm = S.rmm[b][x];
+                const float ex = S.ra1[b][x] == lane_i(w.j, m) ? mm.y : mm.x;
                 S.u.b.v.sX[sl][x] = in ? vmin(ex, raw[m] - lane_f(w.val, m)) : 0.0f;
               }
             }
@@ -575,7 +576,7 @@ template <int NE>
 DEV void chunk_loads(Grp& gp, const WaveTrials& w, const Chunk& c, int par, int r0, int c0,
                      float (&rawA)[NE], unsigned (&rawB)[NE]) {
   const FitDev& d = *gp.d;
-  const auto tv = d.tvec + (size_t)par * TMAX * d.ldmax;
+  const auto tv = d.tvec + (size_t)par * d.tmax * d.ldmax;
   const auto RwT = d.RwT;
   const size_t ldx = d.ldmax, ldm = d.ldm;
   const int x = gp.lane;
@@ -610,7 +611,8 @@ DEV void chunk_stage(Grp& gp, Smem& S, const WaveTrials& w, const Chunk& c, int 
     return;
   }
   const float cb = S.colb[b][x], ri = S.Ri[x];
-  const float m1 = S.rm1[b][x], m2 = S.rm2[b][x];
+  const float2 mm = S.rmm[b][x];
+  const float m1 = mm.x, m2 = mm.y;
   const int a1 = S.ra1[b][x];
 #pragma unroll
   for (int m = 0; m < NE; ++m) {
@@ -787,18 +789,18 @@ DEV void decide(Grp& gp, Smem& S, int nt, double e_cur) {
 DEV void clear_prev(Grp& gp, Smem& S, int par_prev) {
   const FitDev& d = *gp.d;
   const size_t total = (size_t)S.prev_nt * d.ldmax;
-  GA unsigned* v = d.tvec + (size_t)par_prev * TMAX * d.ldmax;
+  GA unsigned* v = d.tvec + (size_t)par_prev * d.tmax * d.ldmax;
   for (size_t e = (size_t)gp.g * NTHR + gp.tid; e < total; e += (size_t)gp.G * NTHR)
     st_coh(&v[e], FMAP_INF);
 }
 
 // ------------------------------------------------------------ refresh
-// After an accepted update (acc != nullptr: component k takes the trial's
+// After an accepted update (has_acc: component k takes the trial acc's
 // vectors, written here by the owner tiles) and at initialisation: argmax
 // counts of every row and column into count buffer cb, td_col partials per
 // row tile, and the top-2 residual partials of component k.  With `full` it
 // also clears the other count buffer.
-DEV void refresh_tiles(Grp& gp, Smem& S, int k, const Trial* acc, int par, int slot, int i,
+DEV void refresh_tiles(Grp& gp, Smem& S, int k, bool has_acc, Trial acc, int par, int slot, int i,
                        bool full, int cb) {
   const FitDev& d = *gp.d;
   const int ntile = d.nrt * d.nct;
@@ -824,14 +826,14 @@ DEV void refresh_tiles(Grp& gp, Smem& S, int k, const Trial* acc, int par, int s
       }
     if (gp.tid < TS) {
       const int t = r0 + gp.tid;
-      const float v = acc ? row_side(d, *acc, par, slot, t) : ld_atomic(&d.Uc[(size_t)k * d.ldm + t]);
+      const float v = has_acc ? row_side(d, acc, par, slot, t) : ld_atomic(&d.Uc[(size_t)k * d.ldm + t]);
       S.uk[gp.tid] = v;
-      if (acc && ct == 0) st_coh(&d.Uc[(size_t)k * d.ldm + t], v);
+      if (has_acc && ct == 0) st_coh(&d.Uc[(size_t)k * d.ldm + t], v);
     } else if (gp.tid < 2 * TS) {
       const int c = c0 + gp.tid - TS;
-      const float v = acc ? col_side(d, *acc, par, slot, c, i) : ld_atomic(&d.V[(size_t)k * d.ldn + c]);
+      const float v = has_acc ? col_side(d, acc, par, slot, c, i) : ld_atomic(&d.V[(size_t)k * d.ldn + c]);
       S.vk[gp.tid - TS] = v;
-      if (acc && rt == 0) st_coh(&d.V[(size_t)k * d.ldn + c], v);
+      if (has_acc && rt == 0) st_coh(&d.V[(size_t)k * d.ldn + c], v);
     }
     if (full) stage_uv(gp, S, r0, c0);
     __syncthreads();
@@ -918,7 +920,7 @@ DEV void refresh_tiles(Grp& gp, Smem& S, int k, const Trial* acc, int par, int s
       }
     }
   }
-  if (acc && gp.g == 0 && gp.tid == 0) st_coh(&d.closed[k], 1);
+  if (has_acc && gp.g == 0 && gp.tid == 0) st_coh(&d.closed[k], 1);
 }
 
 // Residual summaries of component k from the per-tile partials (fixed tile
@@ -1049,10 +1051,10 @@ DEV void sort_by_rank(Grp& gp, Smem& S) {
 
 // Whole refresh: tile pass, barrier, summaries (and the sort in workgroup 0
 // for matrices up to SORT_MAX columns), barrier.
-DEV bool refresh(Grp& gp, Smem& S, int k, const Trial* acc, int par, int slot, int i, bool full,
+DEV bool refresh(Grp& gp, Smem& S, int k, bool has_acc, Trial acc, int par, int slot, int i, bool full,
                  int cb) {
   const FitDev& d = *gp.d;
-  refresh_tiles(gp, S, k, acc, par, slot, i, full, cb);
+  refresh_tiles(gp, S, k, has_acc, acc, par, slot, i, full, cb);
   if (!group_sync(gp, S)) return false;
   const bool small = d.n <= SORT_MAX;
   combine_summaries(gp, S, k, full && !small);
@@ -1247,10 +1249,29 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb) {
   if (gp.tid == 0) S.exhausted = (S.cq_n - S.cq_head) == 0 && S.ord_pos >= d.n;
   // Group the trials for the two passes by key op * RMAX + k (operation-
   // major, then component, stable within a key): S.byk and the key ranges
-  // S.kst.  One thread per trial; ranks within a wave by ballot, offsets from
-  // per-wave counts by key.
-  {
-    const int q = gp.tid;
+  // S.kst.  Key counts first (LDS atomics), key starts by a scan; then, NTHR
+  // trials at a time in order, ranks within a wave by ballot and offsets
+  // from per-wave counts.
+  if (gp.tid < 2 * RMAX) S.kcnt[gp.tid] = 0;
+  __syncthreads();
+  for (int q = gp.tid; q < S.nt; q += NTHR) atomicAdd(&S.kcnt[S.trials[q].op * RMAX + S.trials[q].k], 1);
+  __syncthreads();
+  if (gp.wave == 0) {
+    // lane l: keys l and RMAX + l (F-ULF keys first)
+    const int t0 = S.kcnt[gp.lane], t1 = S.kcnt[RMAX + gp.lane];
+    int i0 = t0, i1 = t1;
+    for (int sft = 1; sft < 64; sft <<= 1) {
+      const int v0 = __shfl_up(i0, sft, 64), v1 = __shfl_up(i1, sft, 64);
+      if (gp.lane >= sft) { i0 += v0; i1 += v1; }
+    }
+    const int nulf = __shfl(i0, 63, 64);
+    S.kst[gp.lane] = S.kcnt[gp.lane] = i0 - t0;
+    S.kst[RMAX + gp.lane] = S.kcnt[RMAX + gp.lane] = nulf + i1 - t1;
+    if (gp.lane == 63) S.kst[2 * RMAX] = nulf + i1;
+  }
+  __syncthreads();
+  for (int base = 0; base < S.nt; base += NTHR) {
+    const int q = base + gp.tid;
     const bool valid = q < S.nt;
     const int key = valid ? S.trials[q].op * RMAX + S.trials[q].k : -1;
     const unsigned long long below = (1ull << gp.lane) - 1ull;
@@ -1270,20 +1291,8 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb) {
     S.wk[gp.wave][RMAX + gp.lane] = c1;
     __syncthreads();
     if (gp.wave == 0) {
-      // lane l: keys l and RMAX + l.  Key starts by exclusive scans over the
-      // keys (F-ULF keys first), then the start of every wave's share.
-      int t0 = 0, t1 = 0;
-      for (int w = 0; w < NWAVE; ++w) { t0 += S.wk[w][gp.lane]; t1 += S.wk[w][RMAX + gp.lane]; }
-      int i0 = t0, i1 = t1;
-      for (int sft = 1; sft < 64; sft <<= 1) {
-        const int v0 = __shfl_up(i0, sft, 64), v1 = __shfl_up(i1, sft, 64);
-        if (gp.lane >= sft) { i0 += v0; i1 += v1; }
-      }
-      const int nulf = __shfl(i0, 63, 64);
-      int run0 = i0 - t0, run1 = nulf + i1 - t1;
-      S.kst[gp.lane] = run0;
-      S.kst[RMAX + gp.lane] = run1;
-      if (gp.lane == 63) S.kst[2 * RMAX] = nulf + i1;
+      // every wave's share of each key starts after the earlier trials'
+      int run0 = S.kcnt[gp.lane], run1 = S.kcnt[RMAX + gp.lane];
       for (int w = 0; w < NWAVE; ++w) {
         const int a = S.wk[w][gp.lane], b = S.wk[w][RMAX + gp.lane];
         S.wk[w][gp.lane] = run0;
@@ -1291,11 +1300,13 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb) {
         run0 += a;
         run1 += b;
       }
+      S.kcnt[gp.lane] = run0;
+      S.kcnt[RMAX + gp.lane] = run1;
     }
     __syncthreads();
     if (valid) S.byk[S.wk[gp.wave][key] + rank] = q;
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // Evaluate the batch in S.trials: residual pass, error pass, per-trial
@@ -1318,7 +1329,7 @@ DEV bool run_batch(Grp& gp, Smem& S, int i, int par, double e_cur, Lap& lap) {
 
 DEV void clear_trial_vectors(Grp& gp) {
   const FitDev& d = *gp.d;
-  const size_t total = (size_t)2 * TMAX * d.ldmax;
+  const size_t total = (size_t)2 * d.tmax * d.ldmax;
   for (size_t x = (size_t)gp.g * NTHR + gp.tid; x < total; x += (size_t)gp.G * NTHR)
     st_coh(&d.tvec[x], FMAP_INF);
 }
@@ -1338,7 +1349,7 @@ DEV bool fit_init(Grp& gp, Smem& S) {
   }
   if (!group_sync(gp, S)) return false;
   for (int k = 0; k < d.r; ++k)
-    if (!refresh(gp, S, k, nullptr, 0, 0, 0, k == d.r - 1, 0)) return false;
+    if (!refresh(gp, S, k, false, Trial{}, 0, 0, 0, k == d.r - 1, 0)) return false;
   if (gp.tid == 0) {
     Trial tr; tr.j = 0; tr.k = 0; tr.op = OP_NULL; tr.val = 0.0f;
     S.trials[0] = tr; S.nt = 1;
@@ -1419,7 +1430,7 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
         const Trial tr = S.trials[dec];
         acc_j = tr.j; acc_k = tr.k; acc_op = tr.op;
         e_cur = ld_atomic(&ctl->e_new);
-        if (!refresh(gp, S, tr.k, &tr, par, dec, i, true, cb ^ 1)) return;
+        if (!refresh(gp, S, tr.k, true, tr, par, dec, i, true, cb ^ 1)) return;
         cb ^= 1;
         lap(4);
         par ^= 1;

@@ -107,7 +107,7 @@ void options_default(stmf_options* o) {
   o->acol_p = 5;
   o->noop_rule = 1;
   o->batch_first = 0;
-  o->batch_max = TMAX;
+  o->batch_max = 0;
 }
 
 static int check_options(const stmf_options& o) {
@@ -116,7 +116,7 @@ static int check_options(const stmf_options& o) {
   if (o.init_mode == 0 && !(o.init_hi >= o.init_lo)) return STMF_EINVAL;
   if (o.init_mode == 1 && o.acol_p < 1) return STMF_EINVAL;
   if (o.count_scope < 0 || o.count_scope > 1) return STMF_EINVAL;
-  if (o.batch_first < 0 || o.batch_max < 1 || o.batch_max > TMAX) return STMF_EINVAL;
+  if (o.batch_first < 0 || o.batch_max < 0 || o.batch_max > TMAX) return STMF_EINVAL;
   if (o.group_size < 0 || o.log_cap < 0 || o.max_row_visits < 0) return STMF_EINVAL;
   if (!(o.eps >= 0.0)) return STMF_EINVAL;
   return STMF_OK;
@@ -125,14 +125,25 @@ static int check_options(const stmf_options& o) {
 // ---------------------------------------------------------------- layout
 struct Layout {
   int m, n, r, iters;
-  int mw, nw, ldm, ldn, nrt, nct, ldmax, G, acol_p;
+  int mw, nw, ldm, ldn, nrt, nct, ldmax, G, acol_p, tmax;
   int transposed;
   size_t Rw, RwT, Uc, V, td, tdpart, crow, ccol, colst, rowst, colpart, rowpart, order,
       tvec, epart, eprime, closed, traj, ctl, dev, perm, stage, check, rowc, colc;
   size_t total;
 };
 
-static void make_layout(int m, int n, int r, int iters, int G, int acol_p, Layout& L) {
+// Largest batch when the caller leaves it to the library: a power of two,
+// 2048 / tiles per workgroup, between 64 and TMAX (the trial buffers of the
+// layout are sized by it).
+static int auto_batch_max(int tiles, int G) {
+  const int per = (tiles + G - 1) / G;
+  int t = 64;
+  while (t * 2 <= 2048 / per && t * 2 <= TMAX) t *= 2;
+  return t;
+}
+
+static void make_layout(int m, int n, int r, int iters, int G, int acol_p, int batch_max,
+                        Layout& L) {
   L.m = m; L.n = n; L.r = r; L.iters = iters; L.G = G; L.acol_p = acol_p;
   L.transposed = m > n;
   L.mw = L.transposed ? n : m;
@@ -142,6 +153,7 @@ static void make_layout(int m, int n, int r, int iters, int G, int acol_p, Layou
   L.nrt = L.ldm / TS;
   L.nct = L.ldn / TS;
   L.ldmax = std::max(L.ldm, L.ldn);
+  L.tmax = batch_max > 0 ? batch_max : auto_batch_max(L.nrt * L.nct, G);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += al256(bytes); return at; };
   L.Rw = take((size_t)L.ldm * L.ldn * 4);
@@ -157,9 +169,9 @@ static void make_layout(int m, int n, int r, int iters, int G, int acol_p, Layou
   L.colpart = take((size_t)L.nrt * L.ldn * sizeof(Top2));
   L.rowpart = take((size_t)L.nct * L.ldm * sizeof(Top2));
   L.order = take((size_t)L.ldn * 4);
-  L.tvec = take((size_t)2 * TMAX * L.ldmax * 4);
-  L.epart = take((size_t)TMAX * G * 8);
-  L.eprime = take((size_t)TMAX * 8);
+  L.tvec = take((size_t)2 * L.tmax * L.ldmax * 4);
+  L.epart = take((size_t)L.tmax * G * 8);
+  L.eprime = take((size_t)L.tmax * 8);
   L.closed = take((size_t)r * 4);
   L.traj = take((size_t)(iters + 1) * 8);
   L.ctl = take(sizeof(FitCtl));
@@ -176,13 +188,13 @@ static void make_layout(int m, int n, int r, int iters, int G, int acol_p, Layou
 // batch costs a fixed latency (barriers, staging) plus a per-trial part that
 // grows with the tiles each workgroup sweeps, so the first batch shrinks as
 // the workgroups' share of tiles grows: 512 / tiles per workgroup, a power of
-// two, at least 4.
+// two, at least 4, at most the largest batch.
 static int auto_batch_first(const Layout& L) {
   const int tiles = L.nrt * L.nct;
   const int per = (tiles + L.G - 1) / L.G;
   int t = 4;
-  while (t * 2 <= TMAX / per && t * 2 <= TMAX) t *= 2;
-  return t;
+  while (t * 2 <= 512 / per && t * 2 <= L.tmax) t *= 2;
+  return std::min(t, L.tmax);
 }
 
 static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int observed) {
@@ -192,8 +204,8 @@ static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int o
   d.ldm = L.ldm; d.ldn = L.ldn; d.nrt = L.nrt; d.nct = L.nct;
   d.iters = L.iters;
   d.noop_rule = o.noop_rule; d.count_scope = o.count_scope;
-  d.tmax = o.batch_max;
-  d.t0 = std::min(o.batch_first > 0 ? o.batch_first : auto_batch_first(L), o.batch_max);
+  d.tmax = L.tmax;
+  d.t0 = std::min(o.batch_first > 0 ? o.batch_first : auto_batch_first(L), L.tmax);
   d.log_cap = o.decision_log ? o.log_cap : 0;
   d.eps = o.eps;
   d.omega = observed;
@@ -472,9 +484,9 @@ size_t stmf_fit_workspace(int m, int n, int rank, int iters, const stmf_options*
   DevProps P;
   if (device_props(P)) return 0;
   Layout L;
-  make_layout(m, n, rank, iters, 1, o.acol_p, L);
+  make_layout(m, n, rank, iters, 1, o.acol_p, o.batch_max, L);
   const int G = auto_group(L, P, o.group_size);
-  make_layout(m, n, rank, iters, G, o.acol_p, L);
+  make_layout(m, n, rank, iters, G, o.acol_p, o.batch_max, L);
   return L.total;
 }
 
@@ -485,7 +497,7 @@ int stmf_draw_init(int m, int n, int rank, uint64_t seed, const stmf_options* op
   if (st) return st;
   if (m < 1 || n < 1 || rank < 1 || rank > RMAX) return STMF_EINVAL;
   Layout L;
-  make_layout(m, n, rank, 0, 1, o.acol_p, L);
+  make_layout(m, n, rank, 0, 1, o.acol_p, o.batch_max, L);
   std::vector<int32_t> perm, cols;
   std::vector<float> U0;
   st = draw_setup(L, seed, o, perm, U0, cols);
@@ -513,9 +525,9 @@ int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters
   st = device_props(P);
   if (st) return st;
   Layout L;
-  make_layout(m, n, rank, iters, 1, o.acol_p, L);
+  make_layout(m, n, rank, iters, 1, o.acol_p, o.batch_max, L);
   const int G = auto_group(L, P, o.group_size);
-  make_layout(m, n, rank, iters, G, o.acol_p, L);
+  make_layout(m, n, rank, iters, G, o.acol_p, o.batch_max, L);
   if (!ws || ((uintptr_t)ws & 255) || ws_bytes < L.total) return STMF_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   char* base = (char*)ws;
@@ -575,7 +587,7 @@ static void plan_batched(const stmf_problem* probs, int nprob, int restarts, con
     Rng g{probs[p].seed};
     for (int q = 0; q < restarts; ++q) {
       Layout L;
-      make_layout(probs[p].m, probs[p].n, probs[p].rank, probs[p].iters, 1, o.acol_p, L);
+      make_layout(probs[p].m, probs[p].n, probs[p].rank, probs[p].iters, 1, o.acol_p, o.batch_max, L);
       B.L.push_back(L);
       B.off.push_back(o_);
       B.prob.push_back(p);
@@ -749,7 +761,7 @@ extern "C" {
 size_t stmf_job_footprint(int m, int n, int rank, int iters) {
   if (m < 1 || n < 1 || rank < 1 || rank > RMAX || iters < 0) return 0;
   Layout L;
-  make_layout(m, n, rank, iters, 1, 5, L);
+  make_layout(m, n, rank, iters, 1, 5, 0, L);
   return L.total;
 }
 
@@ -794,7 +806,7 @@ int stmf_engine_admit(stmf_engine* e, const float* R, const uint8_t* M, int m, i
     if (!e->slots[q].used) { sidx = q; break; }
   if (sidx < 0) return STMF_EBUSY;
   stmf_engine::Slot& S = e->slots[sidx];
-  make_layout(m, n, rank, iters, 1, e->opt.acol_p, S.L);
+  make_layout(m, n, rank, iters, 1, e->opt.acol_p, e->opt.batch_max, S.L);
   size_t off = 0;
   if (!arena_alloc(e, S.L.total, off)) return STMF_EBUSY;
   hipStream_t s = (hipStream_t)stream;

@@ -71,6 +71,9 @@ def test_argument_errors_before_any_gpu_work(stmf):
     o = stmf.options(batch_max=513)
     assert L.stmf_fit(dummy, dummy, 4, 4, 2, 1, 0, dummy, dummy, None, C.byref(o), None,
                       C.c_void_p(256), 1 << 30, None) == stmf.STMF_EINVAL
+    o = stmf.options(batch_first=-1)
+    assert L.stmf_fit(dummy, dummy, 4, 4, 2, 1, 0, dummy, dummy, None, C.byref(o), None,
+                      C.c_void_p(256), 1 << 30, None) == stmf.STMF_EINVAL
     o = stmf.options()
     assert L.stmf_fit(dummy, dummy, 4, 4, 0, 1, 0, dummy, dummy, None, C.byref(o), None,
                       C.c_void_p(256), 1 << 30, None) == stmf.STMF_EINVAL
