@@ -13,6 +13,15 @@ the trials the method evaluates, m' + n' + 1 factor entries each), the
 masked max-plus GOP/s as the paper defines its work (2 r |Omega| per
 evaluation), the fit kernel's roofline against the VALU ceiling, and the CPU
 oracle timed on a bounded prefix of the same workload.
+
+Two smaller comparisons follow the headline step (skipped with --no-extras):
+"batched" runs uneven integer problems with restarts in one persistent
+launch and through the plain one-fit-at-a-time path (results compared bit
+for bit); "serving" replays a Poisson stream of completion jobs through the
+continuous-batching loop and through the plain sequential path (p50/p99
+latency, jobs/s).  Both are scaled down from the batched and serving
+workloads (shapes, ranks and passes stated in their "config") so that the
+default run stays within minutes.
 """
 from __future__ import annotations
 
@@ -36,6 +45,101 @@ HBM_PEAK = 8.0e12
 WORKLOAD = dict(name="gene-expression-shaped", m=500, n=2000, rank=5, missing=0.5, iters=50,
                 seed=2, init="random-acol")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fit_kernel_gene_expr_500x2000_traffic.json")
+BATCHED = dict(count=64, restarts=2, iters=5, m=(50, 250), n=(50, 500), rank=(2, 8),
+               missing=(0.2, 0.8), seed=4)
+SERVING = dict(count=48, rate_per_s=100.0, iters=5, m=(50, 250), n=(50, 500), rank=(2, 8),
+               missing=(0.2, 0.8), seed=5, rows_per_tick=16, slots=256)
+
+
+def splitmix64(seed: int, count: int):
+    """Outputs of the SplitMix64 generator (Steele, Lea, Flood 2014): the
+    restart seeds of a batched problem."""
+    out, x = [], seed & 0xFFFFFFFFFFFFFFFF
+    for _ in range(count):
+        x = (x + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+        z = x
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & 0xFFFFFFFFFFFFFFFF
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def batched_compare():
+    """Batched persistent launch vs the plain path, same fits."""
+    import numpy as np
+    import torch
+    from paper_2205_06619_amd import stmf, synth
+    b = BATCHED
+    probs = synth.batched_problems(b["count"], seed=b["seed"], integer=True, m_range=b["m"],
+                                   n_range=b["n"], r_range=b["rank"], miss_range=b["missing"])
+    dev = [dict(R=torch.from_numpy(p.R).cuda(), M=torch.from_numpy(p.M).cuda(), rank=p.rank,
+                iters=b["iters"], seed=1000 + p.pid) for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs, statuses, info = stmf.stmf_fit_batched(dev, restarts=b["restarts"], integer_exact=1)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    assert statuses == [0] * len(probs)
+    t0 = time.perf_counter()
+    plain_trials, updates, same = 0, 0, True
+    for p, d, (U, V, T) in zip(probs, dev, outs):
+        for q, sd in enumerate(splitmix64(d["seed"], b["restarts"])):
+            g = stmf.stmf_fit(d["R"], d["M"], p.rank, b["iters"], seed=sd, integer_exact=1)
+            plain_trials += g.info["trials"]
+            updates += g.info["trials"] * (min(p.m, p.n) + max(p.m, p.n) + 1)
+            same = same and bool(torch.equal(U[q], g.U)) and bool(torch.equal(V[q], g.V))
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    fits = len(probs) * b["restarts"]
+    return {
+        "config": {"workload": f"{b['count']} integer planted problems x {b['restarts']} restarts, "
+                               f"m in {list(b['m'])}, n in {list(b['n'])}, rank in {list(b['rank'])}, "
+                               f"missing in {list(b['missing'])}, {b['iters']} passes"},
+        "fits": fits,
+        "batched_s": t_batched,
+        "plain_s": t_plain,
+        "batched_fits_per_s": fits / t_batched,
+        "plain_fits_per_s": fits / t_plain,
+        "batched_updates_per_s": updates / t_batched,
+        "plain_updates_per_s": updates / t_plain,
+        "speedup": t_plain / t_batched,
+        "trials": plain_trials,
+        "identical": same,
+    }
+
+
+def serving_compare():
+    """Continuous batching vs the plain sequential path on one Poisson stream."""
+    import numpy as np
+    from paper_2205_06619_amd import serve, stmf
+    c = SERVING
+    jobs = serve.synthetic_jobs(c["count"], c["rate_per_s"], seed=c["seed"], m_range=c["m"],
+                                n_range=c["n"], r_range=c["rank"], miss_range=c["missing"],
+                                iters=c["iters"])
+    need = sum(stmf.stmf_job_footprint(j.R.shape[0], j.R.shape[1], j.rank, j.iters) for j in jobs)
+    backend = serve.EngineBackend(need + (64 << 20), c["slots"])
+    try:
+        st = serve.Server(backend, rows_per_tick=c["rows_per_tick"]).run(jobs)
+    finally:
+        backend.close()
+    served = {j.jid: j.result for j in jobs}
+    seq_jobs = serve.synthetic_jobs(c["count"], c["rate_per_s"], seed=c["seed"], m_range=c["m"],
+                                    n_range=c["n"], r_range=c["rank"], miss_range=c["missing"],
+                                    iters=c["iters"])
+    sq = serve.sequential(seq_jobs, lambda j: stmf.stmf_fit(j.R, j.M, j.rank, j.iters, seed=j.seed))
+    # the plain path spreads a fit over several workgroups (another FP64
+    # summation order): trajectories agree to rounding
+    worst = max(float(np.max(np.abs(served[j.jid].traj - j.result.traj) / np.abs(j.result.traj)))
+                for j in seq_jobs)
+    return {
+        "config": {"workload": f"{c['count']} FP32 noisy planted completion jobs, Poisson arrivals "
+                               f"at {c['rate_per_s']} jobs/s, m in {list(c['m'])}, n in {list(c['n'])}, "
+                               f"rank in {list(c['rank'])}, {c['iters']} passes, "
+                               f"{c['rows_per_tick']} row visits per tick"},
+        "continuous": st.as_dict(),
+        "sequential": sq.as_dict(),
+        "max_traj_rel_diff": worst,
+    }
 
 
 def kernel_source_hash() -> str:
@@ -103,6 +207,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=16,
                     help="row visits of the oracle's CPU-baseline sample (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and serving comparisons")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs a fit on a single MI355X "
@@ -183,6 +289,9 @@ def main():
     }
     if args.cpu_rows > 0:
         out["cpu_baseline"] = cpu_baseline(R, M, args.cpu_rows)
+    if not args.no_extras:
+        out["batched"] = batched_compare()
+        out["serving"] = serving_compare()
     print(json.dumps(out), flush=True)
 
 
