@@ -975,53 +975,53 @@ DEV void combine_summaries(Grp& gp, Smem& S, int k, bool with_td) {
   __syncthreads();
 }
 
-// Column order by (td_col descending, index ascending) in one workgroup:
-// td_col from the row-tile partials (fixed order), bitonic sort in LDS.
-DEV void sort_in_workgroup(Grp& gp, Smem& S) {
+// Column order by (td_col descending, index ascending), for up to SORT_MAX
+// columns, in every workgroup at once: td_col of every column from the
+// row-tile partials (fixed order) into LDS, then the rank of each column of
+// this workgroup's slice (wave w counts the columns before it among keys
+// w, w + NWAVE, ...; the eight counts are added) and order[rank] = column.
+DEV void sort_small(Grp& gp, Smem& S) {
   const FitDev& d = *gp.d;
-  int N = 1;
-  while (N < d.n) N <<= 1;
-  for (int x = gp.tid; x < N; x += NTHR) {
-    if (x < d.n) {
-      double s = 0.0;
-      for (int rt0 = 0; rt0 < d.nrt; rt0 += 8) {
-        double v[8];
+  const auto tdpart = d.tdpart;
+  const auto td = d.td;
+  const auto order = d.order;
+  const size_t ldn = d.ldn;
+  const int n = d.n, nrt = d.nrt;
+  __syncthreads();
+  for (int x = gp.tid; x < n; x += NTHR) {
+    double v[8];
+    double sum = 0.0;
+    for (int rt0 = 0; rt0 < nrt; rt0 += 8) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          v[u] = rt0 + u < d.nrt ? ld_atomic(&d.tdpart[(size_t)(rt0 + u) * d.ldn + x]) : 0.0;
+      for (int u = 0; u < 8; ++u) v[u] = rt0 + u < nrt ? ld_atomic(&tdpart[(rt0 + u) * ldn + x]) : 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s += v[u];
-      }
-      S.u.s.key[x] = s;
-      S.u.s.idx[x] = x;
-      st_coh(&d.td[x], s);
-    } else {
-      S.u.s.key[x] = -1.0;
-      S.u.s.idx[x] = 0x7fffffff;
+      for (int u = 0; u < 8; ++u) sum += v[u];
     }
+    S.u.s.key[x] = sum;
   }
   __syncthreads();
-  for (int kk = 2; kk <= N; kk <<= 1) {
-    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-      for (int x = gp.tid; x < N; x += NTHR) {
-        const int y = x ^ jj;
-        if (y > x) {
-          const double kx = S.u.s.key[x], ky = S.u.s.key[y];
-          const int ix = S.u.s.idx[x], iy = S.u.s.idx[y];
-          // "before": larger td first, then lower index
-          const bool y_before_x = ky > kx || (ky == kx && iy < ix);
-          const bool x_before_y = kx > ky || (kx == ky && ix < iy);
-          const bool up = (x & kk) == 0;
-          if (up ? y_before_x : x_before_y) {
-            S.u.s.key[x] = ky; S.u.s.key[y] = kx;
-            S.u.s.idx[x] = iy; S.u.s.idx[y] = ix;
-          }
-        }
-      }
-      __syncthreads();
+  int lo, hi;
+  slice(n, gp.g, gp.G, lo, hi);
+  int* part = S.u.s.idx;  // NWAVE x 64 counts
+  for (int cb = lo; cb < hi; cb += 64) {
+    const int c = cb + gp.lane;
+    const bool valid = c < hi;
+    const double kc = valid ? S.u.s.key[c] : 0.0;
+    int cnt = 0;
+    for (int x = gp.wave; x < n; x += NWAVE) {
+      const double o = S.u.s.key[x];
+      cnt += (o > kc || (o == kc && x < c)) ? 1 : 0;
     }
+    part[gp.wave * 64 + gp.lane] = cnt;
+    __syncthreads();
+    if (gp.wave == 0 && valid) {
+      int rank = 0;
+      for (int w = 0; w < NWAVE; ++w) rank += part[w * 64 + gp.lane];
+      st_coh(&order[rank], c);
+      st_coh(&td[c], kc);
+    }
+    __syncthreads();
   }
-  for (int x = gp.tid; x < d.n; x += NTHR) st_coh(&d.order[x], S.u.s.idx[x]);
 }
 
 // Column order for wide matrices: every workgroup ranks its slice of columns
@@ -1049,8 +1049,8 @@ DEV void sort_by_rank(Grp& gp, Smem& S) {
   }
 }
 
-// Whole refresh: tile pass, barrier, summaries (and the sort in workgroup 0
-// for matrices up to SORT_MAX columns), barrier.
+// Whole refresh: tile pass, barrier, summaries (and, for matrices up to
+// SORT_MAX columns, the column order), barrier.
 DEV bool refresh(Grp& gp, Smem& S, int k, bool has_acc, Trial acc, int par, int slot, int i, bool full,
                  int cb) {
   const FitDev& d = *gp.d;
@@ -1058,10 +1058,7 @@ DEV bool refresh(Grp& gp, Smem& S, int k, bool has_acc, Trial acc, int par, int 
   if (!group_sync(gp, S)) return false;
   const bool small = d.n <= SORT_MAX;
   combine_summaries(gp, S, k, full && !small);
-  if (full && small && gp.g == 0) {
-    __syncthreads();
-    sort_in_workgroup(gp, S);
-  }
+  if (full && small) sort_small(gp, S);
   if (!group_sync(gp, S)) return false;
   if (full && !small) {
     sort_by_rank(gp, S);
