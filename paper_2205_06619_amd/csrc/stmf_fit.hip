@@ -160,7 +160,6 @@ struct Smem {
     CombineScratch c;
     ReduceScratch r;
   } u;
-  float Ps[TS][TS + 1];      // tile of max over l != k of U_tl + V_lc
   float Ut[RMAX][TS];        // U of the tile rows, every component
   float Vt[RMAX][TS];        // V of the tile columns, every component
   float uk[TS], vk[TS];      // new component values of the tile (refresh)
@@ -321,25 +320,6 @@ DEV void stage_uv(Grp& gp, Smem& S, int r0, int c0) {
     S.Ut[l][x] = ld_atomic(&Uc[l * ldm + r0 + x]);
     S.Vt[l][x] = ld_atomic(&V[l * ldn + c0 + x]);
   }
-}
-
-// Max over l != k of U_tl + V_lc for the tile from the staged U and V
-// (cooperative: wave w fills rows RPW*w .. RPW*w + RPW - 1), left in S.Ps.
-// With rank 1 the set is empty (-inf).
-DEV void compute_pnotk(Grp& gp, Smem& S, int k) {
-  const FitDev& d = *gp.d;
-  float P[RPW];
-#pragma unroll
-  for (int tt = 0; tt < RPW; ++tt) P[tt] = -FINF;
-  const int tl0 = gp.wave * RPW;
-  for (int l = 0; l < d.r; ++l) {
-    if (l == k) continue;
-    const float v = S.Vt[l][gp.lane];
-#pragma unroll
-    for (int tt = 0; tt < RPW; ++tt) P[tt] = vmax(P[tt], S.Ut[l][tl0 + tt] + v);
-  }
-#pragma unroll
-  for (int tt = 0; tt < RPW; ++tt) S.Ps[tl0 + tt][gp.lane] = P[tt];
 }
 
 // ------------------------------------------------------------ trial staging
@@ -660,6 +640,7 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
     __syncthreads();
     stage_uv(gp, S, r0, c0);
     stage_ri(gp, S, i, c0);
+    __syncthreads();
     // an unobserved cell takes R = P = FLT_MAX, which contributes |d| = 0
     float Rev[TS / 2], Pc[TS / 2];
     unsigned obs = 0;
@@ -680,15 +661,31 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
 #pragma unroll 1
     while (cur.k < dr) {
       if (cur.k != kcur) {
-        __syncthreads();
+        // summaries of the component's block (read by the staging after the
+        // chunk's barrier; the previous chunk's staging is done with them)
         if (cur.k >= kb0 + KB) {
           kb0 = cur.k;
           stage_block(gp, S, kb0, dr - kb0 < KB ? dr - kb0 : KB, true, true, r0, c0, i);
         }
-        compute_pnotk(gp, S, cur.k);
-        __syncthreads();
+        // the product without k for this wave's rows and lane column, from
+        // the staged U and V (each wave forms its own: no barrier)
 #pragma unroll
-        for (int t = 0; t < TS / 2; ++t) Pc[t] = ((obs >> t) & 1u) ? S.Ps[h0 + t][gp.lane] : FLT_MAX;
+        for (int t = 0; t < TS / 2; ++t) Pc[t] = -FINF;
+        for (int l = 0; l < dr; ++l) {
+          if (l == cur.k) continue;
+          const float v = S.Vt[l][gp.lane];
+          const float4* u4 = reinterpret_cast<const float4*>(&S.Ut[l][h0]);
+#pragma unroll
+          for (int t4 = 0; t4 < TS / 8; ++t4) {
+            const float4 u = u4[t4];
+            Pc[4 * t4 + 0] = vmax(Pc[4 * t4 + 0], u.x + v);
+            Pc[4 * t4 + 1] = vmax(Pc[4 * t4 + 1], u.y + v);
+            Pc[4 * t4 + 2] = vmax(Pc[4 * t4 + 2], u.z + v);
+            Pc[4 * t4 + 3] = vmax(Pc[4 * t4 + 3], u.w + v);
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < TS / 2; ++t) Pc[t] = ((obs >> t) & 1u) ? Pc[t] : FLT_MAX;
         kcur = cur.k;
       }
       __syncthreads();
