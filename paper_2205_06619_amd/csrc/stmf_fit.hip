@@ -1121,6 +1121,7 @@ DEV void refill_candidates(Grp& gp, Smem& S, int i) {
 // workgroup of the group computes the same list.
 DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb) {
   const FitDev& d = *gp.d;
+  if (T > d.tmax) T = d.tmax;  // never more trials than the trial buffers hold
   const GA int* ccol = d.ccol + (size_t)cb * d.ldn * d.r;
   if (gp.tid == 0) { S.nt = 0; S.batch_noops = 0; }
   __syncthreads();
@@ -1406,7 +1407,16 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
     const int i = row;
     row_begin(gp, S, i, cb);
     lap(0);
+    // first batch: sized from the trials this row's previous visit needed
+    // (batch sizes change which trials are evaluated speculatively, never
+    // the outcome)
+    const int prev_trials = ld_atomic(&d.rowt[i]);
     int T = d.t0;
+    if (prev_trials > 0) {
+      T = 16;
+      while (T < prev_trials) T *= 2;
+    }
+    if (T > d.tmax) T = d.tmax;  // the trial buffers hold tmax trials
     long long row_trials = 0, row_noops = 0, row_spec = 0;
     int acc_j = -1, acc_k = -1, acc_op = -1;
     while (true) {
@@ -1437,6 +1447,7 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
       T = T * 2 > d.tmax ? d.tmax : T * 2;
     }
     if (acc_j >= 0) ++acc_pass;
+    if (gp.g == 0 && gp.tid == 0) st_coh(&d.rowt[i], (int)(row_trials > 0 ? row_trials : 1));
     // bookkeeping by one thread of the group
     if (gp.g == 0 && gp.tid == 0) {
       ctl->trials += row_trials;

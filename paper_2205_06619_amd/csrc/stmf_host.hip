@@ -127,7 +127,7 @@ struct Layout {
   int m, n, r, iters;
   int mw, nw, ldm, ldn, nrt, nct, ldmax, G, acol_p, tmax;
   int transposed;
-  size_t Rw, RwT, Uc, V, td, tdpart, crow, ccol, colst, rowst, colpart, rowpart, order,
+  size_t Rw, RwT, Uc, V, td, tdpart, crow, ccol, colst, rowst, colpart, rowpart, order, rowt,
       tvec, epart, eprime, closed, traj, ctl, dev, perm, stage, check, rowc, colc;
   size_t total;
 };
@@ -173,6 +173,7 @@ static void make_layout(int m, int n, int r, int iters, int G, int acol_p, int b
   L.epart = take((size_t)L.tmax * G * 8);
   L.eprime = take((size_t)L.tmax * 8);
   L.closed = take((size_t)r * 4);
+  L.rowt = take((size_t)L.mw * 4);
   L.traj = take((size_t)(iters + 1) * 8);
   L.ctl = take(sizeof(FitCtl));
   L.dev = take(sizeof(FitDev));
@@ -226,6 +227,7 @@ static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int o
   d.epart = (double*)(base + L.epart);
   d.eprime = (double*)(base + L.eprime);
   d.closed = (int*)(base + L.closed);
+  d.rowt = (int*)(base + L.rowt);
   d.traj = (double*)(base + L.traj);
   d.log = (LogRec*)o.decision_log;
   d.ctl = (FitCtl*)(base + L.ctl);
@@ -341,6 +343,7 @@ static int prepare_fit(const float* R, const uint8_t* M, const Layout& L, char* 
   HIPCHK(hipGetLastError());
   int st = fill_u32(base + L.ctl, sizeof(FitCtl) / 4, 0, s);
   if (!st) st = fill_u32(base + L.closed, (size_t)L.r, 0, s);
+  if (!st) st = fill_u32(base + L.rowt, (size_t)L.mw, 0, s);
   if (!st) st = fill_u32(base + L.traj, (size_t)(L.iters + 1) * 2, 0, s);
   return st;
 }

@@ -115,6 +115,7 @@ struct FitDev {
   STMF_G(double) epart;      // TMAX x gsize: per-workgroup partial errors
   STMF_G(double) eprime;     // TMAX: error of every trial of the batch
   STMF_G(int) closed;        // r
+  STMF_G(int) rowt;          // m': trials the last visit of each row evaluated (0: none yet)
   STMF_G(double) traj;       // iters + 1
   STMF_G(LogRec) log;        // nullable
   STMF_G(FitCtl) ctl;
