@@ -125,10 +125,13 @@ typedef struct {
   int integer_exact;    /* 1: STMF_ERANGE unless every observed |R| and |U0| < 2^24  */
   void* decision_log;   /* device, nullable: one stmf_log_rec per row visit          */
   int log_cap;          /* capacity of decision_log in records                       */
-  int batch_first;      /* speculative trials in the first batch of a row; 0 (default):
-                           512 / tiles per workgroup, a power of two, at least 4  */
-  int batch_max;        /* largest batch, <= 512; 0 (default): 2048 / tiles per
-                           workgroup, a power of two in [64, 512].  The trial
+  int batch_first;      /* speculative trials in the first batch of a row's first
+                           visit; 0 (default): 512 / tiles per workgroup, a power
+                           of two, at least 4.  Later visits of a row start with
+                           the power of two at or above the trials its previous
+                           visit needed (at least 16)                           */
+  int batch_max;        /* largest batch, <= 1024; 0 (default): 2048 / tiles per
+                           workgroup, a power of two in [64, 1024].  The trial
                            buffers of the workspace are sized by it              */
   int group_size;       /* workgroups cooperating on one fit (0 = automatic)          */
   int max_row_visits;   /* stop after this many row visits (0 = no limit)            */

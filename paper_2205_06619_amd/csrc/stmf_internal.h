@@ -17,7 +17,7 @@ namespace stmf {
 constexpr int TS = 64;          // tile side: 64 rows x 64 columns of the working matrix
 constexpr int NWAVE = 8;        // waves per workgroup
 constexpr int NTHR = 64 * NWAVE;
-constexpr int TMAX = 512;       // trials per speculative batch (upper bound)
+constexpr int TMAX = 1024;      // trials per speculative batch (upper bound)
 constexpr int TCH = 64;         // trials staged in LDS at a time
 constexpr int CW = 128;         // candidate columns examined at a time
 constexpr int RMAX = 64;        // largest supported rank

@@ -68,7 +68,7 @@ def test_argument_errors_before_any_gpu_work(stmf):
                            C.c_void_p(256), 1 << 20, None) == stmf.STMF_EINVAL
     assert L.stmf_update_V(dummy, dummy, dummy, dummy, 4, 4, 2, 0, 0, 2, dummy, dummy, dummy,
                            C.c_void_p(256), 1 << 20, None) == stmf.STMF_EINVAL
-    o = stmf.options(batch_max=513)
+    o = stmf.options(batch_max=1025)
     assert L.stmf_fit(dummy, dummy, 4, 4, 2, 1, 0, dummy, dummy, None, C.byref(o), None,
                       C.c_void_p(256), 1 << 30, None) == stmf.STMF_EINVAL
     o = stmf.options(batch_first=-1)
