@@ -15,6 +15,8 @@
 //     argmax multisets                                        Sec. 3.2.1
 //   * F-ULF / F-URF                                           Algorithms 1, 2
 //   * FastSTMF = ByRow, random row permutation, TD_A, wide    Algorithm 3
+//   * the other ByRow selections TD, TD_B and SEQ, and the row orders PermR
+//     (rows by increasing minimum) and none                   Sec. 3.2.1, 3.3
 //
 // Every routine is a template over the value type T.  T = double is "the FP64
 // oracle": all value arithmetic in double on exactly promoted FP32 inputs.
@@ -41,7 +43,19 @@
 //     trajectory is padded with the current error;
 //   - random draws: SplitMix64 (Steele, Lea, Flood 2014), bounded integers by
 //     rejection of x < 2^64 mod b then x mod b, Durstenfeld's Fisher-Yates
-//     from the last index down; draw order: permutation, then U0.
+//     from the last index down; draw order: permutation, then U0 (with PermR
+//     or no permutation the stream starts with U0);
+//   - TD: candidates by td(i, j) = |R_ij - (U (x) V)_ij| descending, ties by
+//     ascending j, k = f(i, j);
+//   - TD_B: candidates as TD_A; j0 = the column of largest td_col (lowest on
+//     ties); ByRow's err(t, j) = td_col(j) does not depend on the row t, so
+//     every row ties for i0 and the lowest working row is taken;
+//     k = f(i, j0) if (U (x) V)_{i j0} >= (U (x) V)_{i0 j}, else f(i0, j);
+//   - SEQ: every (j, k, operation) of row i is evaluated, j and k ascending,
+//     F-ULF before F-URF; the one with the smallest error below the current
+//     one is applied (ties: the first in that order);
+//   - PermR: working rows by increasing minimum observed value, ties by the
+//     lower original index.
 //
 // Parity of the TD_A counting scope, the candidate tie order, the Random-Acol
 // column count and the random stream is unpinned: the paper fixes none of
@@ -197,6 +211,8 @@ struct oracle_opts {
   int count_scope;       // 0 observed cells, 1 every index
   int noop_rule;         // 1: skip no-op trials as rejected
   int integer_exact;     // 1: reject |value| >= 2^24
+  int selection;         // 0 TD_A, 1 TD, 2 TD_B, 3 SEQ
+  int perm_mode;         // 0 random, 1 PermR (increasing minimum), 2 none
 };
 
 struct oracle_log {      // one record per row visit
@@ -274,6 +290,7 @@ int build_working(const float* R, const uint8_t* M, int m, int n,
   w.m = w.transposed ? n : m;
   w.n = w.transposed ? m : n;
   w.perm.resize(w.m);
+  if (o && (o->perm_mode < 0 || o->perm_mode > 2)) return EINVAL_;
   if (o && o->perm) {
     std::vector<char> hit(w.m, 0);
     for (int a = 0; a < w.m; ++a) {
@@ -282,6 +299,22 @@ int build_working(const float* R, const uint8_t* M, int m, int n,
       hit[p] = 1;
       w.perm[a] = p;
     }
+  } else if (o && o->perm_mode == 1) {
+    // PermR: working rows by increasing minimum observed value, stable
+    std::vector<float> mn(w.m, 0.0f);
+    for (int a = 0; a < w.m; ++a) {
+      bool seen = false;
+      for (int b = 0; b < w.n; ++b) {
+        size_t s = w.transposed ? ((size_t)b * n + a) : ((size_t)a * n + b);
+        if (!M[s]) continue;
+        float v = R[s] + 0.0f;
+        if (!seen || v < mn[a]) { mn[a] = v; seen = true; }
+      }
+    }
+    for (int a = 0; a < w.m; ++a) w.perm[a] = a;
+    std::stable_sort(w.perm.begin(), w.perm.end(), [&](int x, int y) { return mn[x] < mn[y]; });
+  } else if (o && o->perm_mode == 2) {
+    for (int a = 0; a < w.m; ++a) w.perm[a] = a;
   } else {
     for (int a = 0; a < w.m; ++a) w.perm[a] = a;
     for (int a = w.m - 1; a >= 1; --a) {
@@ -403,6 +436,8 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
   const int scope_all = o && o->count_scope == 1;
   const int noop_rule = o ? o->noop_rule : 1;
   const double eps = o ? o->eps : 0.0;
+  const int sel = o ? o->selection : 0;
+  if (sel < 0 || sel > 3) return EINVAL_;
 
   int it_done = 0;
   bool stop = false;
@@ -412,56 +447,129 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
     for (int i = 0; i < m; ++i) {
       if (rows_left == 0) { stop = true; break; }
       if (rows_left > 0) --rows_left;
-      // row multiset {{ f(i,t) }} as counts
-      std::vector<int> crow((size_t)r, 0);
-      for (int t = 0; t < n; ++t)
-        if (scope_all || M[(size_t)i * n + t]) crow[A[(size_t)i * n + t]]++;
-      // candidate columns: observed in row i, td_col descending, j ascending
-      std::vector<int> cand;
-      for (int j = 0; j < n; ++j)
-        if (M[(size_t)i * n + j]) cand.push_back(j);
-      std::stable_sort(cand.begin(), cand.end(),
-                       [&](int a, int b) { return td[a] > td[b]; });
       oracle_log rec{it, i, 0, 0, -1, -1, -1, 0, e};
       bool accepted = false;
-      for (int j : cand) {
-        std::vector<int> cnt(crow);
-        for (int t = 0; t < m; ++t)
-          if (scope_all || M[(size_t)t * n + j]) cnt[A[(size_t)t * n + j]]++;
-        int k = 0;
-        for (int l = 1; l < r; ++l)
-          if (cnt[l] > cnt[k]) k = l;
-        for (int op = 0; op < 2 && !accepted; ++op) {
-          T* Uik = &U[(size_t)i * r + k];
-          T* Vkj = &V[(size_t)k * n + j];
-          T Rij = R[(size_t)i * n + j];
-          if (noop_rule && closed[k]) {
-            bool same = op == 0 ? (T)(Rij - *Vkj) == *Uik : (T)(Rij - *Uik) == *Vkj;
-            if (same) { rec.noops++; S.noops++; continue; }
-          }
-          double e2 = op == 0
-              ? f_ulf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k,
+      // One trial on the current state (U, V changed; restore() undoes it).
+      // Returns false for a no-op skip, counted as a rejection.
+      auto try_op = [&](int j, int k, int op, double& e2) -> bool {
+        T* Uik = &U[(size_t)i * r + k];
+        T* Vkj = &V[(size_t)k * n + j];
+        T Rij = R[(size_t)i * n + j];
+        if (noop_rule && closed[k]) {
+          bool same = op == 0 ? (T)(Rij - *Vkj) == *Uik : (T)(Rij - *Uik) == *Vkj;
+          if (same) { rec.noops++; S.noops++; return false; }
+        }
+        e2 = op == 0
+            ? f_ulf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k,
+                    Ubak.data(), Vbak.data(), td_try.data(), A_try.data())
+            : f_urf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k,
+                    Ubak.data(), Vbak.data(), td_try.data(), A_try.data());
+        rec.trials++;
+        S.trials++;
+        S.evaluated_cells += omega;
+        return true;
+      };
+      auto restore = [&](int k) {
+        for (int t = 0; t < m; ++t) U[(size_t)t * r + k] = Ubak[t];
+        for (int c = 0; c < n; ++c) V[(size_t)k * n + c] = Vbak[c];
+      };
+      auto accept = [&](int j, int k, int op, double e2) {
+        e = e2;
+        td.swap(td_try);
+        A.swap(A_try);
+        closed[k] = 1;
+        accepted = true;
+        rec.j = j; rec.k = k; rec.op = op; rec.e = e;
+        S.accepted++;
+        acc_this_pass++;
+      };
+      // (U (x) V)_tj of the current state
+      auto prod = [&](int t, int j) {
+        T best = U[(size_t)t * r + 0] + V[j];
+        for (int l = 1; l < r; ++l) {
+          T x = U[(size_t)t * r + l] + V[(size_t)l * n + j];
+          if (x > best) best = x;
+        }
+        return best;
+      };
+      std::vector<int> cand;  // observed columns of row i
+      for (int j = 0; j < n; ++j)
+        if (M[(size_t)i * n + j]) cand.push_back(j);
+
+      if (sel == 3) {
+        // SEQ: every (j, k, operation), the smallest error below e wins
+        int bj = -1, bk = -1, bop = -1;
+        double be = e;
+        for (int j : cand)
+          for (int k = 0; k < r; ++k)
+            for (int op = 0; op < 2; ++op) {
+              double e2;
+              if (!try_op(j, k, op, e2)) continue;
+              if (e2 < be) { be = e2; bj = j; bk = k; bop = op; }
+              restore(k);
+            }
+        if (bj >= 0) {
+          // apply the chosen update again (the same arithmetic, the same result)
+          double e2 = bop == 0
+              ? f_ulf(R.data(), M, U.data(), V.data(), m, n, r, i, bj, bk,
                       Ubak.data(), Vbak.data(), td_try.data(), A_try.data())
-              : f_urf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k,
+              : f_urf(R.data(), M, U.data(), V.data(), m, n, r, i, bj, bk,
                       Ubak.data(), Vbak.data(), td_try.data(), A_try.data());
-          rec.trials++;
-          S.trials++;
-          S.evaluated_cells += omega;
-          if (e2 < e) {
-            e = e2;
-            td.swap(td_try);
-            A.swap(A_try);
-            closed[k] = 1;
-            accepted = true;
-            rec.j = j; rec.k = k; rec.op = op; rec.e = e;
-            S.accepted++;
-            acc_this_pass++;
+          accept(bj, bk, bop, e2);
+        }
+      } else {
+        // candidate order and the component of each candidate
+        std::vector<int> kof((size_t)n, 0);
+        if (sel == 1) {
+          // TD: entry error td(i, j) descending; k = f(i, j)
+          std::vector<double> tij((size_t)n, 0.0);
+          for (int j : cand) {
+            T d = R[(size_t)i * n + j] - prod(i, j);
+            tij[j] = std::fabs((double)d);
+            kof[j] = A[(size_t)i * n + j];
+          }
+          std::stable_sort(cand.begin(), cand.end(),
+                           [&](int a, int b) { return tij[a] > tij[b]; });
+        } else {
+          // TD_A and TD_B: td_col descending
+          std::stable_sort(cand.begin(), cand.end(),
+                           [&](int a, int b) { return td[a] > td[b]; });
+          if (sel == 0) {
+            // TD_A: the index counted most often in the two argmax multisets
+            std::vector<int> crow((size_t)r, 0);
+            for (int t = 0; t < n; ++t)
+              if (scope_all || M[(size_t)i * n + t]) crow[A[(size_t)i * n + t]]++;
+            for (int j : cand) {
+              std::vector<int> cnt(crow);
+              for (int t = 0; t < m; ++t)
+                if (scope_all || M[(size_t)t * n + j]) cnt[A[(size_t)t * n + j]]++;
+              int k = 0;
+              for (int l = 1; l < r; ++l)
+                if (cnt[l] > cnt[k]) k = l;
+              kof[j] = k;
+            }
           } else {
-            for (int t = 0; t < m; ++t) U[(size_t)t * r + k] = Ubak[t];
-            for (int c = 0; c < n; ++c) V[(size_t)k * n + c] = Vbak[c];
+            // TD_B: j0 = largest td_col, i0 = the first working row
+            int j0 = 0;
+            for (int t = 1; t < n; ++t)
+              if (td[t] > td[j0]) j0 = t;
+            const int i0 = 0;
+            const T p_ij0 = prod(i, j0);
+            const int f_ij0 = A[(size_t)i * n + j0];
+            for (int j : cand)
+              kof[j] = p_ij0 >= prod(i0, j) ? f_ij0 : A[(size_t)i0 * n + j];
           }
         }
-        if (accepted) break;
+        for (int j : cand) {
+          const int k = kof[j];
+          for (int op = 0; op < 2 && !accepted; ++op) {
+            double e2;
+            if (!try_op(j, k, op, e2)) continue;
+            if (e2 < e) accept(j, k, op, e2);
+            else restore(k);
+          }
+          if (accepted) break;
+        }
       }
       S.row_visits++;
       if (log && nlog < log_cap) log[nlog] = rec;

@@ -313,30 +313,69 @@ def test_fit_hand_derived_2x2(prec, noop):
         assert got == want
 
 
-def _brute_force_row(R, M, U, V, i, e, closed, noop_rule, prec):
-    """Independent restatement of one row visit of Algorithm 3 by brute force:
-    every (j, op) is evaluated from scratch with no early exit, the TD_A index
-    is counted with a Counter over the two multisets, and the first strict
-    decrease in (td_col desc, j asc; F-ULF then F-URF) order is returned."""
+def _maxplus_entry(U, V, i, j, T):
+    return max(T(T(U[i, l]) + T(V[l, j])) for l in range(U.shape[1]))
+
+
+def _argmax_entry(U, V, i, j, T):
+    vals = [T(T(U[i, l]) + T(V[l, j])) for l in range(U.shape[1])]
+    return vals.index(max(vals))
+
+
+def _brute_force_row(R, M, U, V, i, e, closed, noop_rule, prec, selection=0):
+    """Independent restatement of one row visit of Algorithm 3 by brute force
+    (Sec. 3.2.1 selections): every (j, k, op) needed is evaluated from
+    scratch with no early exit; TD_A's index is counted with a Counter over the
+    two multisets, TD's order and index come from the entry's own max-plus
+    terms, TD_B compares the two products entry by entry, and SEQ takes the
+    smallest error over every (j, k, op).  The first strict decrease in
+    candidate order (F-ULF then F-URF) is returned."""
     m, n = R.shape; r = U.shape[1]
+    T = np.float32 if prec == "f32" else np.float64
     _, td, A = oracle.masked_error(R, M, U, V, prec)
-    row_ms = [A[i, t] for t in range(n) if M[i, t]]
-    order = sorted([j for j in range(n) if M[i, j]], key=lambda j: (-td[j], j))
+    obs = [j for j in range(n) if M[i, j]]
+
+    def evaluate(j, k, op):
+        if noop_rule and closed[k]:
+            if op == "U" and T(T(R[i, j]) - T(V[k, j])) == T(U[i, k]):
+                return None
+            if op == "V" and T(T(R[i, j]) - T(U[i, k])) == T(V[k, j]):
+                return None
+        U2, V2, e2, *_ = oracle.update(op, R, M, U, V, i, j, k, prec)
+        return (e2, U2, V2)
+
+    if selection == 3:
+        best = None
+        for j in obs:
+            for k in range(r):
+                for op in ("U", "V"):
+                    res = evaluate(j, k, op)
+                    if res is not None and res[0] < e and (best is None or res[0] < best[3][0]):
+                        best = (j, k, op, res)
+        return best
+    if selection == 1:
+        tij = {j: abs(float(T(T(R[i, j]) - _maxplus_entry(U, V, i, j, T)))) for j in obs}
+        order = sorted(obs, key=lambda j: (-tij[j], j))
+        kof = {j: _argmax_entry(U, V, i, j, T) for j in obs}
+    else:
+        order = sorted(obs, key=lambda j: (-td[j], j))
+        if selection == 0:
+            row_ms = [A[i, t] for t in range(n) if M[i, t]]
+            kof = {}
+            for j in order:
+                col_ms = [A[t, j] for t in range(m) if M[t, j]]
+                cnt = collections.Counter(row_ms) + collections.Counter(col_ms)
+                top = max(cnt.values())
+                kof[j] = min(l for l in range(r) if cnt.get(l, 0) == top)
+        else:
+            j0 = min(range(n), key=lambda t: (-td[t], t))
+            p_ij0 = _maxplus_entry(U, V, i, j0, T)
+            kof = {j: (_argmax_entry(U, V, i, j0, T) if p_ij0 >= _maxplus_entry(U, V, 0, j, T)
+                       else _argmax_entry(U, V, 0, j, T)) for j in order}
     results = []
     for j in order:
-        col_ms = [A[t, j] for t in range(m) if M[t, j]]
-        cnt = collections.Counter(row_ms) + collections.Counter(col_ms)
-        best = max(cnt.values())
-        k = min(l for l in range(r) if cnt.get(l, 0) == best)
         for op in ("U", "V"):
-            T = np.float32 if prec == "f32" else np.float64
-            if noop_rule and closed[k]:
-                if op == "U" and T(T(R[i, j]) - T(V[k, j])) == T(U[i, k]):
-                    results.append((j, k, op, None)); continue
-                if op == "V" and T(T(R[i, j]) - T(U[i, k])) == T(V[k, j]):
-                    results.append((j, k, op, None)); continue
-            U2, V2, e2, *_ = oracle.update(op, R, M, U, V, i, j, k, prec)
-            results.append((j, k, op, (e2, U2, V2)))
+            results.append((j, kof[j], op, evaluate(j, kof[j], op)))
     for j, k, op, res in results:
         if res is not None and res[0] < e:
             return j, k, op, res
@@ -345,13 +384,14 @@ def _brute_force_row(R, M, U, V, i, e, closed, noop_rule, prec):
 
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("seed", range(4))
-def test_fit_rows_match_brute_force(prec, seed):
+@pytest.mark.parametrize("selection", [0, 1, 2, 3])
+def test_fit_rows_match_brute_force(prec, seed, selection):
     m, n, r = 5, 7, 3
     R, M = synth.tiny_int_case(m, n, r, 40 + seed, hi=9, missing=0.2, planted=True)
     U0 = np.random.default_rng(seed).integers(0, 10, (m, r)).astype(np.float32)
     perm = np.arange(m)
     iters = 3
-    res = oracle.fit(R, M, r, iters, prec=prec, init_mode=2, U0=U0, perm=perm)
+    res = oracle.fit(R, M, r, iters, prec=prec, init_mode=2, U0=U0, perm=perm, selection=selection)
     assert res.status == 0
     # replay with brute force
     U = U0.astype(np.float64); V = np.zeros((r, n))
@@ -360,12 +400,16 @@ def test_fit_rows_match_brute_force(prec, seed):
     e, _, _ = oracle.masked_error(R, M, U, V, prec)
     closed = [False] * r
     logi = 0
+    accepted = 0
     for it in range(1, iters + 1):
         if logi >= len(res.log):
             break
         for i in range(m):
             rec = res.log[logi]; logi += 1
-            got = _brute_force_row(R, M, U, V, i, e, closed, True, prec)
+            if selection == 3:
+                # every (j, k, op) of the row is tried or skipped as a no-op
+                assert rec["trials"] + rec["noops"] == 2 * r * int(M[i].sum())
+            got = _brute_force_row(R, M, U, V, i, e, closed, True, prec, selection)
             if got is None:
                 assert rec["j"] == -1
             else:
@@ -374,8 +418,72 @@ def test_fit_rows_match_brute_force(prec, seed):
                 assert rec["e"] == e2
                 U, V, e = U2, V2, e2
                 closed[k] = True
+                accepted += 1
+    assert accepted > 0
     np.testing.assert_array_equal(res.U, U.astype(np.float32))
     np.testing.assert_array_equal(res.V, V.astype(np.float32))
+
+
+def test_seq_never_above_td_a_on_one_row_visit():
+    # SEQ takes the best decrease over every (j, k, op) of the row, so after
+    # one row visit from the same state its error is at most TD_A's
+    for seed in range(6):
+        R, M = synth.tiny_int_case(6, 9, 3, 60 + seed, hi=12, missing=0.3, planted=False)
+        U0 = np.random.default_rng(seed).integers(0, 12, (6, 3)).astype(np.float32)
+        kw = dict(prec="f64", init_mode=2, U0=U0, perm=np.arange(6), row_limit=1)
+        a = oracle.fit(R, M, 3, 1, selection=0, **kw)
+        s = oracle.fit(R, M, 3, 1, selection=3, **kw)
+        assert a.status == 0 and s.status == 0
+        assert s.log[0]["e"] <= a.log[0]["e"]
+
+
+def _row_minima_order(R, M):
+    mins = np.where(M == 1, R, np.inf).min(axis=1)
+    return np.argsort(mins, kind="stable")
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_permr_orders_rows_by_increasing_minimum(transpose):
+    # PermR (Sec. 3.2): rows sorted by increasing minimum observed value; the
+    # order equals numpy's stable argsort of the row minima, and PermR is the
+    # same fit as passing that permutation explicitly
+    R, M = synth.int_planted(14, 22, 3, seed=16)
+    R = R.copy(); R[M == 0] = -1000.0   # unobserved values never count
+    R[3] = R[5]; M[3] = M[5]            # a tie between two rows
+    if transpose:
+        R, M = R.T.copy(), M.T.copy()
+    Rw, Mw = (R.T, M.T) if transpose else (R, M)
+    want = _row_minima_order(Rw, Mw)
+    s, perm, _ = oracle.draw_init(R, M, 3, seed=4, perm_mode=1)
+    assert s == 0
+    np.testing.assert_array_equal(perm, want)
+    mins = np.where(Mw == 1, Rw, np.inf).min(axis=1)[perm]
+    assert np.all(np.diff(mins) >= 0)
+    a = oracle.fit(R, M, 3, 2, seed=4, prec="f32", perm_mode=1)
+    b = oracle.fit(R, M, 3, 2, seed=4, prec="f32", perm=want)
+    assert a.status == 0
+    np.testing.assert_array_equal(a.U, b.U); np.testing.assert_array_equal(a.V, b.V)
+    np.testing.assert_array_equal(a.traj, b.traj)
+
+
+def test_no_permutation_is_identity_order():
+    R, M = synth.int_planted(12, 20, 2, seed=17)
+    s, perm, _ = oracle.draw_init(R, M, 2, seed=9, perm_mode=2)
+    assert s == 0
+    np.testing.assert_array_equal(perm, np.arange(12))
+    a = oracle.fit(R, M, 2, 2, seed=9, prec="f32", perm_mode=2)
+    b = oracle.fit(R, M, 2, 2, seed=9, prec="f32", perm=np.arange(12))
+    np.testing.assert_array_equal(a.U, b.U); np.testing.assert_array_equal(a.traj, b.traj)
+
+
+def test_selection_defaults_are_faststmf():
+    # the defaults are Algorithm 3: random permutation and TD_A
+    R, M = synth.int_planted(15, 24, 3, seed=18)
+    a = oracle.fit(R, M, 3, 3, seed=6, prec="f32")
+    b = oracle.fit(R, M, 3, 3, seed=6, prec="f32", selection=0, perm_mode=0)
+    np.testing.assert_array_equal(a.U, b.U); np.testing.assert_array_equal(a.traj, b.traj)
+    assert oracle.fit(R, M, 3, 1, selection=4).status == 1
+    assert oracle.fit(R, M, 3, 1, perm_mode=3).status == 1
 
 
 @pytest.mark.parametrize("prec", PRECS)
