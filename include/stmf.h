@@ -135,6 +135,26 @@ typedef struct {
                            buffers of the workspace are sized by it              */
   int group_size;       /* workgroups cooperating on one fit (0 = automatic)          */
   int max_row_visits;   /* stop after this many row visits (0 = no limit)            */
+  int selection;        /* ByRow choice of (j, k) within a row visit (Sec. 3.2.1):
+                           0 TD_A (default, Algorithm 3): columns by td_col
+                             descending, k counted most often in the two argmax
+                             multisets of row i and column j;
+                           1 TD: the row's observed columns by the entry error
+                             |R_ij - (U (x) V)_ij| descending, k = f(i, j);
+                           2 TD_B: columns as TD_A, j0 the first of them, i0 the
+                             first working row (td_col does not depend on the
+                             row), k = f(i, j0) if (U (x) V)_{i j0} >=
+                             (U (x) V)_{i0 j}, else f(i0, j);
+                           3 SEQ: every (j, k, operation) of the row, j and k
+                             ascending, F-ULF first; the smallest error below
+                             the current one is applied (the first on ties).
+                           Ties in every order: the lower index first.         */
+  int perm_mode;        /* working-row order when perm is null (Sec. 3.2):
+                           0 random permutation drawn from the seed (default),
+                           1 PermR: rows by increasing minimum observed value,
+                             ties by the lower working index,
+                           2 none (identity).  With 1 and 2 the seed's stream
+                           starts with the initial U.                           */
 } stmf_options;
 
 /* Per-row-visit decision record (decision_log). */
@@ -177,7 +197,7 @@ size_t stmf_fit_workspace(int m, int n, int rank, int iters, const stmf_options*
  *   after a fixed point (a pass with no accepted update) or the eps stop the
  *   rest is padded with the last value.  info (host, nullable).
  *   seed drives SplitMix64: the working-row permutation is drawn first
- *   (Durstenfeld shuffle), then the initial U.
+ *   (Durstenfeld shuffle; not with perm_mode 1 or 2), then the initial U.
  * Errors: STMF_EINVAL, STMF_EEMPTY_LINE, STMF_ERANGE, STMF_ENOMEM, STMF_EHIP,
  * STMF_ETIMEOUT. */
 int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters,
@@ -188,7 +208,9 @@ int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters
 /* Setup draws of stmf_fit without fitting (host outputs): the working-row
  * permutation (m' = min(m, n) entries) and the initial U (m' x rank, working
  * orientation, before Random Acol averaging when init_mode = 1, which instead
- * writes the drawn column indices, rank x acol_p, as floats). */
+ * writes the drawn column indices, rank x acol_p, as floats).  perm_mode 2
+ * gives the identity; perm_mode 1 (PermR depends on R, not on the seed) is
+ * STMF_EINVAL unless perm is given. */
 int stmf_draw_init(int m, int n, int rank, uint64_t seed, const stmf_options* opt,
                    int32_t* perm_out, float* U0_out);
 

@@ -45,6 +45,7 @@ namespace stmf {
 static constexpr float FINF = __builtin_huge_valf();
 static constexpr unsigned long long BARRIER_TIMEOUT = 400000000ull;  // 4 s at 100 MHz
 static constexpr int ST_TIMEOUT = 7;
+static constexpr int ST_INTERNAL = 8;   // a re-evaluated trial did not reproduce its error
 static constexpr int RPW = TS / NWAVE;  // tile rows (or columns) per wave
 static constexpr int CQ_CAP = NTHR + CW + 128;
 static constexpr int KB = 8;            // components whose summaries are staged together
@@ -197,7 +198,12 @@ struct Smem {
   float cvu[CW], cvv[CW];
   int cnu[CW], cnv[CW];
   int kbest[CW][4], kval[CW][4];
+  float kvalf[CW][4];
   float vsel[CW];
+  // TD_B: U of the first working row, and (U (x) V) and its argmax at (i, j0)
+  float urow0[RMAX];
+  float p_ij0;
+  int f_ij0;
 };
 
 static_assert(sizeof(Smem) <= 160 * 1024, "LDS layout exceeds a CU's 160 KB");
@@ -765,14 +771,39 @@ DEV void reduce_errors(Grp& gp, Smem& S, int nt) {
   }
 }
 
-// Decision of a batch (last workgroup to arrive): the first trial whose
-// error is strictly below the current one.
-DEV void decide(Grp& gp, Smem& S, int nt, double e_cur) {
+// Decision of a batch (last workgroup to arrive), among the trials whose
+// error is strictly below thr: the first one, or with `best` the one of
+// smallest error (the first of them on ties).
+DEV void decide(Grp& gp, Smem& S, int nt, double thr, bool best) {
   const auto eprime = gp.d->eprime;
   if (gp.tid == 0) S.dec = 0x7fffffff;
   __syncthreads();
-  for (int q = gp.tid; q < nt; q += NTHR)
-    if (ld_atomic(&eprime[q]) < e_cur) atomicMin(&S.dec, q);
+  if (!best) {
+    for (int q = gp.tid; q < nt; q += NTHR)
+      if (ld_atomic(&eprime[q]) < thr) atomicMin(&S.dec, q);
+  } else {
+    double bv = thr;
+    int bq = 0x7fffffff;
+    for (int q = gp.tid; q < nt; q += NTHR) {
+      const double v = ld_atomic(&eprime[q]);
+      if (v < bv) { bv = v; bq = q; }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ov = __shfl_xor(bv, off, 64);
+      const int oq = __shfl_xor(bq, off, 64);
+      if (ov < bv || (ov == bv && oq < bq)) { bv = ov; bq = oq; }
+    }
+    if (gp.lane == 0) { S.u.r.v[gp.wave] = bv; S.wcount[gp.wave] = bq; }
+    __syncthreads();
+    if (gp.tid == 0) {
+      for (int w = 1; w < NWAVE; ++w) {
+        const double ov = S.u.r.v[w];
+        const int oq = S.wcount[w];
+        if (ov < bv || (ov == bv && oq < bq)) { bv = ov; bq = oq; }
+      }
+      S.dec = bq;
+    }
+  }
   __syncthreads();
   if (gp.tid == 0) {
     const int dec = S.dec == 0x7fffffff ? -1 : S.dec;
@@ -972,31 +1003,12 @@ DEV void combine_summaries(Grp& gp, Smem& S, int k, bool with_td) {
   __syncthreads();
 }
 
-// Column order by (td_col descending, index ascending), for up to SORT_MAX
-// columns, in every workgroup at once: td_col of every column from the
-// row-tile partials (fixed order) into LDS, then the rank of each column of
-// this workgroup's slice (wave w counts the columns before it among keys
-// w, w + NWAVE, ...; the eight counts are added) and order[rank] = column.
-DEV void sort_small(Grp& gp, Smem& S) {
-  const FitDev& d = *gp.d;
-  const auto tdpart = d.tdpart;
-  const auto td = d.td;
-  const auto order = d.order;
-  const size_t ldn = d.ldn;
-  const int n = d.n, nrt = d.nrt;
-  __syncthreads();
-  for (int x = gp.tid; x < n; x += NTHR) {
-    double v[8];
-    double sum = 0.0;
-    for (int rt0 = 0; rt0 < nrt; rt0 += 8) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = rt0 + u < nrt ? ld_atomic(&tdpart[(rt0 + u) * ldn + x]) : 0.0;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) sum += v[u];
-    }
-    S.u.s.key[x] = sum;
-  }
-  __syncthreads();
+// Rank sort of the keys S.u.s.key[0 .. n) (n <= SORT_MAX), descending,
+// index ascending on ties, in every workgroup at once: each workgroup ranks
+// its slice (wave w counts the keys before a column among keys w, w + NWAVE,
+// ...; the eight counts are added) and writes out[rank] = column and, if
+// keys_out is given, keys_out[column] = key.
+DEV void rank_slice_lds(Grp& gp, Smem& S, int n, GA int* out, GA double* keys_out) {
   int lo, hi;
   slice(n, gp.g, gp.G, lo, hi);
   int* part = S.u.s.idx;  // NWAVE x 64 counts
@@ -1014,27 +1026,52 @@ DEV void sort_small(Grp& gp, Smem& S) {
     if (gp.wave == 0 && valid) {
       int rank = 0;
       for (int w = 0; w < NWAVE; ++w) rank += part[w * 64 + gp.lane];
-      st_coh(&order[rank], c);
-      st_coh(&td[c], kc);
+      st_coh(&out[rank], c);
+      if (keys_out) st_coh(&keys_out[c], kc);
     }
     __syncthreads();
   }
 }
 
-// Column order for wide matrices: every workgroup ranks its slice of columns
-// against all of td_col, staged through LDS in chunks.
-DEV void sort_by_rank(Grp& gp, Smem& S) {
+// Column order by (td_col descending, index ascending), for up to SORT_MAX
+// columns: td_col of every column from the row-tile partials (fixed order)
+// into LDS in every workgroup, then the ranks of each workgroup's slice.
+DEV void sort_small(Grp& gp, Smem& S) {
+  const FitDev& d = *gp.d;
+  const auto tdpart = d.tdpart;
+  const size_t ldn = d.ldn;
+  const int n = d.n, nrt = d.nrt;
+  __syncthreads();
+  for (int x = gp.tid; x < n; x += NTHR) {
+    double v[8];
+    double sum = 0.0;
+    for (int rt0 = 0; rt0 < nrt; rt0 += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = rt0 + u < nrt ? ld_atomic(&tdpart[(rt0 + u) * ldn + x]) : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sum += v[u];
+    }
+    S.u.s.key[x] = sum;
+  }
+  __syncthreads();
+  rank_slice_lds(gp, S, n, d.order, d.td);
+}
+
+// Order of wide matrices: every workgroup ranks its slice of columns against
+// all the keys (descending, index ascending on ties), staged through LDS in
+// chunks; out[rank] = column.
+DEV void sort_by_rank(Grp& gp, Smem& S, const GA double* keys, GA int* out) {
   const FitDev& d = *gp.d;
   int lo, hi;
   slice(d.n, gp.g, gp.G, lo, hi);
   for (int base = lo; base < hi; base += NTHR) {
     const int c = base + gp.tid;
-    const double key = c < hi ? ld_atomic(&d.td[c]) : 0.0;
+    const double key = c < hi ? ld_atomic(&keys[c]) : 0.0;
     int rank = 0;
     for (int x0 = 0; x0 < d.n; x0 += SORT_MAX) {
       const int len = d.n - x0 < SORT_MAX ? d.n - x0 : SORT_MAX;
       __syncthreads();
-      for (int x = gp.tid; x < len; x += NTHR) S.u.s.key[x] = ld_atomic(&d.td[x0 + x]);
+      for (int x = gp.tid; x < len; x += NTHR) S.u.s.key[x] = ld_atomic(&keys[x0 + x]);
       __syncthreads();
       if (c < hi)
         for (int x = 0; x < len; ++x) {
@@ -1042,7 +1079,7 @@ DEV void sort_by_rank(Grp& gp, Smem& S) {
           rank += (o > key || (o == key && x0 + x < c)) ? 1 : 0;
         }
     }
-    if (c < hi) st_coh(&d.order[rank], c);
+    if (c < hi) st_coh(&out[rank], c);
   }
 }
 
@@ -1058,7 +1095,7 @@ DEV bool refresh(Grp& gp, Smem& S, int k, bool has_acc, Trial acc, int par, int 
   if (full && small) sort_small(gp, S);
   if (!group_sync(gp, S)) return false;
   if (full && !small) {
-    sort_by_rank(gp, S);
+    sort_by_rank(gp, S, d.td, d.order);
     if (!group_sync(gp, S)) return false;
   }
   return true;
@@ -1067,24 +1104,75 @@ DEV bool refresh(Grp& gp, Smem& S, int k, bool has_acc, Trial acc, int par, int 
 // ------------------------------------------------------------ row visit pieces
 // Start a row visit: argmax counts, U and closed flags of row i into LDS,
 // candidate queue empty.
-DEV void row_begin(Grp& gp, Smem& S, int i, int cb) {
+DEV void row_begin(Grp& gp, Smem& S, int i, int cb, int sel) {
   const FitDev& d = *gp.d;
   if (gp.tid < d.r) {
     S.crow_i[gp.tid] = ld_atomic(&d.crow[((size_t)cb * d.ldm + i) * d.r + gp.tid]);
     S.urow_i[gp.tid] = ld_atomic(&d.Uc[(size_t)gp.tid * d.ldm + i]);
     S.closed_s[gp.tid] = ld_atomic(&d.closed[gp.tid]);
   }
+  if (sel == SEL_TD_B) {
+    // i0 = the first working row (the column error td_col does not depend on
+    // the row, so every row ties and the lowest index is taken); j0 = the
+    // column of largest td_col, the first of the order
+    if (gp.tid < d.r) S.urow0[gp.tid] = ld_atomic(&d.Uc[(size_t)gp.tid * d.ldm]);
+    if (gp.tid == 0) {
+      const int j0 = ld_atomic(&d.order[0]);
+      float best = 0.0f;
+      int kb = 0;
+      for (int l = 0; l < d.r; ++l) {
+        const float x = ld_atomic(&d.Uc[(size_t)l * d.ldm + i]) + ld_atomic(&d.V[(size_t)l * d.ldn + j0]);
+        if (l == 0 || x > best) { best = x; kb = l; }
+      }
+      S.p_ij0 = best;
+      S.f_ij0 = kb;
+    }
+  }
   if (gp.tid == 0) { S.cq_head = 0; S.cq_n = 0; S.ord_pos = 0; S.cur_op = 0; }
   __syncthreads();
+}
+
+// TD (Sec. 3.2.1): the visited row's columns by the entry error
+// |R_ic - (U (x) V)_ic| descending, index ascending on ties, into d.rord
+// (unobserved columns last, key -1).  Values in FP32 as everywhere on the
+// value path; the key is the exact widening of the FP32 difference.
+DEV double td_entry_key(const FitDev& d, const Smem& S, int i, int c) {
+  const float rv = d.Rw[(size_t)i * d.ldn + c];
+  if (rv == FINF) return -1.0;
+  float p = S.urow_i[0] + ld_atomic(&d.V[c]);
+  for (int l = 1; l < d.r; ++l) p = vmax(p, S.urow_i[l] + ld_atomic(&d.V[(size_t)l * d.ldn + c]));
+  return (double)fabsf(rv - p);
+}
+
+DEV bool row_order_td(Grp& gp, Smem& S, int i) {
+  const FitDev& d = *gp.d;
+  if (d.n <= SORT_MAX) {
+    // every workgroup computes every key in LDS, then ranks its slice
+    for (int c = gp.tid; c < d.n; c += NTHR) S.u.s.key[c] = td_entry_key(d, S, i, c);
+    __syncthreads();
+    rank_slice_lds(gp, S, d.n, d.rord, nullptr);
+  } else {
+    int lo, hi;
+    slice(d.n, gp.g, gp.G, lo, hi);
+    for (int c = lo + gp.tid; c < hi; c += NTHR) st_coh(&d.tdrow[c], td_entry_key(d, S, i, c));
+    if (!group_sync(gp, S)) return false;
+    sort_by_rank(gp, S, d.tdrow, d.rord);
+  }
+  return group_sync(gp, S);
 }
 
 // Keep at least CW candidates of row i queued (observed columns in the
 // current order), unless the order is exhausted.  Every workgroup of the
 // group builds the same queue.
-DEV void refill_candidates(Grp& gp, Smem& S, int i) {
+DEV void refill_candidates(Grp& gp, Smem& S, int i, int sel) {
   const FitDev& d = *gp.d;
   const GA float* Ri = d.Rw + (size_t)i * d.ldn;
-  while (S.cq_n - S.cq_head < CW && S.ord_pos < d.n) {
+  // TD_A, TD_B: the column order; TD: the row's own order; SEQ: every
+  // (column, component) pair, both ascending (entry j * RMAX + k)
+  const bool seq = sel == SEL_SEQ;
+  const GA int* ord = sel == SEL_TD ? d.rord : d.order;
+  const int total = seq ? d.n * d.r : d.n;
+  while (S.cq_n - S.cq_head < CW && S.ord_pos < total) {
     // move the unconsumed tail to the front
     const int keep = S.cq_n - S.cq_head;
     int v = 0;
@@ -1093,9 +1181,14 @@ DEV void refill_candidates(Grp& gp, Smem& S, int i) {
     if (gp.tid < keep) S.cq[gp.tid] = v;
     const int pos = S.ord_pos + gp.tid;
     int j = -1;
-    if (pos < d.n) {
-      j = ld_atomic(&d.order[pos]);
-      if (Ri[j] == FINF) j = -1;
+    if (pos < total) {
+      if (seq) {
+        const int c = pos / d.r;
+        j = Ri[c] == FINF ? -1 : c * RMAX + (pos - c * d.r);
+      } else {
+        j = ld_atomic(&ord[pos]);
+        if (Ri[j] == FINF) j = -1;
+      }
     }
     const unsigned long long m = __ballot(j >= 0);
     const int below = __popcll(m & ((1ull << gp.lane) - 1ull));
@@ -1119,51 +1212,95 @@ DEV void refill_candidates(Grp& gp, Smem& S, int i) {
 // Next batch of up to T trials from the cursor, in the method's order:
 // candidate by candidate, F-ULF then F-URF, skipping no-op trials.  Every
 // workgroup of the group computes the same list.
-DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb) {
+DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb, int sel) {
   const FitDev& d = *gp.d;
   if (T > d.tmax) T = d.tmax;  // never more trials than the trial buffers hold
   const GA int* ccol = d.ccol + (size_t)cb * d.ldn * d.r;
   if (gp.tid == 0) { S.nt = 0; S.batch_noops = 0; }
   __syncthreads();
   while (true) {
-    refill_candidates(gp, S, i);
+    refill_candidates(gp, S, i, sel);
     const int avail0 = S.cq_n - S.cq_head;
     if (S.nt >= T || avail0 == 0) break;
     const int avail = avail0 < CW ? avail0 : CW;
-    // TD_A index of each candidate in the window: four threads per
-    // candidate, each over components l = sub, sub + 4, ... (their counts and
-    // V_lj loaded in one round)
+    // Component of each candidate in the window, four threads per candidate,
+    // each over components l = sub, sub + 4, ... (V_lj, and for TD_A the
+    // column counts, loaded in one round):
+    //   TD_A: the index counted most often in row i's and column j's argmax
+    //         multisets (lowest on ties);
+    //   TD:   f(i, j), the lowest argmax of U_il + V_lj;
+    //   TD_B: f(i, j0) if (U (x) V)_{i j0} >= (U (x) V)_{i0 j}, else f(i0, j);
+    //   SEQ:  the candidate's own component.
     {
       const int p = gp.tid >> 2, sub = gp.tid & 3;
       float vv[RMAX / 4];
       if (p < avail) {
-        const int j = S.cq[S.cq_head + p];
-        int cnt[RMAX / 4];
+        const int e = S.cq[S.cq_head + p];
+        const int j = sel == SEL_SEQ ? e / RMAX : e;
 #pragma unroll
         for (int u = 0; u < RMAX / 4; ++u) {
           const int l = sub + 4 * u;
-          cnt[u] = l < d.r ? ld_atomic(&ccol[(size_t)j * d.r + l]) : 0;
           vv[u] = l < d.r ? ld_atomic(&d.V[(size_t)l * d.ldn + j]) : 0.0f;
         }
-        int best = -1, kb = 0;
+        if (sel == SEL_TD_A) {
+          int cnt[RMAX / 4];
 #pragma unroll
-        for (int u = 0; u < RMAX / 4; ++u) {
-          const int l = sub + 4 * u;
-          if (l < d.r) {
-            const int v = S.crow_i[l] + cnt[u];
-            if (v > best) { best = v; kb = l; }
+          for (int u = 0; u < RMAX / 4; ++u) {
+            const int l = sub + 4 * u;
+            cnt[u] = l < d.r ? ld_atomic(&ccol[(size_t)j * d.r + l]) : 0;
           }
+          int best = -1, kb = 0;
+#pragma unroll
+          for (int u = 0; u < RMAX / 4; ++u) {
+            const int l = sub + 4 * u;
+            if (l < d.r) {
+              const int v = S.crow_i[l] + cnt[u];
+              if (v > best) { best = v; kb = l; }
+            }
+          }
+          S.kval[p][sub] = best;
+          S.kbest[p][sub] = kb;
+        } else if (sel != SEL_SEQ) {
+          // row i (TD) or row i0 (TD_B): value selects, not address selects
+          const bool own = sel == SEL_TD;
+          float best = 0.0f;
+          int kb = -1;
+#pragma unroll
+          for (int u = 0; u < RMAX / 4; ++u) {
+            const int l = sub + 4 * u;
+            if (l < d.r) {
+              const float uv = own ? S.urow_i[l] : S.urow0[l];
+              const float x = uv + vv[u];
+              if (kb < 0 || x > best) { best = x; kb = l; }
+            }
+          }
+          S.kvalf[p][sub] = best;
+          S.kbest[p][sub] = kb;
         }
-        S.kval[p][sub] = best;
-        S.kbest[p][sub] = kb;
       }
       __syncthreads();
       if (gp.tid < avail) {
         const int q = gp.tid;
-        int best = -1, k = 0;
-        for (int u = 0; u < 4; ++u) {
-          const int v = S.kval[q][u], kb = S.kbest[q][u];
-          if (v > best || (v == best && kb < k)) { best = v; k = kb; }
+        int k = 0;
+        if (sel == SEL_TD_A) {
+          int best = -1;
+          for (int u = 0; u < 4; ++u) {
+            const int v = S.kval[q][u], kb = S.kbest[q][u];
+            if (v > best || (v == best && kb < k)) { best = v; k = kb; }
+          }
+        } else if (sel == SEL_SEQ) {
+          k = S.cq[S.cq_head + q] % RMAX;
+        } else {
+          float best = 0.0f;
+          int kb = -1;
+          for (int u = 0; u < 4; ++u) {
+            const int c = S.kbest[q][u];
+            if (c < 0) continue;
+            const float v = S.kvalf[q][u];
+            if (kb < 0 || v > best || (v == best && c < kb)) { best = v; kb = c; }
+          }
+          k = kb;
+          if (sel == SEL_TD_B && S.p_ij0 >= best) k = S.f_ij0;
         }
         S.ck[q] = k;
       }
@@ -1179,7 +1316,8 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb) {
     __syncthreads();
     if (gp.tid < avail) {
       const int p = gp.tid;
-      const int j = S.cq[S.cq_head + p];
+      const int e = S.cq[S.cq_head + p];
+      const int j = sel == SEL_SEQ ? e / RMAX : e;
       const int k = S.ck[p];
       const float Rij = d.Rw[(size_t)i * d.ldn + j];
       const float Uik = S.urow_i[k];
@@ -1241,7 +1379,8 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb) {
     }
     __syncthreads();
   }
-  if (gp.tid == 0) S.exhausted = (S.cq_n - S.cq_head) == 0 && S.ord_pos >= d.n;
+  if (gp.tid == 0)
+    S.exhausted = (S.cq_n - S.cq_head) == 0 && S.ord_pos >= (sel == SEL_SEQ ? d.n * d.r : d.n);
   // Group the trials for the two passes by key op * RMAX + k (operation-
   // major, then component, stable within a key): S.byk and the key ranges
   // S.kst.  Key counts first (LDS atomics), key starts by a scan; then, NTHR
@@ -1305,10 +1444,10 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb) {
 }
 
 // Evaluate the batch in S.trials: residual pass, error pass, per-trial
-// reduction, and the decision (first trial with e' < e) made by the last
-// workgroup to arrive.
+// reduction, and the decision (the first trial with e' < thr, or with `best`
+// the smallest such e') made by the last workgroup to arrive.
 template <typename Lap>
-DEV bool run_batch(Grp& gp, Smem& S, int i, int par, double e_cur, Lap& lap) {
+DEV bool run_batch(Grp& gp, Smem& S, int i, int par, double thr, bool best, Lap& lap) {
   batch_residual_pass(gp, S, i, par);
   if (!group_sync(gp, S)) return false;
   lap(2);
@@ -1317,9 +1456,24 @@ DEV bool run_batch(Grp& gp, Smem& S, int i, int par, double e_cur, Lap& lap) {
   if (!group_sync(gp, S)) return false;
   lap(6);
   reduce_errors(gp, S, S.nt);
-  const bool ok = group_sync_last(gp, S, [&] { decide(gp, S, S.nt, e_cur); });
+  const bool ok = group_sync_last(gp, S, [&] { decide(gp, S, S.nt, thr, best); });
   lap(3);
   return ok;
+}
+
+// A batch of the one trial tr (its key range and list position).
+DEV void single_trial(Grp& gp, Smem& S, Trial tr) {
+  __syncthreads();
+  if (gp.tid == 0) {
+    const int key = tr.op * RMAX + tr.k;
+    S.trials[0] = tr;
+    S.noops_before[0] = 0;
+    S.nt = 1;
+    S.batch_noops = 0;
+    for (int q = 0; q <= 2 * RMAX; ++q) S.kst[q] = q <= key ? 0 : 1;
+    S.byk[0] = 0;
+  }
+  __syncthreads();
 }
 
 DEV void clear_trial_vectors(Grp& gp) {
@@ -1374,8 +1528,12 @@ DEV bool fit_init(Grp& gp, Smem& S) {
 
 // Run the fit from its saved state for at most max_rows row visits (0: no
 // limit).  All workgroups of the group execute the same control flow.
+// FastSTMF's TD_A (ANY_SEL false) is compiled on its own, without the code of
+// the other selections.
+template <bool ANY_SEL>
 DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
   const FitDev& d = *gp.d;
+  const int sel = ANY_SEL ? d.sel : (int)SEL_TD_A;
   GA FitCtl* ctl = gp.ctl;
   if (gp.tid == 0) { S.prev_nt = 0; S.status = 0; }
   __syncthreads();
@@ -1405,29 +1563,45 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
   while (phase == 1) {
     if (max_rows > 0 && rows_done >= max_rows) break;
     const int i = row;
-    row_begin(gp, S, i, cb);
+    row_begin(gp, S, i, cb, sel);
+    if (sel == SEL_TD && !row_order_td(gp, S, i)) return;
     lap(0);
+    // SEQ evaluates every trial of the row: full batches, the best one kept
+    const bool seq = sel == SEL_SEQ;
     // first batch: sized from the trials this row's previous visit needed
     // (batch sizes change which trials are evaluated speculatively, never
     // the outcome)
     const int prev_trials = ld_atomic(&d.rowt[i]);
     int T = d.t0;
-    if (prev_trials > 0) {
+    if (seq) {
+      T = d.tmax;
+    } else if (prev_trials > 0) {
       T = 16;
       while (T < prev_trials) T *= 2;
     }
     if (T > d.tmax) T = d.tmax;  // the trial buffers hold tmax trials
     long long row_trials = 0, row_noops = 0, row_spec = 0;
     int acc_j = -1, acc_k = -1, acc_op = -1;
+    double e_best = e_cur;
+    Trial best_tr;
+    best_tr.j = -1; best_tr.k = 0; best_tr.op = OP_NULL; best_tr.val = 0.0f;
     while (true) {
-      build_batch(gp, S, i, T, cb);
+      build_batch(gp, S, i, T, cb, sel);
       lap(1);
       const int nt = S.nt;
       if (nt == 0) { row_noops += S.batch_noops; break; }
-      if (!run_batch(gp, S, i, par, e_cur, lap)) return;
+      if (!run_batch(gp, S, i, par, seq ? e_best : e_cur, seq, lap)) return;
       const int dec = ld_atomic(&ctl->decision);
       row_spec += nt;
       if (gp.tid == 0) S.prev_nt = nt;
+      if (seq) {
+        row_trials += nt;
+        row_noops += S.batch_noops;
+        if (dec >= 0) { best_tr = S.trials[dec]; e_best = ld_atomic(&ctl->e_new); }
+        par ^= 1;
+        if (S.exhausted) break;
+        continue;
+      }
       if (dec >= 0) {
         row_trials += dec + 1;
         row_noops += S.noops_before[dec];
@@ -1445,6 +1619,28 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
       par ^= 1;
       if (S.exhausted) break;
       T = T * 2 > d.tmax ? d.tmax : T * 2;
+    }
+    if (seq && best_tr.j >= 0) {
+      // the chosen trial once more, alone, for its vectors (the evaluation is
+      // deterministic: it reproduces the error it was chosen for)
+      single_trial(gp, S, best_tr);
+      if (!run_batch(gp, S, i, par, e_cur, false, lap)) return;
+      row_spec += 1;
+      if (gp.tid == 0) S.prev_nt = 1;
+      if (ld_atomic(&ctl->decision) != 0 || ld_atomic(&ctl->e_new) != e_best) {
+        if (gp.tid == 0) {
+          int zero = 0;
+          __hip_atomic_compare_exchange_strong(&ctl->status, &zero, ST_INTERNAL, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+      }
+      acc_j = best_tr.j; acc_k = best_tr.k; acc_op = best_tr.op;
+      e_cur = e_best;
+      if (!refresh(gp, S, best_tr.k, true, best_tr, par, 0, i, true, cb ^ 1)) return;
+      cb ^= 1;
+      lap(4);
+      par ^= 1;
     }
     if (acc_j >= 0) ++acc_pass;
     if (gp.g == 0 && gp.tid == 0) st_coh(&d.rowt[i], (int)(row_trials > 0 ? row_trials : 1));
@@ -1493,9 +1689,9 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
 
 // One fit per group of gsize workgroups.  With nfits > 1 every workgroup
 // takes fits from a queue, one workgroup per fit.
-__global__ void __launch_bounds__(NTHR) fit_kernel(const FitDev* __restrict__ fits, int nfits,
-                                                   int gsize, int max_rows,
-                                                   unsigned* __restrict__ queue) {
+template <bool ANY_SEL>
+DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int gsize, int max_rows,
+                         unsigned* __restrict__ queue) {
   extern __shared__ __align__(16) char smem_raw[];
   Smem& S = *reinterpret_cast<Smem*>(smem_raw);
   Grp gp;
@@ -1507,7 +1703,7 @@ __global__ void __launch_bounds__(NTHR) fit_kernel(const FitDev* __restrict__ fi
   if (nfits == 1 && gsize == (int)gridDim.x) {
     gp.d = &fits[0];
     gp.ctl = fits[0].ctl;
-    if (ld_atomic(&gp.ctl->phase) != 2) fit_run(gp, S, max_rows);
+    if (ld_atomic(&gp.ctl->phase) != 2) fit_run<ANY_SEL>(gp, S, max_rows);
     return;
   }
   __shared__ int fid_s;
@@ -1521,8 +1717,22 @@ __global__ void __launch_bounds__(NTHR) fit_kernel(const FitDev* __restrict__ fi
     gp.ctl = fits[fid].ctl;
     gp.g = 0;
     gp.G = 1;
-    if (ld_atomic(&gp.ctl->phase) != 2) fit_run(gp, S, max_rows);
+    if (ld_atomic(&gp.ctl->phase) != 2) fit_run<ANY_SEL>(gp, S, max_rows);
   }
+}
+
+// FastSTMF (TD_A) fits.
+__global__ void __launch_bounds__(NTHR) fit_kernel(const FitDev* __restrict__ fits, int nfits,
+                                                   int gsize, int max_rows,
+                                                   unsigned* __restrict__ queue) {
+  fit_kernel_body<false>(fits, nfits, gsize, max_rows, queue);
+}
+
+// Fits with any ByRow selection (all fits of one launch share it).
+__global__ void __launch_bounds__(NTHR) fit_kernel_sel(const FitDev* __restrict__ fits, int nfits,
+                                                       int gsize, int max_rows,
+                                                       unsigned* __restrict__ queue) {
+  fit_kernel_body<true>(fits, nfits, gsize, max_rows, queue);
 }
 
 size_t fit_smem_bytes() { return sizeof(Smem); }

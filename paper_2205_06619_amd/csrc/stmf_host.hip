@@ -16,6 +16,7 @@ namespace stmf {
 
 // kernels (stmf_fit.hip, stmf_prims.hip, stmf_setup.hip)
 __global__ void fit_kernel(const FitDev* fits, int nfits, int gsize, int max_rows, unsigned* queue);
+__global__ void fit_kernel_sel(const FitDev* fits, int nfits, int gsize, int max_rows, unsigned* queue);
 size_t fit_smem_bytes();
 size_t masked_error_ws(int m, int n);
 hipError_t launch_maxplus(const float*, const float*, int, int, int, float*, int32_t*, hipStream_t);
@@ -29,6 +30,8 @@ __global__ void fill_u32_kernel(unsigned*, size_t, unsigned);
 __global__ void pack_kernel(const float*, const uint8_t*, int, int, int, int, int, int, const int*,
                             float*);
 __global__ void transpose_kernel(const float*, int, int, float*);
+__global__ void rowmin_kernel(const float*, const uint8_t*, int, int, int, float*);
+__global__ void rank_perm_kernel(const float*, int, int*);
 __global__ void u0_given_kernel(const float*, int, int, int, float*);
 __global__ void u0_acol_kernel(const float*, int, int, int, int, int, int, const int*, float*);
 __global__ void vinit_kernel(const float*, const float*, int, int, int, int, int, float*);
@@ -90,9 +93,14 @@ static int device_props(DevProps& out) {
     const size_t smem = fit_smem_bytes();
     HIPCHK(hipFuncSetAttribute((const void*)fit_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)smem));
-    int per = 0;
+    HIPCHK(hipFuncSetAttribute((const void*)fit_kernel_sel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    // the two fit kernels share the LDS layout; the group size must suit both
+    int per = 0, per_sel = 0;
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)fit_kernel, NTHR, smem));
-    p.coresident = per * p.cus;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_sel, (const void*)fit_kernel_sel, NTHR,
+                                                        smem));
+    p.coresident = std::min(per, per_sel) * p.cus;
     p.ok = true;
   }
   out = p;
@@ -119,6 +127,7 @@ static int check_options(const stmf_options& o) {
   if (o.batch_first < 0 || o.batch_max < 0 || o.batch_max > TMAX) return STMF_EINVAL;
   if (o.group_size < 0 || o.log_cap < 0 || o.max_row_visits < 0) return STMF_EINVAL;
   if (!(o.eps >= 0.0)) return STMF_EINVAL;
+  if (o.selection < 0 || o.selection > 3 || o.perm_mode < 0 || o.perm_mode > 2) return STMF_EINVAL;
   return STMF_OK;
 }
 
@@ -128,7 +137,7 @@ struct Layout {
   int mw, nw, ldm, ldn, nrt, nct, ldmax, G, acol_p, tmax;
   int transposed;
   size_t Rw, RwT, Uc, V, td, tdpart, crow, ccol, colst, rowst, colpart, rowpart, order, rowt,
-      tvec, epart, eprime, closed, traj, ctl, dev, perm, stage, check, rowc, colc;
+      rord, tdrow, tvec, epart, eprime, closed, traj, ctl, dev, perm, stage, check, rowc, colc;
   size_t total;
 };
 
@@ -169,6 +178,8 @@ static void make_layout(int m, int n, int r, int iters, int G, int acol_p, int b
   L.colpart = take((size_t)L.nrt * L.ldn * sizeof(Top2));
   L.rowpart = take((size_t)L.nct * L.ldm * sizeof(Top2));
   L.order = take((size_t)L.ldn * 4);
+  L.rord = take((size_t)L.ldn * 4);
+  L.tdrow = take((size_t)L.ldn * 8);
   L.tvec = take((size_t)2 * L.tmax * L.ldmax * 4);
   L.epart = take((size_t)L.tmax * G * 8);
   L.eprime = take((size_t)L.tmax * 8);
@@ -210,6 +221,7 @@ static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int o
   d.log_cap = o.decision_log ? o.log_cap : 0;
   d.eps = o.eps;
   d.omega = observed;
+  d.sel = o.selection;
   d.Rw = (const float*)(base + L.Rw);
   d.RwT = (const float*)(base + L.RwT);
   d.Uc = (float*)(base + L.Uc);
@@ -223,6 +235,8 @@ static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int o
   d.colpart = (Top2*)(base + L.colpart);
   d.rowpart = (Top2*)(base + L.rowpart);
   d.order = (int*)(base + L.order);
+  d.rord = (int*)(base + L.rord);
+  d.tdrow = (double*)(base + L.tdrow);
   d.tvec = (unsigned*)(base + L.tvec);
   d.epart = (double*)(base + L.epart);
   d.eprime = (double*)(base + L.eprime);
@@ -271,8 +285,10 @@ static int check_inputs(const float* R, const uint8_t* M, const Layout& L, char*
   return STMF_OK;
 }
 
-// Draws of a fit from its seed: the working permutation (unless given), then
-// the initial U (random integers) or the Random Acol column indices.
+// Draws of a fit from its seed: the working permutation (unless given, or
+// PermR / none), then the initial U (random integers) or the Random Acol
+// column indices.  The PermR order is data-dependent: prepare_fit computes it
+// on the device, and perm holds the identity until then.
 static int draw_setup(const Layout& L, uint64_t seed, const stmf_options& o,
                       std::vector<int32_t>& perm, std::vector<float>& U0, std::vector<int32_t>& cols) {
   Rng g{seed};
@@ -287,7 +303,7 @@ static int draw_setup(const Layout& L, uint64_t seed, const stmf_options& o,
     }
   } else {
     for (int a = 0; a < L.mw; ++a) perm[a] = a;
-    for (int a = L.mw - 1; a >= 1; --a) {
+    for (int a = o.perm_mode == 0 ? L.mw - 1 : 0; a >= 1; --a) {
       int b = (int)g.below((uint64_t)a + 1);
       std::swap(perm[a], perm[b]);
     }
@@ -318,7 +334,18 @@ static int prepare_fit(const float* R, const uint8_t* M, const Layout& L, char* 
       if (!(std::fabs(x) < 16777216.0f)) return STMF_ERANGE;
   for (float x : U0)
     if (!std::isfinite(x) || std::fabs(x) >= 1e30f) return STMF_ERANGE;
-  HIPCHK(hipMemcpyAsync(base + L.perm, perm.data(), perm.size() * 4, hipMemcpyHostToDevice, s));
+  if (o.perm_mode == 1 && !o.perm) {
+    // PermR: minimum observed value of every working row, then the stable
+    // order by it (both on the device; the minima use the staging buffer,
+    // which the initial U overwrites later in stream order)
+    hipLaunchKernelGGL(rowmin_kernel, dim3(L.mw), dim3(256), 0, s, R, M, L.n, L.nw, L.transposed,
+                       (float*)(base + L.stage));
+    hipLaunchKernelGGL(rank_perm_kernel, dim3((L.mw + 255) / 256), dim3(256), 0, s,
+                       (const float*)(base + L.stage), L.mw, (int*)(base + L.perm));
+    HIPCHK(hipGetLastError());
+  } else {
+    HIPCHK(hipMemcpyAsync(base + L.perm, perm.data(), perm.size() * 4, hipMemcpyHostToDevice, s));
+  }
   {
     dim3 grid((L.ldn + 255) / 256, L.ldm);
     hipLaunchKernelGGL(pack_kernel, grid, dim3(256), 0, s, R, M, L.n, L.mw, L.nw, L.ldm, L.ldn,
@@ -356,16 +383,23 @@ static int launch_output(const Layout& L, char* base, float* U_out, float* V_out
   return hipGetLastError() == hipSuccess ? STMF_OK : STMF_EHIP;
 }
 
+// sel: the ByRow selection of every fit of the launch (TD_A runs the kernel
+// compiled for it alone).
 static int launch_fit_kernel(const FitDev* dev_fits, int nfits, int G, int grid, int max_rows,
-                             unsigned* queue, hipStream_t s) {
+                             unsigned* queue, int sel, hipStream_t s) {
   const size_t smem = fit_smem_bytes();
   if (G > 1) {
     void* args[] = {(void*)&dev_fits, (void*)&nfits, (void*)&G, (void*)&max_rows, (void*)&queue};
-    HIPCHK(hipLaunchCooperativeKernel((const void*)fit_kernel, dim3(grid), dim3(NTHR), args,
-                                      (unsigned)smem, s));
+    HIPCHK(hipLaunchCooperativeKernel(sel == SEL_TD_A ? (const void*)fit_kernel
+                                                      : (const void*)fit_kernel_sel,
+                                      dim3(grid), dim3(NTHR), args, (unsigned)smem, s));
   } else {
-    hipLaunchKernelGGL(fit_kernel, dim3(grid), dim3(NTHR), smem, s, dev_fits, nfits, G, max_rows,
-                       queue);
+    if (sel == SEL_TD_A)
+      hipLaunchKernelGGL(fit_kernel, dim3(grid), dim3(NTHR), smem, s, dev_fits, nfits, G, max_rows,
+                         queue);
+    else
+      hipLaunchKernelGGL(fit_kernel_sel, dim3(grid), dim3(NTHR), smem, s, dev_fits, nfits, G,
+                         max_rows, queue);
     HIPCHK(hipGetLastError());
   }
   return STMF_OK;
@@ -499,6 +533,7 @@ int stmf_draw_init(int m, int n, int rank, uint64_t seed, const stmf_options* op
   int st = resolve(opt, o);
   if (st) return st;
   if (m < 1 || n < 1 || rank < 1 || rank > RMAX) return STMF_EINVAL;
+  if (o.perm_mode == 1 && !o.perm) return STMF_EINVAL;  // the PermR order is not a draw
   Layout L;
   make_layout(m, n, rank, 0, 1, o.acol_p, o.batch_max, L);
   std::vector<int32_t> perm, cols;
@@ -549,7 +584,8 @@ int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters
   HIPCHK(hipEventCreate(&ev0));
   HIPCHK(hipEventCreate(&ev1));
   HIPCHK(hipEventRecord(ev0, s));
-  st = launch_fit_kernel((const FitDev*)(base + L.dev), 1, G, G, o.max_row_visits, nullptr, s);
+  st = launch_fit_kernel((const FitDev*)(base + L.dev), 1, G, G, o.max_row_visits, nullptr,
+                         o.selection, s);
   if (st) { (void)hipEventDestroy(ev0); (void)hipEventDestroy(ev1); return st; }
   HIPCHK(hipEventRecord(ev1, s));
   FitCtl c;
@@ -673,7 +709,7 @@ int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts, const stmf_op
     if (st) return st;
     const int grid = std::min<int>((int)table.size(), P.coresident);
     st = launch_fit_kernel((const FitDev*)(base + B.table), (int)table.size(), 1, grid, 0,
-                           (unsigned*)(base + B.queue), s);
+                           (unsigned*)(base + B.queue), o.selection, s);
     if (st) return st;
   }
   HIPCHK(hipStreamSynchronize(s));  // host staging vectors go out of scope after this
@@ -848,7 +884,7 @@ int stmf_batch_tick(stmf_engine* e, int max_rows, void* stream) {
   if (st) return st;
   const int grid = std::min<int>((int)table.size(), P.coresident);
   st = launch_fit_kernel((const FitDev*)(e->arena + e->table_off), (int)table.size(), 1, grid,
-                         max_rows, (unsigned*)(e->arena + e->queue_off), s);
+                         max_rows, (unsigned*)(e->arena + e->queue_off), e->opt.selection, s);
   if (st) return st;
   // the table is read by the launch: wait for it before the host array changes
   HIPCHK(hipStreamSynchronize(s));

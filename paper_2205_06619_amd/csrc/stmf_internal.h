@@ -35,6 +35,9 @@ struct Top2 {
 
 enum Op : int { OP_ULF = 0, OP_URF = 1, OP_NULL = 2 };
 
+// ByRow selections of (j, k) within a row visit (Sec. 3.2.1).
+enum Sel : int { SEL_TD_A = 0, SEL_TD = 1, SEL_TD_B = 2, SEL_SEQ = 3 };
+
 struct Trial {
   int j, k, op;
   float val;   // the step-2 value written at (i, k) of U (F-ULF) or (k, j) of V (F-URF)
@@ -97,6 +100,7 @@ struct FitDev {
   int t0;                // first batch of a row visit
   int log_cap;
   int omega;             // number of observed cells
+  int sel;               // Sel
   double eps;
   STMF_G(const float) Rw;    // ldm x ldn, +inf at unobserved and padding cells
   STMF_G(const float) RwT;   // ldn x ldm, the transpose
@@ -111,6 +115,8 @@ struct FitDev {
   STMF_G(Top2) colpart;      // nrt x ldn: per row-tile partial of colst (one component)
   STMF_G(Top2) rowpart;      // nct x ldm
   STMF_G(int) order;         // ldn: columns by (td_col desc, index asc)
+  STMF_G(int) rord;          // ldn: TD order of the visited row's columns
+  STMF_G(double) tdrow;      // ldn: TD keys of the visited row (wide matrices)
   STMF_G(unsigned) tvec;     // 2 x TMAX x ldmax: atomic-min targets (order-mapped floats)
   STMF_G(double) epart;      // TMAX x gsize: per-workgroup partial errors
   STMF_G(double) eprime;     // TMAX: error of every trial of the batch

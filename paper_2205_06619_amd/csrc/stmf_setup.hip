@@ -1,5 +1,6 @@
 // Set-up and output steps of a fit (Algorithm 3): input checks, the working
-// matrix (transposed when R is not wide, rows permuted, missing cells as
+// matrix (transposed when R is not wide, rows permuted or in the PermR order
+// of Sec. 3.2, missing cells as
 // +inf), the initial U (given, random integers drawn on the host, or Random
 // Acol averages), the initial V = (-U)^T (x)* R for every component, and the
 // un-permuted, un-transposed output.
@@ -62,6 +63,45 @@ __global__ void pack_kernel(const float* __restrict__ R, const uint8_t* __restri
     if (M[idx]) v = R[idx] + 0.0f;
   }
   Rw[(size_t)a * ldn + b] = v;
+}
+
+// PermR (Sec. 3.2), first step: mn[a] = the minimum observed value of
+// working row a (original row a, or original column a when transposed), one
+// workgroup of 256 threads per row.  Every row has an observed cell (checked
+// before).  -0 and +0 compare equal, so the order never depends on the sign
+// of a zero.
+__global__ void __launch_bounds__(256) rowmin_kernel(const float* __restrict__ R,
+                                                     const uint8_t* __restrict__ M, int n_in,
+                                                     int nw, int transposed, float* __restrict__ mn) {
+  __shared__ float part[256];
+  const int a = blockIdx.x;
+  float best = SINF;
+  for (int b = threadIdx.x; b < nw; b += 256) {
+    const size_t idx = transposed ? ((size_t)b * n_in + a) : ((size_t)a * n_in + b);
+    if (M[idx]) best = fminf(best, R[idx]);
+  }
+  part[threadIdx.x] = best;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] = fminf(part[threadIdx.x], part[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) mn[a] = part[0] + 0.0f;
+}
+
+// PermR, second step: the stable order of the rows by increasing minimum,
+// perm[rank of a] = a, the rank counting the rows with a smaller minimum or
+// an equal one at a lower index.
+__global__ void rank_perm_kernel(const float* __restrict__ mn, int mw, int* __restrict__ perm) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= mw) return;
+  const float v = mn[a];
+  int rank = 0;
+  for (int b = 0; b < mw; ++b) {
+    const float o = mn[b];
+    rank += (o < v || (o == v && b < a)) ? 1 : 0;
+  }
+  perm[rank] = a;
 }
 
 // RwT = Rw^T through 64 x 64 LDS tiles.

@@ -74,6 +74,10 @@ def test_argument_errors_before_any_gpu_work(stmf):
     o = stmf.options(batch_first=-1)
     assert L.stmf_fit(dummy, dummy, 4, 4, 2, 1, 0, dummy, dummy, None, C.byref(o), None,
                       C.c_void_p(256), 1 << 30, None) == stmf.STMF_EINVAL
+    for bad in (dict(selection=4), dict(selection=-1), dict(perm_mode=3), dict(perm_mode=-1)):
+        o = stmf.options(**bad)
+        assert L.stmf_fit(dummy, dummy, 4, 4, 2, 1, 0, dummy, dummy, None, C.byref(o), None,
+                          C.c_void_p(256), 1 << 30, None) == stmf.STMF_EINVAL
     o = stmf.options()
     assert L.stmf_fit(dummy, dummy, 4, 4, 0, 1, 0, dummy, dummy, None, C.byref(o), None,
                       C.c_void_p(256), 1 << 30, None) == stmf.STMF_EINVAL
@@ -91,6 +95,20 @@ def test_library_draws_equal_oracle_draws(stmf, m, n, rank, seed):
     assert s == 0
     np.testing.assert_array_equal(perm, operm)
     np.testing.assert_array_equal(U0.reshape(oU0.shape), oU0)
+
+
+@pytest.mark.parametrize("m,n", [(20, 30), (30, 20)])
+def test_library_draws_without_permutation(stmf, m, n):
+    # perm_mode 2: no permutation, the stream starts with U0; perm_mode 1
+    # (PermR) depends on R, so the draw-only call refuses it
+    perm, U0 = stmf.stmf_draw_init(m, n, 3, 5, perm_mode=2)
+    R = np.zeros((m, n), np.float32); M = np.ones((m, n), np.uint8)
+    s, operm, oU0 = oracle.draw_init(R, M, 3, 5, perm_mode=2)
+    np.testing.assert_array_equal(perm, np.arange(min(m, n)))
+    np.testing.assert_array_equal(perm, operm)
+    np.testing.assert_array_equal(U0.reshape(oU0.shape), oU0)
+    with pytest.raises(stmf.StmfError):
+        stmf.stmf_draw_init(m, n, 3, 5, perm_mode=1)
 
 
 def test_library_acol_draws_equal_oracle(stmf):
