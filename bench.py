@@ -14,12 +14,14 @@ masked max-plus GOP/s as the paper defines its work (2 r |Omega| per
 evaluation), the fit kernel's roofline against the VALU ceiling, and the CPU
 oracle timed on a bounded prefix of the same workload.
 
-Two smaller comparisons follow the headline step (skipped with --no-extras):
+Three smaller comparisons follow the headline step (skipped with --no-extras):
 "batched" runs uneven integer problems with restarts in one persistent
 launch and through the plain one-fit-at-a-time path (results compared bit
 for bit); "serving" replays a Poisson stream of completion jobs through the
 continuous-batching loop and through the plain sequential path (p50/p99
-latency, jobs/s).  Both are scaled down from the batched and serving
+latency, jobs/s); "selections" runs the other ByRow selections (TD, TD_B,
+SEQ) and the PermR row order on the headline matrix for a few passes each.
+The first two are scaled down from the batched and serving
 workloads (shapes, ranks and passes stated in their "config") so that the
 default run stays within minutes.
 """
@@ -142,6 +144,45 @@ def serving_compare():
     }
 
 
+SELECTIONS = [  # (name, selection, perm_mode, passes)
+    ("TD_A, PermR", 0, 1, 10), ("TD", 1, 0, 10), ("TD_B", 2, 0, 10), ("SEQ", 3, 0, 1),
+]
+
+
+def selections_compare(Rd, Md, omega):
+    """The other ByRow selections and row orders on the headline workload,
+    for a few passes each (SEQ evaluates every trial of a row: one pass)."""
+    from paper_2205_06619_amd import stmf
+    w = WORKLOAD
+    mw, nw = min(Rd.shape), max(Rd.shape)
+    out = []
+    for name, sel, pm, passes in SELECTIONS:
+        opt = stmf.options(init_mode=1, selection=sel, perm_mode=pm)
+        t0 = time.perf_counter()
+        r = stmf.stmf_fit(Rd, Md, w["rank"], passes, seed=w["seed"], opt=opt)
+        wall = time.perf_counter() - t0
+        kernel_s = r.info["kernel_ms"] / 1e3
+        trials = r.info["trials"]
+        ops = trials * (2 * w["rank"] + 6) * omega
+        out.append({
+            "selection": name,
+            "passes": passes,
+            "wall_s": wall,
+            "kernel_ms": r.info["kernel_ms"],
+            "trials": trials,
+            "spec_trials": r.info["spec_trials"],
+            "accepted": r.info["accepted"],
+            "updates_per_s": trials * (mw + nw + 1) / wall,
+            "maxplus_gops": trials * 2 * w["rank"] * omega / wall / 1e9,
+            "alu_frac": ops / kernel_s / VALU_PEAK_OPS,
+            "error_after": float(r.traj[-1]),
+        })
+    return {"config": {"workload": f"{w['name']} {w['m']}x{w['n']}, rank {w['rank']}, "
+                                   f"{w['init']} init, seed {w['seed']}; passes per selection "
+                                   f"as listed"},
+            "runs": out}
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2205_06619_amd", "csrc")
@@ -207,8 +248,10 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=16,
                     help="row visits of the oracle's CPU-baseline sample (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--selections-only", action="store_true",
+                    help="run only the selection comparison (one JSON line)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched and serving comparisons")
+                    help="skip the batched, serving and selection comparisons")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs a fit on a single MI355X "
@@ -230,6 +273,10 @@ def main():
     mw, nw = min(R.shape), max(R.shape)
     opt = stmf.options(init_mode=1)
     ws = stmf.workspace(stmf.stmf_fit_workspace(w["m"], w["n"], w["rank"], w["iters"], opt))
+
+    if args.selections_only:
+        print(json.dumps(selections_compare(Rd, Md, omega)), flush=True)
+        return
 
     def step():
         return stmf.stmf_fit(Rd, Md, w["rank"], w["iters"], seed=w["seed"], opt=opt, ws=ws)
@@ -292,6 +339,7 @@ def main():
     if not args.no_extras:
         out["batched"] = batched_compare()
         out["serving"] = serving_compare()
+        out["selections"] = selections_compare(Rd, Md, omega)
     print(json.dumps(out), flush=True)
 
 
