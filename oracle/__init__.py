@@ -33,6 +33,7 @@ class Opts(C.Structure):
         ("integer_exact", C.c_int),
         ("selection", C.c_int),
         ("perm_mode", C.c_int),
+        ("strategy", C.c_int),
     ]
 
 
@@ -166,7 +167,8 @@ class FitResult:
 
 
 def make_opts(init_mode=0, init_lo=0.0, init_hi=100.0, acol_p=5, U0=None, perm=None,
-              eps=0.0, count_scope=0, noop_rule=1, integer_exact=0, selection=0, perm_mode=0):
+              eps=0.0, count_scope=0, noop_rule=1, integer_exact=0, selection=0, perm_mode=0,
+              strategy=0):
     o = Opts()
     o.init_mode = init_mode; o.init_lo = init_lo; o.init_hi = init_hi; o.acol_p = acol_p
     keep = []
@@ -176,7 +178,7 @@ def make_opts(init_mode=0, init_lo=0.0, init_hi=100.0, acol_p=5, U0=None, perm=N
         perm = _c(perm, np.int32); keep.append(perm); o.perm = perm.ctypes.data
     o.eps = eps; o.count_scope = count_scope; o.noop_rule = noop_rule
     o.integer_exact = integer_exact
-    o.selection = selection; o.perm_mode = perm_mode
+    o.selection = selection; o.perm_mode = perm_mode; o.strategy = strategy
     return o, keep
 
 

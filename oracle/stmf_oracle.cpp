@@ -17,6 +17,9 @@
 //   * FastSTMF = ByRow, random row permutation, TD_A, wide    Algorithm 3
 //   * the other ByRow selections TD, TD_B and SEQ, and the row orders PermR
 //     (rows by increasing minimum) and none                   Sec. 3.2.1, 3.3
+//   * ByElement with PermC (columns by increasing minimum), TD
+//     selection of k                          Sec. 3.2.2, supplementary
+//                                             ByElement pseudocode
 //
 // Every routine is a template over the value type T.  T = double is "the FP64
 // oracle": all value arithmetic in double on exactly promoted FP32 inputs.
@@ -56,6 +59,16 @@
 //     one is applied (ties: the first in that order);
 //   - PermR: working rows by increasing minimum observed value, ties by the
 //     lower original index.
+//   - ByElement: the working rows in order (PermC permutes only columns),
+//     in each row its observed columns in working column order; k = f(i, j);
+//     an entry with R_ij = (U (x) V)_ij (td = 0) is not updated; F-ULF, and
+//     F-URF after a rejected F-ULF; an accepted update does not end the row
+//     visit, the next element follows; a pass with no accepted update is a
+//     fixed point.  Log: one record per accepted update (trials and no-op
+//     skips since the previous record of the visit) and one closing record
+//     per row visit (j = -1);
+//   - PermC: working columns by increasing minimum observed value, ties by
+//     the lower working index; V's columns are put back at the output.
 //
 // Parity of the TD_A counting scope, the candidate tie order, the Random-Acol
 // column count and the random stream is unpinned: the paper fixes none of
@@ -212,10 +225,13 @@ struct oracle_opts {
   int noop_rule;         // 1: skip no-op trials as rejected
   int integer_exact;     // 1: reject |value| >= 2^24
   int selection;         // 0 TD_A, 1 TD, 2 TD_B, 3 SEQ
-  int perm_mode;         // 0 random, 1 PermR (increasing minimum), 2 none
+  int perm_mode;         // 0 random, 1 PermR (increasing minimum), 2 none,
+                         // 3 PermC (columns by increasing minimum, rows as given)
+  int strategy;          // 0 ByRow, 1 ByElement
 };
 
-struct oracle_log {      // one record per row visit
+struct oracle_log {      // ByRow: one record per row visit; ByElement: one per
+                         // accepted update and one closing each row visit
   int32_t iter, row, trials, noops, j, k, op;  // j = -1: nothing accepted
   int32_t pad;
   double e;
@@ -281,6 +297,7 @@ struct Working {
   std::vector<float> R;
   std::vector<uint8_t> M;
   std::vector<int32_t> perm;
+  std::vector<int32_t> cperm;  // working column b is column cperm[b]
 };
 
 int build_working(const float* R, const uint8_t* M, int m, int n,
@@ -290,7 +307,29 @@ int build_working(const float* R, const uint8_t* M, int m, int n,
   w.m = w.transposed ? n : m;
   w.n = w.transposed ? m : n;
   w.perm.resize(w.m);
-  if (o && (o->perm_mode < 0 || o->perm_mode > 2)) return EINVAL_;
+  if (o && (o->perm_mode < 0 || o->perm_mode > 3)) return EINVAL_;
+  // minimum observed value of working line a (a row, or with cols a column)
+  auto line_min = [&](int a, bool cols) {
+    float mn = 0.0f;
+    bool seen = false;
+    const int len = cols ? w.m : w.n;
+    for (int b = 0; b < len; ++b) {
+      const int wr = cols ? b : a, wc = cols ? a : b;
+      size_t s = w.transposed ? ((size_t)wc * n + wr) : ((size_t)wr * n + wc);
+      if (!M[s]) continue;
+      float v = R[s] + 0.0f;
+      if (!seen || v < mn) { mn = v; seen = true; }
+    }
+    return mn;
+  };
+  w.cperm.resize(w.n);
+  for (int b = 0; b < w.n; ++b) w.cperm[b] = b;
+  if (o && o->perm_mode == 3) {
+    // PermC: working columns by increasing minimum observed value, stable
+    std::vector<float> mn(w.n);
+    for (int b = 0; b < w.n; ++b) mn[b] = line_min(b, true);
+    std::stable_sort(w.cperm.begin(), w.cperm.end(), [&](int x, int y) { return mn[x] < mn[y]; });
+  }
   if (o && o->perm) {
     std::vector<char> hit(w.m, 0);
     for (int a = 0; a < w.m; ++a) {
@@ -302,18 +341,10 @@ int build_working(const float* R, const uint8_t* M, int m, int n,
   } else if (o && o->perm_mode == 1) {
     // PermR: working rows by increasing minimum observed value, stable
     std::vector<float> mn(w.m, 0.0f);
-    for (int a = 0; a < w.m; ++a) {
-      bool seen = false;
-      for (int b = 0; b < w.n; ++b) {
-        size_t s = w.transposed ? ((size_t)b * n + a) : ((size_t)a * n + b);
-        if (!M[s]) continue;
-        float v = R[s] + 0.0f;
-        if (!seen || v < mn[a]) { mn[a] = v; seen = true; }
-      }
-    }
+    for (int a = 0; a < w.m; ++a) mn[a] = line_min(a, false);
     for (int a = 0; a < w.m; ++a) w.perm[a] = a;
     std::stable_sort(w.perm.begin(), w.perm.end(), [&](int x, int y) { return mn[x] < mn[y]; });
-  } else if (o && o->perm_mode == 2) {
+  } else if (o && (o->perm_mode == 2 || o->perm_mode == 3)) {
     for (int a = 0; a < w.m; ++a) w.perm[a] = a;
   } else {
     for (int a = 0; a < w.m; ++a) w.perm[a] = a;
@@ -327,8 +358,8 @@ int build_working(const float* R, const uint8_t* M, int m, int n,
   w.M.assign((size_t)w.m * w.n, 0);
   for (int a = 0; a < w.m; ++a)
     for (int b = 0; b < w.n; ++b) {
-      int src = w.perm[a];
-      size_t s = w.transposed ? ((size_t)b * n + src) : ((size_t)src * n + b);
+      int src = w.perm[a], csrc = w.cperm[b];
+      size_t s = w.transposed ? ((size_t)csrc * n + src) : ((size_t)src * n + csrc);
       uint8_t obs = M[s] ? 1 : 0;
       w.M[(size_t)a * w.n + b] = obs;
       // -0 becomes +0; unobserved values are never read into arithmetic.
@@ -438,6 +469,8 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
   const double eps = o ? o->eps : 0.0;
   const int sel = o ? o->selection : 0;
   if (sel < 0 || sel > 3) return EINVAL_;
+  const int strategy = o ? o->strategy : 0;
+  if (strategy < 0 || strategy > 1) return EINVAL_;
 
   int it_done = 0;
   bool stop = false;
@@ -492,6 +525,38 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
         }
         return best;
       };
+      if (strategy == 1) {
+        // ByElement: every observed (i, j) of the row in working column
+        // order, k = f(i, j), F-ULF then F-URF; a perfect entry (td = 0) is
+        // not updated; after an accepted update the visit goes on with the
+        // next element
+        for (int j = 0; j < n; ++j) {
+          if (!M[(size_t)i * n + j]) continue;
+          T best = U[(size_t)i * r] + V[j];
+          int k = 0;
+          for (int l = 1; l < r; ++l) {
+            T x = U[(size_t)i * r + l] + V[(size_t)l * n + j];
+            if (x > best) { best = x; k = l; }
+          }
+          if ((T)(R[(size_t)i * n + j] - best) == (T)0) continue;
+          accepted = false;
+          for (int op = 0; op < 2 && !accepted; ++op) {
+            double e2;
+            if (!try_op(j, k, op, e2)) continue;
+            if (e2 < e) accept(j, k, op, e2);
+            else restore(k);
+          }
+          if (accepted) {
+            if (log && nlog < log_cap) log[nlog] = rec;
+            nlog++;
+            rec = oracle_log{it, i, 0, 0, -1, -1, -1, 0, e};
+          }
+        }
+        rec.e = e;
+        if (log && nlog < log_cap) log[nlog] = rec;
+        nlog++;
+        continue;
+      }
       std::vector<int> cand;  // observed columns of row i
       for (int j = 0; j < n; ++j)
         if (M[(size_t)i * n + j]) cand.push_back(j);
@@ -594,15 +659,18 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
   std::vector<float> Uw((size_t)m * r);
   for (int a = 0; a < m; ++a)
     for (int l = 0; l < r; ++l) Uw[(size_t)w.perm[a] * r + l] = (float)U[(size_t)a * r + l];
+  // working column b goes back to column cperm[b]
+  std::vector<float> Vw((size_t)r * n);
+  for (int l = 0; l < r; ++l)
+    for (int b = 0; b < n; ++b) Vw[(size_t)l * n + w.cperm[b]] = (float)V[(size_t)l * n + b];
   if (!w.transposed) {
     if (U_out) std::memcpy(U_out, Uw.data(), sizeof(float) * Uw.size());
-    if (V_out)
-      for (size_t q = 0; q < V.size(); ++q) V_out[q] = (float)V[q];
+    if (V_out) std::memcpy(V_out, Vw.data(), sizeof(float) * Vw.size());
   } else {
     // original is n x m' ... U_out (m_in x r) = V_w^T, V_out (r x n_in) = U_unperm^T
     if (U_out)
       for (int a = 0; a < m_in; ++a)
-        for (int l = 0; l < r; ++l) U_out[(size_t)a * r + l] = (float)V[(size_t)l * n + a];
+        for (int l = 0; l < r; ++l) U_out[(size_t)a * r + l] = Vw[(size_t)l * n + a];
     if (V_out)
       for (int l = 0; l < r; ++l)
         for (int b = 0; b < n_in; ++b) V_out[(size_t)l * n_in + b] = Uw[(size_t)b * r + l];

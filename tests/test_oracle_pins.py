@@ -483,7 +483,145 @@ def test_selection_defaults_are_faststmf():
     b = oracle.fit(R, M, 3, 3, seed=6, prec="f32", selection=0, perm_mode=0)
     np.testing.assert_array_equal(a.U, b.U); np.testing.assert_array_equal(a.traj, b.traj)
     assert oracle.fit(R, M, 3, 1, selection=4).status == 1
-    assert oracle.fit(R, M, 3, 1, perm_mode=3).status == 1
+    assert oracle.fit(R, M, 3, 1, perm_mode=4).status == 1
+    assert oracle.fit(R, M, 3, 1, strategy=2).status == 1
+
+
+# ------------------------------------------------------------------ ByElement
+def _brute_force_byelement(R, M, U, V, iters, prec, noop_rule=True):
+    """Independent restatement of ByElement (Sec. 3.2.2 and its supplementary
+    pseudocode) on an already-permuted working matrix: rows in order, each
+    row's observed columns in order, k = f(i, j) from the entry's own
+    max-plus terms, entries with td = 0 skipped, F-ULF then F-URF evaluated
+    from scratch by the pinned update routine, the first strict decrease
+    accepted and the visit continued.  Returns the log records (one per
+    accepted update, one closing each row visit), U, V and the trajectory."""
+    m, n = R.shape; r = U.shape[1]
+    T = np.float32 if prec == "f32" else np.float64
+    e, _, _ = oracle.masked_error(R, M, U, V, prec)
+    closed = [False] * r
+    recs, traj = [], [e]
+    for it in range(1, iters + 1):
+        acc_pass = 0
+        for i in range(m):
+            seg = [0, 0]
+            for j in range(n):
+                if not M[i, j]:
+                    continue
+                if T(T(R[i, j]) - _maxplus_entry(U, V, i, j, T)) == 0:
+                    continue
+                k = _argmax_entry(U, V, i, j, T)
+                for op in ("U", "V"):
+                    if noop_rule and closed[k]:
+                        same = (T(T(R[i, j]) - T(V[k, j])) == T(U[i, k])) if op == "U" else \
+                               (T(T(R[i, j]) - T(U[i, k])) == T(V[k, j]))
+                        if same:
+                            seg[1] += 1
+                            continue
+                    U2, V2, e2, *_ = oracle.update(op, R, M, U, V, i, j, k, prec)
+                    seg[0] += 1
+                    if e2 < e:
+                        U, V, e = U2, V2, e2
+                        closed[k] = True
+                        acc_pass += 1
+                        recs.append((it, i, seg[0], seg[1], j, k, 0 if op == "U" else 1, e))
+                        seg = [0, 0]
+                        break
+            recs.append((it, i, seg[0], seg[1], -1, -1, -1, e))
+        traj.append(e)
+        if acc_pass == 0:
+            traj += [e] * (iters - it)
+            break
+    return recs, U, V, traj
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("seed", range(4))
+def test_byelement_matches_brute_force(prec, seed):
+    m, n, r = 5, 8, 3
+    R, M = synth.tiny_int_case(m, n, r, 80 + seed, hi=9, missing=0.25, planted=seed % 2 == 0)
+    U0 = np.random.default_rng(seed).integers(0, 10, (m, r)).astype(np.float32)
+    iters = 3
+    res = oracle.fit(R, M, r, iters, prec=prec, init_mode=2, U0=U0, perm_mode=2, strategy=1,
+                     log_cap=4000)
+    assert res.status == 0
+    U = U0.astype(np.float64); V = np.zeros((r, n))
+    for k in range(r):
+        V = oracle.col_res(R, M, U, V, k, prec)
+    recs, Ub, Vb, traj = _brute_force_byelement(R, M, U, V, iters, prec)
+    got = [(int(x["iter"]), int(x["row"]), int(x["trials"]), int(x["noops"]), int(x["j"]),
+            int(x["k"]), int(x["op"]), float(x["e"])) for x in res.log]
+    assert got == recs
+    assert sum(1 for x in recs if x[4] >= 0) > 0
+    np.testing.assert_array_equal(res.U, Ub.astype(np.float32))
+    np.testing.assert_array_equal(res.V, Vb.astype(np.float32))
+    np.testing.assert_array_equal(res.traj, traj)
+
+
+def test_byelement_at_an_exact_factorization_tries_nothing():
+    # R = U* (x) V* fully observed and U0 = U*: the initial V is the principal
+    # solution, every entry is exact (td = 0), so ByElement evaluates no
+    # trial and the first pass is a fixed point; ByRow still tries (and
+    # rejects) candidates
+    rng = np.random.default_rng(3)
+    Us = rng.integers(0, 20, (6, 2)).astype(np.float32)
+    Vs = rng.integers(0, 20, (2, 9)).astype(np.float32)
+    R = np.max(Us[:, :, None] + Vs[None, :, :], axis=1).astype(np.float32)
+    M = np.ones_like(R, np.uint8)
+    a = oracle.fit(R, M, 2, 3, prec="f64", init_mode=2, U0=Us, perm_mode=2, strategy=1)
+    assert a.status == 0 and a.stats["trials"] == 0 and a.stats["accepted"] == 0
+    np.testing.assert_array_equal(a.traj, [0.0] * 4)
+    b = oracle.fit(R, M, 2, 1, prec="f64", init_mode=2, U0=Us, perm_mode=2)
+    assert b.stats["trials"] > 0 and b.stats["accepted"] == 0
+
+
+def _col_minima_order(R, M):
+    mins = np.where(M == 1, R, np.inf).min(axis=0)
+    return np.argsort(mins, kind="stable")
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("strategy", [0, 1])
+def test_permc_orders_columns_by_increasing_minimum(transpose, strategy):
+    # PermC (Sec. 3.2): the fit on R with PermC equals the fit on R with its
+    # working columns put in numpy's stable order of the column minima (and
+    # no permutation), with V's columns put back
+    R, M = synth.int_planted(9, 17, 2, seed=19, hi=30)
+    R = R.copy(); R[M == 0] = -500.0     # unobserved values never count
+    R[:, 4] = R[:, 11]; M[:, 4] = M[:, 11]  # two columns with the same minimum
+    kw = dict(prec="f32", init_hi=30, strategy=strategy, log_cap=2000)
+    if transpose:
+        R, M = R.T.copy(), M.T.copy()
+    Rw, Mw = (R.T, M.T) if transpose else (R, M)
+    cp = _col_minima_order(Rw, Mw)
+    a = oracle.fit(R, M, 2, 2, seed=8, perm_mode=3, **kw)
+    Rp, Mp = np.ascontiguousarray(Rw[:, cp]), np.ascontiguousarray(Mw[:, cp])
+    b = oracle.fit(Rp, Mp, 2, 2, seed=8, perm_mode=2, **kw)
+    assert a.status == 0 and b.status == 0
+    np.testing.assert_array_equal(a.traj, b.traj)
+    Ua, Va = (a.V.T, a.U.T) if transpose else (a.U, a.V)
+    np.testing.assert_array_equal(Ua, b.U)
+    np.testing.assert_array_equal(Va[:, cp], b.V)
+
+
+def test_byelement_trajectory_and_precisions():
+    R, M = synth.int_planted(20, 30, 3, seed=20)
+    kw = dict(seed=20, perm_mode=3, strategy=1, log_cap=20000)
+    a = oracle.fit(R, M, 3, 4, prec="f64", **kw)
+    b = oracle.fit(R, M, 3, 4, prec="f32", **kw)
+    assert a.status == 0
+    np.testing.assert_array_equal(a.traj, b.traj)
+    np.testing.assert_array_equal(a.U, b.U)
+    assert np.all(np.diff(a.traj) <= 0)
+    prev = a.traj[0]
+    for rec in a.log:
+        assert rec["e"] <= prev
+        if rec["j"] >= 0:
+            assert rec["e"] < prev
+        prev = rec["e"]
+    # several accepted updates in one row visit happen
+    rows = collections.Counter((int(x["iter"]), int(x["row"])) for x in a.log if x["j"] >= 0)
+    assert max(rows.values()) > 1
 
 
 @pytest.mark.parametrize("prec", PRECS)
