@@ -20,7 +20,8 @@ launch and through the plain one-fit-at-a-time path (results compared bit
 for bit); "serving" replays a Poisson stream of completion jobs through the
 continuous-batching loop and through the plain sequential path (p50/p99
 latency, jobs/s); "selections" runs the other ByRow selections (TD, TD_B,
-SEQ) and the PermR row order on the headline matrix for a few passes each.
+SEQ), ByElement with PermC and the PermR row order on the headline matrix
+for a few passes each.
 The first two are scaled down from the batched and serving
 workloads (shapes, ranks and passes stated in their "config") so that the
 default run stays within minutes.
@@ -144,20 +145,22 @@ def serving_compare():
     }
 
 
-SELECTIONS = [  # (name, selection, perm_mode, passes)
-    ("TD_A, PermR", 0, 1, 10), ("TD", 1, 0, 10), ("TD_B", 2, 0, 10), ("SEQ", 3, 0, 1),
+SELECTIONS = [  # (name, strategy, selection, perm_mode, passes)
+    ("TD_A, PermR", 0, 0, 1, 10), ("TD", 0, 1, 0, 10), ("TD_B", 0, 2, 0, 10), ("SEQ", 0, 3, 0, 1),
+    ("ByElement, PermC", 1, 0, 3, 1),
 ]
 
 
 def selections_compare(Rd, Md, omega):
-    """The other ByRow selections and row orders on the headline workload,
-    for a few passes each (SEQ evaluates every trial of a row: one pass)."""
+    """The other ByRow selections, ByElement and the row and column orders on
+    the headline workload, for a few passes each (SEQ evaluates every trial of
+    a row, ByElement every entry: one pass)."""
     from paper_2205_06619_amd import stmf
     w = WORKLOAD
     mw, nw = min(Rd.shape), max(Rd.shape)
     out = []
-    for name, sel, pm, passes in SELECTIONS:
-        opt = stmf.options(init_mode=1, selection=sel, perm_mode=pm)
+    for name, strategy, sel, pm, passes in SELECTIONS:
+        opt = stmf.options(init_mode=1, strategy=strategy, selection=sel, perm_mode=pm)
         t0 = time.perf_counter()
         r = stmf.stmf_fit(Rd, Md, w["rank"], passes, seed=w["seed"], opt=opt)
         wall = time.perf_counter() - t0

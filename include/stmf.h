@@ -153,8 +153,24 @@ typedef struct {
                            0 random permutation drawn from the seed (default),
                            1 PermR: rows by increasing minimum observed value,
                              ties by the lower working index,
-                           2 none (identity).  With 1 and 2 the seed's stream
-                           starts with the initial U.                           */
+                           2 none (identity),
+                           3 PermC: rows as given (perm, else identity) and the
+                             working columns by increasing minimum observed
+                             value, ties by the lower index (V's columns are
+                             put back at the output).
+                           With 1-3 the seed's stream starts with the initial U. */
+  int strategy;         /* 0 ByRow (default; Sec. 3.2.1, with `selection`),
+                           1 ByElement (Sec. 3.2.2 and its supplementary
+                             pseudocode): every observed entry of each working
+                             row in working column order, k = f(i, j), entries
+                             with R_ij = (U (x) V)_ij skipped, F-ULF then F-URF;
+                             an accepted update does not end the row visit.
+                             `selection` is ignored.  decision_log: one record
+                             per accepted update (trials and no-op skips since
+                             the previous record of the visit) and one closing
+                             each row visit (j = -1).  The paper's
+                             STMF_ByElement_PermC_TD_W is strategy 1 with
+                             perm_mode 3.                                       */
 } stmf_options;
 
 /* Per-row-visit decision record (decision_log). */

@@ -197,6 +197,7 @@ struct Smem {
   int cj[CW], ck[CW];
   float cvu[CW], cvv[CW];
   int cnu[CW], cnv[CW];
+  int cskip[CW];             // ByElement: an exact entry (td = 0), not a trial
   int kbest[CW][4], kval[CW][4];
   float kvalf[CW][4];
   float vsel[CW];
@@ -1104,7 +1105,7 @@ DEV bool refresh(Grp& gp, Smem& S, int k, bool has_acc, Trial acc, int par, int 
 // ------------------------------------------------------------ row visit pieces
 // Start a row visit: argmax counts, U and closed flags of row i into LDS,
 // candidate queue empty.
-DEV void row_begin(Grp& gp, Smem& S, int i, int cb, int sel) {
+DEV void row_begin(Grp& gp, Smem& S, int i, int cb, int sel, int start = 0) {
   const FitDev& d = *gp.d;
   if (gp.tid < d.r) {
     S.crow_i[gp.tid] = ld_atomic(&d.crow[((size_t)cb * d.ldm + i) * d.r + gp.tid]);
@@ -1128,7 +1129,7 @@ DEV void row_begin(Grp& gp, Smem& S, int i, int cb, int sel) {
       S.f_ij0 = kb;
     }
   }
-  if (gp.tid == 0) { S.cq_head = 0; S.cq_n = 0; S.ord_pos = 0; S.cur_op = 0; }
+  if (gp.tid == 0) { S.cq_head = 0; S.cq_n = 0; S.ord_pos = start; S.cur_op = 0; }
   __syncthreads();
 }
 
@@ -1168,8 +1169,9 @@ DEV void refill_candidates(Grp& gp, Smem& S, int i, int sel) {
   const FitDev& d = *gp.d;
   const GA float* Ri = d.Rw + (size_t)i * d.ldn;
   // TD_A, TD_B: the column order; TD: the row's own order; SEQ: every
-  // (column, component) pair, both ascending (entry j * RMAX + k)
-  const bool seq = sel == SEL_SEQ;
+  // (column, component) pair, both ascending (entry j * RMAX + k);
+  // ByElement: the working columns in order
+  const bool seq = sel == SEL_SEQ, elem = sel == SEL_ELEM;
   const GA int* ord = sel == SEL_TD ? d.rord : d.order;
   const int total = seq ? d.n * d.r : d.n;
   while (S.cq_n - S.cq_head < CW && S.ord_pos < total) {
@@ -1185,6 +1187,8 @@ DEV void refill_candidates(Grp& gp, Smem& S, int i, int sel) {
       if (seq) {
         const int c = pos / d.r;
         j = Ri[c] == FINF ? -1 : c * RMAX + (pos - c * d.r);
+      } else if (elem) {
+        j = Ri[pos] == FINF ? -1 : pos;
       } else {
         j = ld_atomic(&ord[pos]);
         if (Ri[j] == FINF) j = -1;
@@ -1230,7 +1234,8 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb, int sel) {
     //         multisets (lowest on ties);
     //   TD:   f(i, j), the lowest argmax of U_il + V_lj;
     //   TD_B: f(i, j0) if (U (x) V)_{i j0} >= (U (x) V)_{i0 j}, else f(i0, j);
-    //   SEQ:  the candidate's own component.
+    //   SEQ:  the candidate's own component;
+    //   ByElement: f(i, j), and an entry with R_ij = (U (x) V)_ij is skipped.
     {
       const int p = gp.tid >> 2, sub = gp.tid & 3;
       float vv[RMAX / 4];
@@ -1262,7 +1267,7 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb, int sel) {
           S.kbest[p][sub] = kb;
         } else if (sel != SEL_SEQ) {
           // row i (TD) or row i0 (TD_B): value selects, not address selects
-          const bool own = sel == SEL_TD;
+          const bool own = sel == SEL_TD || sel == SEL_ELEM;
           float best = 0.0f;
           int kb = -1;
 #pragma unroll
@@ -1282,6 +1287,7 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb, int sel) {
       if (gp.tid < avail) {
         const int q = gp.tid;
         int k = 0;
+        int skip = 0;
         if (sel == SEL_TD_A) {
           int best = -1;
           for (int u = 0; u < 4; ++u) {
@@ -1301,8 +1307,10 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb, int sel) {
           }
           k = kb;
           if (sel == SEL_TD_B && S.p_ij0 >= best) k = S.f_ij0;
+          if (sel == SEL_ELEM) skip = d.Rw[(size_t)i * d.ldn + S.cq[S.cq_head + q]] == best;
         }
         S.ck[q] = k;
+        S.cskip[q] = skip;
       }
       __syncthreads();
       if (p < avail && (S.ck[p] & 3) == sub) {
@@ -1334,11 +1342,15 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb, int sel) {
     // while fewer than T - nt trials precede it; consumed no-op pairs count as
     // skipped trials.  Prefix counts by ballot.
     const int nt0 = S.nt, room = T - nt0, nn0 = S.batch_noops, op0 = S.cur_op;
+    // A skipped (exact) candidate's pairs are consumed without a trial.
     const int x = gp.tid;
     const bool valid = x < 2 * avail && x >= op0;
-    bool noop = false;
-    if (valid) noop = (x & 1) ? S.cnv[x >> 1] : S.cnu[x >> 1];
-    const bool kept = valid && !noop;
+    bool noop = false, skip = false;
+    if (valid) {
+      skip = S.cskip[x >> 1];
+      noop = !skip && ((x & 1) ? S.cnv[x >> 1] : S.cnu[x >> 1]);
+    }
+    const bool kept = valid && !noop && !skip;
     const unsigned long long mk = __ballot(kept);
     const unsigned long long mn = __ballot(valid && noop);
     const unsigned long long below_mask = (1ull << gp.lane) - 1ull;
@@ -1526,10 +1538,91 @@ DEV bool fit_init(Grp& gp, Smem& S) {
   return true;
 }
 
+// Statistics and the decision record of a finished row visit (ByRow) or
+// segment of one (ByElement), by one thread of the group.
+DEV void book(Grp& gp, int it, int i, long long trials, long long noops, long long spec, int acc_j,
+              int acc_k, int acc_op, double e_cur) {
+  const FitDev& d = *gp.d;
+  GA FitCtl* ctl = gp.ctl;
+  if (gp.g != 0 || gp.tid != 0) return;
+  ctl->trials += trials;
+  ctl->spec_trials += spec;
+  ctl->noops += noops;
+  ctl->cells += trials * (long long)d.omega;
+  if (acc_j >= 0) { ctl->accepted += 1; ctl->e = e_cur; }
+  if (d.log && ctl->nlog < d.log_cap) {
+    LogRec rec;
+    rec.iter = it; rec.row = i; rec.trials = (int)trials; rec.noops = (int)noops;
+    rec.j = acc_j; rec.k = acc_k; rec.op = acc_op; rec.pad = 0; rec.e = e_cur;
+    d.log[ctl->nlog] = rec;
+  }
+  ctl->nlog += 1;
+}
+
+// ByElement row visit (Sec. 3.2.2): the row's observed entries in working
+// column order, k = f(i, j), exact entries skipped, F-ULF then F-URF.  An
+// accepted update ends a segment (its record is written) and the visit goes
+// on from the next entry with the new state; the last segment closes the
+// visit with j = -1.  Each segment's first batch is sized from the trials
+// the previous segment needed.
+template <typename Lap>
+DEV bool elem_row_visit(Grp& gp, Smem& S, int i, int it, int& cb, int& par, double& e_cur,
+                        int& acc_pass, int& seg_t, Lap& lap) {
+  const FitDev& d = *gp.d;
+  GA FitCtl* ctl = gp.ctl;
+  int start = 0;
+  while (true) {
+    row_begin(gp, S, i, cb, SEL_ELEM, start);
+    lap(0);
+    int T = seg_t;
+    long long trials = 0, noops = 0, spec = 0;
+    int acc_j = -1, acc_k = -1, acc_op = -1;
+    while (true) {
+      build_batch(gp, S, i, T, cb, SEL_ELEM);
+      lap(1);
+      const int nt = S.nt;
+      if (nt == 0) { noops += S.batch_noops; break; }
+      if (!run_batch(gp, S, i, par, e_cur, false, lap)) return false;
+      const int dec = ld_atomic(&ctl->decision);
+      spec += nt;
+      if (gp.tid == 0) S.prev_nt = nt;
+      if (dec >= 0) {
+        trials += dec + 1;
+        noops += S.noops_before[dec];
+        const Trial tr = S.trials[dec];
+        acc_j = tr.j; acc_k = tr.k; acc_op = tr.op;
+        e_cur = ld_atomic(&ctl->e_new);
+        if (!refresh(gp, S, tr.k, true, tr, par, dec, i, true, cb ^ 1)) return false;
+        cb ^= 1;
+        lap(4);
+        par ^= 1;
+        break;
+      }
+      trials += nt;
+      noops += S.batch_noops;
+      par ^= 1;
+      if (S.exhausted) break;
+      T = T * 2 > d.tmax ? d.tmax : T * 2;
+    }
+    int t = 16;
+    while (t < trials) t *= 2;
+    seg_t = t > d.tmax ? d.tmax : t;
+    if (acc_j >= 0) ++acc_pass;
+    book(gp, it, i, trials, noops, spec, acc_j, acc_k, acc_op, e_cur);
+    lap(5);
+    if (acc_j < 0) return true;
+    start = acc_j + 1;
+  }
+}
+
 // Run the fit from its saved state for at most max_rows row visits (0: no
 // limit).  All workgroups of the group execute the same control flow.
 // FastSTMF's TD_A (ANY_SEL false) is compiled on its own, without the code of
-// the other selections.
+// the other selections.  A ByRow row visit (Algorithm 3; the selections of
+// Sec. 3.2.1) runs batches of trials until the first accepted update (SEQ:
+// every trial, then the best), its refresh and the visit's record; it stays
+// written out here rather than in a function of its own, which measured
+// 1.3% slower on the TD_A fit (register allocation around the passes).
 template <bool ANY_SEL>
 DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
   const FitDev& d = *gp.d;
@@ -1560,106 +1653,97 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
     ticks[which] += (long long)(now - tmark);
     tmark = now;
   };
+  int seg_t = d.t0;  // ByElement: first batch of the next segment
   while (phase == 1) {
     if (max_rows > 0 && rows_done >= max_rows) break;
     const int i = row;
-    row_begin(gp, S, i, cb, sel);
-    if (sel == SEL_TD && !row_order_td(gp, S, i)) return;
-    lap(0);
-    // SEQ evaluates every trial of the row: full batches, the best one kept
-    const bool seq = sel == SEL_SEQ;
-    // first batch: sized from the trials this row's previous visit needed
-    // (batch sizes change which trials are evaluated speculatively, never
-    // the outcome)
-    const int prev_trials = ld_atomic(&d.rowt[i]);
-    int T = d.t0;
-    if (seq) {
-      T = d.tmax;
-    } else if (prev_trials > 0) {
-      T = 16;
-      while (T < prev_trials) T *= 2;
-    }
-    if (T > d.tmax) T = d.tmax;  // the trial buffers hold tmax trials
-    long long row_trials = 0, row_noops = 0, row_spec = 0;
-    int acc_j = -1, acc_k = -1, acc_op = -1;
-    double e_best = e_cur;
-    Trial best_tr;
-    best_tr.j = -1; best_tr.k = 0; best_tr.op = OP_NULL; best_tr.val = 0.0f;
-    while (true) {
-      build_batch(gp, S, i, T, cb, sel);
-      lap(1);
-      const int nt = S.nt;
-      if (nt == 0) { row_noops += S.batch_noops; break; }
-      if (!run_batch(gp, S, i, par, seq ? e_best : e_cur, seq, lap)) return;
-      const int dec = ld_atomic(&ctl->decision);
-      row_spec += nt;
-      if (gp.tid == 0) S.prev_nt = nt;
+    if (sel == SEL_ELEM) {
+      if (!elem_row_visit(gp, S, i, it, cb, par, e_cur, acc_pass, seg_t, lap)) return;
+    } else {
+      row_begin(gp, S, i, cb, sel);
+      if (sel == SEL_TD && !row_order_td(gp, S, i)) return;
+      lap(0);
+      // SEQ evaluates every trial of the row: full batches, the best one kept
+      const bool seq = sel == SEL_SEQ;
+      // first batch: sized from the trials this row's previous visit needed
+      // (batch sizes change which trials are evaluated speculatively, never
+      // the outcome)
+      const int prev_trials = ld_atomic(&d.rowt[i]);
+      int T = d.t0;
       if (seq) {
+        T = d.tmax;
+      } else if (prev_trials > 0) {
+        T = 16;
+        while (T < prev_trials) T *= 2;
+      }
+      if (T > d.tmax) T = d.tmax;  // the trial buffers hold tmax trials
+      long long row_trials = 0, row_noops = 0, row_spec = 0;
+      int acc_j = -1, acc_k = -1, acc_op = -1;
+      double e_best = e_cur;
+      Trial best_tr;
+      best_tr.j = -1; best_tr.k = 0; best_tr.op = OP_NULL; best_tr.val = 0.0f;
+      while (true) {
+        build_batch(gp, S, i, T, cb, sel);
+        lap(1);
+        const int nt = S.nt;
+        if (nt == 0) { row_noops += S.batch_noops; break; }
+        if (!run_batch(gp, S, i, par, seq ? e_best : e_cur, seq, lap)) return;
+        const int dec = ld_atomic(&ctl->decision);
+        row_spec += nt;
+        if (gp.tid == 0) S.prev_nt = nt;
+        if (seq) {
+          row_trials += nt;
+          row_noops += S.batch_noops;
+          if (dec >= 0) { best_tr = S.trials[dec]; e_best = ld_atomic(&ctl->e_new); }
+          par ^= 1;
+          if (S.exhausted) break;
+          continue;
+        }
+        if (dec >= 0) {
+          row_trials += dec + 1;
+          row_noops += S.noops_before[dec];
+          const Trial tr = S.trials[dec];
+          acc_j = tr.j; acc_k = tr.k; acc_op = tr.op;
+          e_cur = ld_atomic(&ctl->e_new);
+          if (!refresh(gp, S, tr.k, true, tr, par, dec, i, true, cb ^ 1)) return;
+          cb ^= 1;
+          lap(4);
+          par ^= 1;
+          break;
+        }
         row_trials += nt;
         row_noops += S.batch_noops;
-        if (dec >= 0) { best_tr = S.trials[dec]; e_best = ld_atomic(&ctl->e_new); }
         par ^= 1;
         if (S.exhausted) break;
-        continue;
+        T = T * 2 > d.tmax ? d.tmax : T * 2;
       }
-      if (dec >= 0) {
-        row_trials += dec + 1;
-        row_noops += S.noops_before[dec];
-        const Trial tr = S.trials[dec];
-        acc_j = tr.j; acc_k = tr.k; acc_op = tr.op;
-        e_cur = ld_atomic(&ctl->e_new);
-        if (!refresh(gp, S, tr.k, true, tr, par, dec, i, true, cb ^ 1)) return;
+      if (seq && best_tr.j >= 0) {
+        // the chosen trial once more, alone, for its vectors (the evaluation is
+        // deterministic: it reproduces the error it was chosen for)
+        single_trial(gp, S, best_tr);
+        if (!run_batch(gp, S, i, par, e_cur, false, lap)) return;
+        row_spec += 1;
+        if (gp.tid == 0) S.prev_nt = 1;
+        if (ld_atomic(&ctl->decision) != 0 || ld_atomic(&ctl->e_new) != e_best) {
+          if (gp.tid == 0) {
+            int zero = 0;
+            __hip_atomic_compare_exchange_strong(&ctl->status, &zero, ST_INTERNAL, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          return;
+        }
+        acc_j = best_tr.j; acc_k = best_tr.k; acc_op = best_tr.op;
+        e_cur = e_best;
+        if (!refresh(gp, S, best_tr.k, true, best_tr, par, 0, i, true, cb ^ 1)) return;
         cb ^= 1;
         lap(4);
         par ^= 1;
-        break;
       }
-      row_trials += nt;
-      row_noops += S.batch_noops;
-      par ^= 1;
-      if (S.exhausted) break;
-      T = T * 2 > d.tmax ? d.tmax : T * 2;
+      if (acc_j >= 0) ++acc_pass;
+      if (gp.g == 0 && gp.tid == 0) st_coh(&d.rowt[i], (int)(row_trials > 0 ? row_trials : 1));
+      book(gp, it, i, row_trials, row_noops, row_spec, acc_j, acc_k, acc_op, e_cur);
     }
-    if (seq && best_tr.j >= 0) {
-      // the chosen trial once more, alone, for its vectors (the evaluation is
-      // deterministic: it reproduces the error it was chosen for)
-      single_trial(gp, S, best_tr);
-      if (!run_batch(gp, S, i, par, e_cur, false, lap)) return;
-      row_spec += 1;
-      if (gp.tid == 0) S.prev_nt = 1;
-      if (ld_atomic(&ctl->decision) != 0 || ld_atomic(&ctl->e_new) != e_best) {
-        if (gp.tid == 0) {
-          int zero = 0;
-          __hip_atomic_compare_exchange_strong(&ctl->status, &zero, ST_INTERNAL, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        return;
-      }
-      acc_j = best_tr.j; acc_k = best_tr.k; acc_op = best_tr.op;
-      e_cur = e_best;
-      if (!refresh(gp, S, best_tr.k, true, best_tr, par, 0, i, true, cb ^ 1)) return;
-      cb ^= 1;
-      lap(4);
-      par ^= 1;
-    }
-    if (acc_j >= 0) ++acc_pass;
-    if (gp.g == 0 && gp.tid == 0) st_coh(&d.rowt[i], (int)(row_trials > 0 ? row_trials : 1));
-    // bookkeeping by one thread of the group
-    if (gp.g == 0 && gp.tid == 0) {
-      ctl->trials += row_trials;
-      ctl->spec_trials += row_spec;
-      ctl->noops += row_noops;
-      ctl->row_visits += 1;
-      ctl->cells += row_trials * (long long)d.omega;
-      if (acc_j >= 0) { ctl->accepted += 1; ctl->e = e_cur; }
-      if (d.log && ctl->nlog < d.log_cap) {
-        LogRec rec;
-        rec.iter = it; rec.row = i; rec.trials = (int)row_trials; rec.noops = (int)row_noops;
-        rec.j = acc_j; rec.k = acc_k; rec.op = acc_op; rec.pad = 0; rec.e = e_cur;
-        d.log[ctl->nlog] = rec;
-      }
-      ctl->nlog += 1;
-    }
+    if (gp.g == 0 && gp.tid == 0) ctl->row_visits += 1;
     ++row;
     ++rows_done;
     if (row == d.m) {

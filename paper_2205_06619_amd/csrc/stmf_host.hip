@@ -28,14 +28,17 @@ __global__ void check_count_kernel(const float*, const uint8_t*, int, int, int*,
 __global__ void check_empty_kernel(const int*, const int*, int, int, CheckOut*);
 __global__ void fill_u32_kernel(unsigned*, size_t, unsigned);
 __global__ void pack_kernel(const float*, const uint8_t*, int, int, int, int, int, int, const int*,
+                            const int*,
                             float*);
 __global__ void transpose_kernel(const float*, int, int, float*);
 __global__ void rowmin_kernel(const float*, const uint8_t*, int, int, int, float*);
 __global__ void rank_perm_kernel(const float*, int, int*);
+__global__ void iota_kernel(int*, int);
 __global__ void u0_given_kernel(const float*, int, int, int, float*);
 __global__ void u0_acol_kernel(const float*, int, int, int, int, int, int, const int*, float*);
 __global__ void vinit_kernel(const float*, const float*, int, int, int, int, int, float*);
 __global__ void output_kernel(const float*, const float*, int, int, int, int, int, int, const int*,
+                              const int*,
                               float*, float*);
 __global__ void copy_f64_kernel(const double*, double*, int);
 
@@ -127,7 +130,8 @@ static int check_options(const stmf_options& o) {
   if (o.batch_first < 0 || o.batch_max < 0 || o.batch_max > TMAX) return STMF_EINVAL;
   if (o.group_size < 0 || o.log_cap < 0 || o.max_row_visits < 0) return STMF_EINVAL;
   if (!(o.eps >= 0.0)) return STMF_EINVAL;
-  if (o.selection < 0 || o.selection > 3 || o.perm_mode < 0 || o.perm_mode > 2) return STMF_EINVAL;
+  if (o.selection < 0 || o.selection > 3 || o.perm_mode < 0 || o.perm_mode > 3) return STMF_EINVAL;
+  if (o.strategy < 0 || o.strategy > 1) return STMF_EINVAL;
   return STMF_OK;
 }
 
@@ -137,7 +141,8 @@ struct Layout {
   int mw, nw, ldm, ldn, nrt, nct, ldmax, G, acol_p, tmax;
   int transposed;
   size_t Rw, RwT, Uc, V, td, tdpart, crow, ccol, colst, rowst, colpart, rowpart, order, rowt,
-      rord, tdrow, tvec, epart, eprime, closed, traj, ctl, dev, perm, stage, check, rowc, colc;
+      rord, tdrow, tvec, epart, eprime, closed, traj, ctl, dev, perm, cperm, stage, check, rowc,
+      colc;
   size_t total;
 };
 
@@ -189,7 +194,8 @@ static void make_layout(int m, int n, int r, int iters, int G, int acol_p, int b
   L.ctl = take(sizeof(FitCtl));
   L.dev = take(sizeof(FitDev));
   L.perm = take((size_t)L.mw * 4);
-  L.stage = take(std::max((size_t)L.mw * r * 4, (size_t)r * acol_p * 4));
+  L.cperm = take((size_t)L.nw * 4);
+  L.stage = take(std::max({(size_t)L.mw * r * 4, (size_t)r * acol_p * 4, (size_t)L.nw * 4}));
   L.check = take(sizeof(CheckOut));
   L.rowc = take((size_t)m * 4);
   L.colc = take((size_t)n * 4);
@@ -209,6 +215,11 @@ static int auto_batch_first(const Layout& L) {
   return std::min(t, L.tmax);
 }
 
+// What the fit kernel runs: a ByRow selection, or ByElement.
+static int kernel_sel(const stmf_options& o) {
+  return o.strategy == 1 ? (int)SEL_ELEM : o.selection;
+}
+
 static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int observed) {
   FitDev d;
   std::memset(&d, 0, sizeof(d));
@@ -221,7 +232,7 @@ static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int o
   d.log_cap = o.decision_log ? o.log_cap : 0;
   d.eps = o.eps;
   d.omega = observed;
-  d.sel = o.selection;
+  d.sel = kernel_sel(o);
   d.Rw = (const float*)(base + L.Rw);
   d.RwT = (const float*)(base + L.RwT);
   d.Uc = (float*)(base + L.Uc);
@@ -346,10 +357,24 @@ static int prepare_fit(const float* R, const uint8_t* M, const Layout& L, char* 
   } else {
     HIPCHK(hipMemcpyAsync(base + L.perm, perm.data(), perm.size() * 4, hipMemcpyHostToDevice, s));
   }
+  if (o.perm_mode == 3) {
+    // PermC: minimum observed value of every working column, then the stable
+    // order by it (a working column is an original column, or an original
+    // row when transposed)
+    hipLaunchKernelGGL(rowmin_kernel, dim3(L.nw), dim3(256), 0, s, R, M, L.n, L.mw, !L.transposed,
+                       (float*)(base + L.stage));
+    hipLaunchKernelGGL(rank_perm_kernel, dim3((L.nw + 255) / 256), dim3(256), 0, s,
+                       (const float*)(base + L.stage), L.nw, (int*)(base + L.cperm));
+  } else {
+    hipLaunchKernelGGL(iota_kernel, dim3((L.nw + 255) / 256), dim3(256), 0, s,
+                       (int*)(base + L.cperm), L.nw);
+  }
+  HIPCHK(hipGetLastError());
   {
     dim3 grid((L.ldn + 255) / 256, L.ldm);
     hipLaunchKernelGGL(pack_kernel, grid, dim3(256), 0, s, R, M, L.n, L.mw, L.nw, L.ldm, L.ldn,
-                       L.transposed, (const int*)(base + L.perm), (float*)(base + L.Rw));
+                       L.transposed, (const int*)(base + L.perm), (const int*)(base + L.cperm),
+                       (float*)(base + L.Rw));
     dim3 tg(L.ldn / TS, L.ldm / TS);
     hipLaunchKernelGGL(transpose_kernel, tg, dim3(256), 0, s, (const float*)(base + L.Rw), L.ldm,
                        L.ldn, (float*)(base + L.RwT));
@@ -379,7 +404,8 @@ static int launch_output(const Layout& L, char* base, float* U_out, float* V_out
   const int mx = std::max(L.mw, L.nw);
   hipLaunchKernelGGL(output_kernel, dim3((mx + 255) / 256, L.r), dim3(256), 0, s,
                      (const float*)(base + L.Uc), (const float*)(base + L.V), L.mw, L.nw, L.ldm,
-                     L.ldn, L.r, L.transposed, (const int*)(base + L.perm), U_out, V_out);
+                     L.ldn, L.r, L.transposed, (const int*)(base + L.perm),
+                     (const int*)(base + L.cperm), U_out, V_out);
   return hipGetLastError() == hipSuccess ? STMF_OK : STMF_EHIP;
 }
 
@@ -585,7 +611,7 @@ int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters
   HIPCHK(hipEventCreate(&ev1));
   HIPCHK(hipEventRecord(ev0, s));
   st = launch_fit_kernel((const FitDev*)(base + L.dev), 1, G, G, o.max_row_visits, nullptr,
-                         o.selection, s);
+                         kernel_sel(o), s);
   if (st) { (void)hipEventDestroy(ev0); (void)hipEventDestroy(ev1); return st; }
   HIPCHK(hipEventRecord(ev1, s));
   FitCtl c;
@@ -709,7 +735,7 @@ int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts, const stmf_op
     if (st) return st;
     const int grid = std::min<int>((int)table.size(), P.coresident);
     st = launch_fit_kernel((const FitDev*)(base + B.table), (int)table.size(), 1, grid, 0,
-                           (unsigned*)(base + B.queue), o.selection, s);
+                           (unsigned*)(base + B.queue), kernel_sel(o), s);
     if (st) return st;
   }
   HIPCHK(hipStreamSynchronize(s));  // host staging vectors go out of scope after this
@@ -884,7 +910,7 @@ int stmf_batch_tick(stmf_engine* e, int max_rows, void* stream) {
   if (st) return st;
   const int grid = std::min<int>((int)table.size(), P.coresident);
   st = launch_fit_kernel((const FitDev*)(e->arena + e->table_off), (int)table.size(), 1, grid,
-                         max_rows, (unsigned*)(e->arena + e->queue_off), e->opt.selection, s);
+                         max_rows, (unsigned*)(e->arena + e->queue_off), kernel_sel(e->opt), s);
   if (st) return st;
   // the table is read by the launch: wait for it before the host array changes
   HIPCHK(hipStreamSynchronize(s));

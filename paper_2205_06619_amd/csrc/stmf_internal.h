@@ -35,8 +35,9 @@ struct Top2 {
 
 enum Op : int { OP_ULF = 0, OP_URF = 1, OP_NULL = 2 };
 
-// ByRow selections of (j, k) within a row visit (Sec. 3.2.1).
-enum Sel : int { SEL_TD_A = 0, SEL_TD = 1, SEL_TD_B = 2, SEL_SEQ = 3 };
+// ByRow selections of (j, k) within a row visit (Sec. 3.2.1), and the
+// ByElement strategy (Sec. 3.2.2), which the fit kernel runs as a fifth.
+enum Sel : int { SEL_TD_A = 0, SEL_TD = 1, SEL_TD_B = 2, SEL_SEQ = 3, SEL_ELEM = 4 };
 
 struct Trial {
   int j, k, op;

@@ -48,27 +48,29 @@ __global__ void fill_u32_kernel(unsigned* __restrict__ p, size_t count, unsigned
     p[x] = v;
 }
 
-// Working matrix: Rw[a][b] = R at original (perm[a], b), or (b, perm[a]) when
-// transposed; +inf at missing and padding cells; -0 becomes +0.
+// Working matrix: Rw[a][b] = R at original (perm[a], cperm[b]), or
+// (cperm[b], perm[a]) when transposed; +inf at missing and padding cells; -0
+// becomes +0.
 __global__ void pack_kernel(const float* __restrict__ R, const uint8_t* __restrict__ M, int n_in,
                             int mw, int nw, int ldm, int ldn, int transposed,
-                            const int* __restrict__ perm, float* __restrict__ Rw) {
+                            const int* __restrict__ perm, const int* __restrict__ cperm,
+                            float* __restrict__ Rw) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const int a = blockIdx.y;
   if (b >= ldn || a >= ldm) return;
   float v = SINF;
   if (a < mw && b < nw) {
-    const int src = perm[a];
-    const size_t idx = transposed ? ((size_t)b * n_in + src) : ((size_t)src * n_in + b);
+    const int src = perm[a], csrc = cperm[b];
+    const size_t idx = transposed ? ((size_t)csrc * n_in + src) : ((size_t)src * n_in + csrc);
     if (M[idx]) v = R[idx] + 0.0f;
   }
   Rw[(size_t)a * ldn + b] = v;
 }
 
-// PermR (Sec. 3.2), first step: mn[a] = the minimum observed value of
-// working row a (original row a, or original column a when transposed), one
-// workgroup of 256 threads per row.  Every row has an observed cell (checked
-// before).  -0 and +0 compare equal, so the order never depends on the sign
+// PermR / PermC (Sec. 3.2), first step: mn[a] = the minimum observed value
+// of line a: original row a (elements R[a][b], b < nw), or with `transposed`
+// original column a (elements R[b][a]); one workgroup of 256 threads per
+// line.  Every line has an observed cell (checked before).  -0 and +0 compare equal, so the order never depends on the sign
 // of a zero.
 __global__ void __launch_bounds__(256) rowmin_kernel(const float* __restrict__ R,
                                                      const uint8_t* __restrict__ M, int n_in,
@@ -89,9 +91,9 @@ __global__ void __launch_bounds__(256) rowmin_kernel(const float* __restrict__ R
   if (threadIdx.x == 0) mn[a] = part[0] + 0.0f;
 }
 
-// PermR, second step: the stable order of the rows by increasing minimum,
-// perm[rank of a] = a, the rank counting the rows with a smaller minimum or
-// an equal one at a lower index.
+// PermR / PermC, second step: the stable order of the lines by increasing
+// minimum, perm[rank of a] = a, the rank counting the lines with a smaller
+// minimum or an equal one at a lower index.
 __global__ void rank_perm_kernel(const float* __restrict__ mn, int mw, int* __restrict__ perm) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= mw) return;
@@ -102,6 +104,12 @@ __global__ void rank_perm_kernel(const float* __restrict__ mn, int mw, int* __re
     rank += (o < v || (o == v && b < a)) ? 1 : 0;
   }
   perm[rank] = a;
+}
+
+// perm[a] = a for a < count.
+__global__ void iota_kernel(int* __restrict__ perm, int count) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a < count) perm[a] = a;
 }
 
 // RwT = Rw^T through 64 x 64 LDS tiles.
@@ -168,21 +176,22 @@ __global__ void vinit_kernel(const float* __restrict__ Rw, const float* __restri
   V[(size_t)l * ldn + c] = best;
 }
 
-// Output (Algorithm 3, last step): U_unperm[perm[a]] = U_w[a]; if transposed,
-// U_out = V_w^T and V_out = U_unperm^T, else U_out = U_unperm, V_out = V_w.
+// Output (Algorithm 3, last step): U_unperm[perm[a]] = U_w[a] and
+// V_unperm[:, cperm[c]] = V_w[:, c]; if transposed, U_out = V_unperm^T and
+// V_out = U_unperm^T, else U_out = U_unperm, V_out = V_unperm.
 __global__ void output_kernel(const float* __restrict__ Uc, const float* __restrict__ V, int mw,
                               int nw, int ldm, int ldn, int r, int transposed,
-                              const int* __restrict__ perm, float* __restrict__ U_out,
-                              float* __restrict__ V_out) {
+                              const int* __restrict__ perm, const int* __restrict__ cperm,
+                              float* __restrict__ U_out, float* __restrict__ V_out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int l = blockIdx.y;
   if (!transposed) {
     // original m = mw rows, n = nw columns
     if (x < mw) U_out[(size_t)perm[x] * r + l] = Uc[(size_t)l * ldm + x];
-    if (x < nw) V_out[(size_t)l * nw + x] = V[(size_t)l * ldn + x];
+    if (x < nw) V_out[(size_t)l * nw + cperm[x]] = V[(size_t)l * ldn + x];
   } else {
     // original m = nw rows, n = mw columns
-    if (x < nw) U_out[(size_t)x * r + l] = V[(size_t)l * ldn + x];
+    if (x < nw) U_out[(size_t)cperm[x] * r + l] = V[(size_t)l * ldn + x];
     if (x < mw) V_out[(size_t)l * mw + perm[x]] = Uc[(size_t)l * ldm + x];
   }
 }

@@ -1,5 +1,6 @@
-"""GPU parity of the other ByRow selections (TD, TD_B, SEQ; Sec. 3.2.1) and
-row orders (PermR, none; Sec. 3.2) against the CPU oracle.
+"""GPU parity of the other ByRow selections (TD, TD_B, SEQ; Sec. 3.2.1), the
+ByElement strategy (Sec. 3.2.2) and the row and column orders (PermR, PermC,
+none; Sec. 3.2) against the CPU oracle.
 
 As for TD_A: on integer data U, V, the trajectory and the decision log are
 identical; on real data the values and decisions match and the trajectory
@@ -161,6 +162,79 @@ def test_selection_batched_equals_plain(S):
 def test_selection_bad_options(S):
     print("selection options", flush=True)
     R, M = synth.int_planted(10, 12, 2, 0.2, seed=14)
-    for kw in (dict(selection=4), dict(selection=-1), dict(perm_mode=3)):
+    for kw in (dict(selection=4), dict(selection=-1), dict(perm_mode=4), dict(strategy=2)):
         with pytest.raises(S.StmfError):
             S.stmf_fit(_t(R), _t(M), 2, 1, **kw)
+
+
+# ------------------------------------------------------------------ ByElement
+ELEM_CASES = [  # m, n, rank, iters, seed, missing, perm_mode
+    (40, 70, 3, 3, 21, 0.3, 3), (70, 150, 4, 2, 22, 0.4, 3), (150, 70, 2, 2, 23, 0.3, 3),
+    (1, 40, 2, 2, 24, 0.2, 2), (33, 65, 1, 2, 25, 0.0, 2),
+]
+
+
+@pytest.mark.parametrize("m,n,rank,iters,seed,miss,pm", ELEM_CASES)
+@pytest.mark.parametrize("group", [0, 1])
+def test_byelement_integer(S, m, n, rank, iters, seed, miss, pm, group):
+    print(f"ByElement int {m}x{n} r={rank} perm_mode={pm} group={group}", flush=True)
+    R, M = synth.int_planted(m, n, rank, miss, seed=seed, hi=30)
+    cap = int(M.sum()) * iters + min(m, n) * iters + 1
+    o = oracle.fit(R, M, rank, iters, seed=seed, prec="f32", init_hi=30, strategy=1,
+                   perm_mode=pm, log_cap=cap)
+    assert o.status == 0
+    g = S.stmf_fit(_t(R), _t(M), rank, iters, seed=seed, init_hi=30.0, group_size=group,
+                   strategy=1, perm_mode=pm, log_cap=cap)
+    _compare(g, o)
+
+
+def test_byelement_exact_entries_are_skipped(S):
+    # every entry exact from the start: no trial at all, as in the oracle
+    print("ByElement exact start", flush=True)
+    rng = np.random.default_rng(3)
+    Us = rng.integers(0, 20, (30, 3)).astype(np.float32)
+    Vs = rng.integers(0, 20, (3, 50)).astype(np.float32)
+    R = np.max(Us[:, :, None] + Vs[None, :, :], axis=1).astype(np.float32)
+    M = np.ones_like(R, np.uint8)
+    g = S.stmf_fit(_t(R), _t(M), 3, 3, U0=Us, perm_mode=2, strategy=1, log_cap=200)
+    assert g.info["trials"] == 0 and g.info["accepted"] == 0
+    np.testing.assert_array_equal(g.traj, [0.0] * 4)
+
+
+def test_byelement_real(S):
+    print("ByElement real 60x150", flush=True)
+    R, M = synth.gene_expr(60, 150, 4, 0.5, seed=2)
+    cap = int(M.sum()) * 3 + 200
+    o = oracle.fit(R, M, 4, 3, seed=2, prec="f32", init_mode=1, strategy=1, perm_mode=3,
+                   log_cap=cap)
+    g = S.stmf_fit(_t(R), _t(M), 4, 3, seed=2, init_mode=1, strategy=1, perm_mode=3, log_cap=cap)
+    _compare(g, o, exact=False)
+
+
+def test_byelement_gene_expression_prefix(S):
+    # the full gene-expression-shaped workload in the cooperative launch:
+    # the first row visit (about 1000 entries), record by record
+    print("ByElement real 500x2000 prefix", flush=True)
+    R, M = synth.gene_expr()
+    o = oracle.fit(R, M, 5, 50, seed=2, prec="f32", init_mode=1, row_limit=1, strategy=1,
+                   perm_mode=3, log_cap=4000)
+    g = S.stmf_fit(_t(R), _t(M), 5, 50, seed=2, init_mode=1, max_row_visits=1, log_cap=4000,
+                   strategy=1, perm_mode=3)
+    assert len(o.log) > 2
+    assert _log_rows(g.log) == _log_rows(o.log)
+    np.testing.assert_allclose(g.log["e"], o.log["e"], rtol=1e-9)
+
+
+def test_byelement_batched_equals_oracle(S):
+    print("ByElement batched", flush=True)
+    probs = synth.batched_problems(4, seed=71, integer=True, m_range=(12, 80), n_range=(12, 120),
+                                   r_range=(2, 4), miss_range=(0.2, 0.5))
+    dev = [dict(R=_t(p.R), M=_t(p.M), rank=p.rank, iters=2, seed=950 + p.pid) for p in probs]
+    outs, statuses, _ = S.stmf_fit_batched(dev, restarts=1, strategy=1, perm_mode=3)
+    assert statuses == [0] * len(probs)
+    for p, d, (U, V, T) in zip(probs, dev, outs):
+        o = oracle.fit(p.R, p.M, p.rank, 2, seed=d["seed"], prec="f32", strategy=1, perm_mode=3,
+                       log_cap=1)
+        np.testing.assert_array_equal(U[0].cpu().numpy(), o.U)
+        np.testing.assert_array_equal(V[0].cpu().numpy(), o.V)
+        np.testing.assert_array_equal(T[0].cpu().numpy(), o.traj)
