@@ -149,7 +149,7 @@ typedef struct {
                              ascending, F-ULF first; the smallest error below
                              the current one is applied (the first on ties).
                            Ties in every order: the lower index first.         */
-  int perm_mode;        /* working-row order when perm is null (Sec. 3.2):
+  int perm_mode;        /* working-row order when perm is null (Sec. 3.3):
                            0 random permutation drawn from the seed (default),
                            1 PermR: rows by increasing minimum observed value,
                              ties by the lower working index,

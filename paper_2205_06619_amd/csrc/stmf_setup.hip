@@ -67,7 +67,7 @@ __global__ void pack_kernel(const float* __restrict__ R, const uint8_t* __restri
   Rw[(size_t)a * ldn + b] = v;
 }
 
-// PermR / PermC (Sec. 3.2), first step: mn[a] = the minimum observed value
+// PermR / PermC (Sec. 3.3), first step: mn[a] = the minimum observed value
 // of line a: original row a (elements R[a][b], b < nw), or with `transposed`
 // original column a (elements R[b][a]); one workgroup of 256 threads per
 // line.  Every line has an observed cell (checked before).  -0 and +0 compare equal, so the order never depends on the sign

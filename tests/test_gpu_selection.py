@@ -1,6 +1,6 @@
 """GPU parity of the other ByRow selections (TD, TD_B, SEQ; Sec. 3.2.1), the
 ByElement strategy (Sec. 3.2.2) and the row and column orders (PermR, PermC,
-none; Sec. 3.2) against the CPU oracle.
+none; Sec. 3.3) against the CPU oracle.
 
 As for TD_A: on integer data U, V, the trajectory and the decision log are
 identical; on real data the values and decisions match and the trajectory

@@ -444,7 +444,7 @@ def _row_minima_order(R, M):
 
 @pytest.mark.parametrize("transpose", [False, True])
 def test_permr_orders_rows_by_increasing_minimum(transpose):
-    # PermR (Sec. 3.2): rows sorted by increasing minimum observed value; the
+    # PermR (Sec. 3.3): rows sorted by increasing minimum observed value; the
     # order equals numpy's stable argsort of the row minima, and PermR is the
     # same fit as passing that permutation explicitly
     R, M = synth.int_planted(14, 22, 3, seed=16)
@@ -583,7 +583,7 @@ def _col_minima_order(R, M):
 @pytest.mark.parametrize("transpose", [False, True])
 @pytest.mark.parametrize("strategy", [0, 1])
 def test_permc_orders_columns_by_increasing_minimum(transpose, strategy):
-    # PermC (Sec. 3.2): the fit on R with PermC equals the fit on R with its
+    # PermC (Sec. 3.3): the fit on R with PermC equals the fit on R with its
     # working columns put in numpy's stable order of the column minima (and
     # no permutation), with V's columns put back
     R, M = synth.int_planted(9, 17, 2, seed=19, hi=30)
