@@ -44,6 +44,7 @@ __all__ = [
     "batched_problems",
     "poisson_arrivals",
     "tiny_int_case",
+    "holdout",
 ]
 
 
@@ -205,3 +206,32 @@ def tiny_int_case(m: int, n: int, rank: int, seed: int, hi: int = 4,
         R = rng.integers(0, hi + 1, size=(m, n)).astype(np.float32)
     M = _mask_uniform(m, n, missing, rng)
     return R, M
+
+
+def holdout(M: np.ndarray, frac: float = 0.2, seed: int = 0) -> Tuple[np.ndarray, np.ndarray]:
+    """Split the observed cells of M into training and held-out masks: about
+    round(frac * |Omega|) cells, drawn uniformly, go to the held-out set, each
+    only if its row and column keep a training cell (a fit needs every line
+    observed).  Returns (M_train, M_test), disjoint, their union M."""
+    rng = np.random.default_rng(seed)
+    M = np.asarray(M).astype(np.uint8)
+    train = M.copy()
+    test = np.zeros_like(M)
+    obs = np.flatnonzero(M.ravel())
+    want = int(round(frac * obs.size))
+    rows = train.sum(axis=1).astype(np.int64)
+    cols = train.sum(axis=0).astype(np.int64)
+    n = M.shape[1]
+    taken = 0
+    for q in rng.permutation(obs):
+        if taken == want:
+            break
+        i, j = divmod(int(q), n)
+        if rows[i] > 1 and cols[j] > 1:
+            train[i, j] = 0
+            test[i, j] = 1
+            rows[i] -= 1
+            cols[j] -= 1
+            taken += 1
+    return train, test
+
