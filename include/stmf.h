@@ -298,6 +298,42 @@ int stmf_engine_poll(stmf_engine* eng, int slot, int* done, void* stream);
 int stmf_engine_retire(stmf_engine* eng, int slot, float* U_out, float* V_out,
                        double* err_traj, stmf_fit_info* info, void* stream);
 
+/* ---------------------------------------------------------------- quality */
+
+/* Workspace bytes of stmf_distance_correlation for N samples. */
+size_t stmf_dcor_workspace(int N);
+
+/* Distance correlation (Sec. 3.6, the DC of Szekely, Rizzo and Bakirov,
+ * Ann. Statist. 35(6), 2007; V-statistic form) of the samples x[0..N) and
+ * y[0..N) (device, FP32).  out (host, 4 doubles): dCor, dCov^2(x, y),
+ * dVar^2(x), dVar^2(y); dCor = 0 when a variance is 0 (N = 0 gives zeros).
+ * row_terms (device, nullable, N x 5 doubles): per sample k the sums over
+ * all l of |x_k - x_l|, |y_k - y_l|, their product and their squares.
+ * Every sum is FP64 in a fixed order (deterministic).  Synchronous.
+ * Errors: STMF_EINVAL (N < 0, null pointer), STMF_ENOMEM (workspace smaller
+ * than stmf_dcor_workspace(N) or not 256-byte aligned), STMF_EHIP. */
+int stmf_distance_correlation(const float* x, const float* y, int N, double* out,
+                              double* row_terms, void* ws, size_t ws_bytes,
+                              void* stream);
+
+/* Workspace bytes of stmf_completion_metrics (0 for invalid sizes). */
+size_t stmf_completion_metrics_workspace(int m, int n, int r);
+
+/* Completion quality of a factorization on a held-out split (Sec. 3.6 and the
+ * 20% held-out protocol of Sec. 3.7), with P = U (x) V formed in FP32
+ * (R, M_train, M_test m x n row-major, U m x r, V r x n; all device):
+ *   out[0] RMSE-A = sqrt(mean over M_train cells of (R - P)^2)
+ *   out[1] RMSE-P = sqrt(mean over M_test cells of (R - P)^2)
+ *   out[2] DC of the M_test cells' (R, P) pairs (row-major order)
+ *   out[3], out[4] the numbers of training and held-out cells
+ * out: host, 5 doubles.  A cell in both masks counts in both; an empty set
+ * gives RMSE 0.  Differences and sums FP64, fixed orders.  Synchronous.
+ * Errors: STMF_EINVAL, STMF_ENOMEM, STMF_EHIP. */
+int stmf_completion_metrics(const float* R, const uint8_t* M_train,
+                            const uint8_t* M_test, const float* U, const float* V,
+                            int m, int n, int r, double* out, void* ws,
+                            size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,8 @@ EXPORTS = (
     "stmf_options_default", "stmf_fit_workspace", "stmf_fit", "stmf_draw_init",
     "stmf_fit_batched_workspace", "stmf_fit_batched", "stmf_engine_create", "stmf_engine_destroy",
     "stmf_job_footprint", "stmf_engine_admit", "stmf_batch_tick", "stmf_engine_poll",
-    "stmf_engine_retire",
+    "stmf_engine_retire", "stmf_dcor_workspace", "stmf_distance_correlation",
+    "stmf_completion_metrics_workspace", "stmf_completion_metrics",
 )
 
 
@@ -102,6 +103,10 @@ def _load():
         "stmf_batch_tick": ([P, I, P], I),
         "stmf_engine_poll": ([P, I, P, P], I),
         "stmf_engine_retire": ([P, I, P, P, P, P, P], I),
+        "stmf_dcor_workspace": ([I], Z),
+        "stmf_distance_correlation": ([P, P, I, P, P, P, Z, P], I),
+        "stmf_completion_metrics_workspace": ([I, I, I], Z),
+        "stmf_completion_metrics": ([P, P, P, P, P, I, I, I, P, P, Z, P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -406,3 +411,47 @@ def stmf_engine_retire(eng: Engine, slot: int, stream=None) -> FitResult:
                                 C.byref(info), _stream(stream)), "stmf_engine_retire")
     del eng.shapes[slot]
     return FitResult(U, V, traj, info.as_dict())
+
+
+# ------------------------------------------------------------------ quality
+def stmf_distance_correlation(x, y, row_terms=False, ws=None, stream=None):
+    """Distance correlation of two device float32 vectors: dict with dcor,
+    dcov2, dvarx2, dvary2 (and row_terms, an (N, 5) float64 tensor, if asked)."""
+    torch = _torch()
+    N = x.numel()
+    _check(x, torch.float32, (N,), "x"); _check(y, torch.float32, (N,), "y")
+    need = lib.stmf_dcor_workspace(N)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, x.device)
+    terms = torch.empty((N, 5), dtype=torch.float64, device=x.device) if row_terms else None
+    out = np.zeros(4, np.float64)
+    _chk(lib.stmf_distance_correlation(_ptr(x), _ptr(y), N, out.ctypes.data_as(C.c_void_p),
+                                       _ptr(terms), _ptr(ws), ws.numel(), _stream(stream)),
+         "stmf_distance_correlation")
+    res = dict(dcor=float(out[0]), dcov2=float(out[1]), dvarx2=float(out[2]), dvary2=float(out[3]))
+    if row_terms:
+        res["row_terms"] = terms
+    return res
+
+
+def stmf_completion_metrics(R, M_train, M_test, U, V, ws=None, stream=None):
+    """RMSE-A, RMSE-P and DC of a factorization on a held-out split (device
+    tensors); returns a dict with rmse_a, rmse_p, dc, n_train, n_test."""
+    torch = _torch()
+    m, n = R.shape
+    r = U.shape[1]
+    _check(R, torch.float32, (m, n), "R")
+    _check(M_train, torch.uint8, (m, n), "M_train"); _check(M_test, torch.uint8, (m, n), "M_test")
+    _check(U, torch.float32, (m, r), "U"); _check(V, torch.float32, (r, n), "V")
+    need = lib.stmf_completion_metrics_workspace(m, n, r)
+    if need == 0:
+        raise StmfError(STMF_EINVAL, "stmf_completion_metrics_workspace")
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, R.device)
+    out = np.zeros(5, np.float64)
+    _chk(lib.stmf_completion_metrics(_ptr(R), _ptr(M_train), _ptr(M_test), _ptr(U), _ptr(V), m, n, r,
+                                     out.ctypes.data_as(C.c_void_p), _ptr(ws), ws.numel(),
+                                     _stream(stream)), "stmf_completion_metrics")
+    return dict(rmse_a=float(out[0]), rmse_p=float(out[1]), dc=float(out[2]),
+                n_train=int(out[3]), n_test=int(out[4]))
+

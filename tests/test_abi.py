@@ -82,6 +82,16 @@ def test_argument_errors_before_any_gpu_work(stmf):
     o = stmf.options()
     assert L.stmf_fit(dummy, dummy, 4, 4, 0, 1, 0, dummy, dummy, None, C.byref(o), None,
                       C.c_void_p(256), 1 << 30, None) == stmf.STMF_EINVAL
+    assert L.stmf_distance_correlation(dummy, dummy, -1, dummy, None, C.c_void_p(256), 1 << 20,
+                                       None) == stmf.STMF_EINVAL
+    assert L.stmf_distance_correlation(dummy, dummy, 10, dummy, None, C.c_void_p(257), 1 << 20,
+                                       None) == stmf.STMF_ENOMEM
+    assert L.stmf_distance_correlation(dummy, dummy, 10, dummy, None, C.c_void_p(256), 8,
+                                       None) == stmf.STMF_ENOMEM
+    assert L.stmf_completion_metrics_workspace(0, 5, 2) == 0
+    assert L.stmf_completion_metrics_workspace(4, 5, 65) == 0
+    assert L.stmf_completion_metrics(dummy, dummy, dummy, dummy, dummy, 4, 5, 0, dummy,
+                                     C.c_void_p(256), 1 << 20, None) == stmf.STMF_EINVAL
     assert L.stmf_job_footprint(0, 5, 2, 1) == 0
     assert L.stmf_job_footprint(50, 40, 2, 1) > 50 * 40 * 8
 
