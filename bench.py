@@ -21,7 +21,9 @@ for bit); "serving" replays a Poisson stream of completion jobs through the
 continuous-batching loop and through the plain sequential path (p50/p99
 latency, jobs/s); "selections" runs the other ByRow selections (TD, TD_B,
 SEQ), ByElement with PermC and the PermR row order on the headline matrix
-for a few passes each.
+for a few passes each; "quality" measures completion quality (RMSE-A,
+RMSE-P, distance correlation on 20% held-out cells of R_lambda matrices)
+per strategy, and times the distance-correlation kernel on 600,000 cells.
 The first two are scaled down from the batched and serving
 workloads (shapes, ranks and passes stated in their "config") so that the
 default run stays within minutes.
@@ -186,6 +188,56 @@ def selections_compare(Rd, Md, omega):
             "runs": out}
 
 
+QUALITY = dict(m=200, n=200, rank=3, lams=(0.0, 0.5, 1.0), holdout=0.2, passes=30, seed=7,
+               dc_m=10000, dc_n=300)
+QUALITY_RUNS = [  # (name, strategy, selection, perm_mode)
+    ("TD_A (FastSTMF)", 0, 0, 0), ("TD", 0, 1, 0), ("TD_B", 0, 2, 0), ("SEQ", 0, 3, 0),
+    ("ByElement, PermC", 1, 0, 3),
+]
+FP64_PEAK_OPS = 256 * 64 * 2.4e9  # one non-FMA FP64 vector op per lane and cycle
+
+
+def quality_compare():
+    """Completion quality (Sec. 3.6) on R_lambda (Sec. 3.4) with 20% of the
+    cells held out (Sec. 3.7), per strategy, and the distance-correlation
+    kernel at the paper's large synthetic size (10000 x 300, 20% held out)."""
+    import numpy as np
+    import torch
+    from paper_2205_06619_amd import quality, stmf, synth
+    q = QUALITY
+    runs = []
+    for lam in q["lams"]:
+        R, M = synth.r_lambda(q["m"], q["n"], lam, rank=q["rank"], missing=0.0, seed=q["seed"])
+        for name, strategy, sel, pm in QUALITY_RUNS:
+            met, fit, _ = quality.evaluate(R, M, q["rank"], q["passes"], seed=q["seed"],
+                                           frac=q["holdout"], split_seed=q["seed"], init_mode=1,
+                                           strategy=strategy, selection=sel, perm_mode=pm)
+            runs.append({"lambda": lam, "method": name, "rmse_a": met["rmse_a"],
+                         "rmse_p": met["rmse_p"], "dc": met["dc"], "fit_s": met["fit_s"],
+                         "trials": met["trials"], "final_error": met["final_error"]})
+    # the DC kernel alone on 600,000 held-out cells
+    N = int(round(q["holdout"] * q["dc_m"] * q["dc_n"]))
+    rng = np.random.default_rng(q["seed"])
+    x = torch.from_numpy(rng.random(N).astype(np.float32)).cuda()
+    y = torch.from_numpy(rng.random(N).astype(np.float32)).cuda()
+    ws = stmf.workspace(stmf.lib.stmf_dcor_workspace(N))
+    stmf.stmf_distance_correlation(x, y, ws=ws)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stmf.stmf_distance_correlation(x, y, ws=ws)
+    dt = time.perf_counter() - t0
+    pairs = float(N) * N
+    return {
+        "config": {"workload": f"R_lambda {q['m']}x{q['n']}, rank {q['rank']}, lambda in "
+                               f"{list(q['lams'])}, {int(q['holdout'] * 100)}% of cells held out, "
+                               f"{q['passes']} passes, Random Acol init, seed {q['seed']}; DC kernel "
+                               f"on {N} held-out cells ({q['dc_m']}x{q['dc_n']})"},
+        "runs": runs,
+        "dcor_kernel": {"samples": N, "seconds": dt, "pairs_per_s": pairs / dt,
+                        "fp64_alu_frac": pairs * 10 / dt / FP64_PEAK_OPS},
+    }
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2205_06619_amd", "csrc")
@@ -253,8 +305,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--selections-only", action="store_true",
                     help="run only the selection comparison (one JSON line)")
+    ap.add_argument("--quality-only", action="store_true",
+                    help="run only the completion-quality comparison (one JSON line)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched, serving and selection comparisons")
+                    help="skip the batched, serving, selection and quality comparisons")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs a fit on a single MI355X "
@@ -279,6 +333,9 @@ def main():
 
     if args.selections_only:
         print(json.dumps(selections_compare(Rd, Md, omega)), flush=True)
+        return
+    if args.quality_only:
+        print(json.dumps(quality_compare()), flush=True)
         return
 
     def step():
@@ -343,6 +400,7 @@ def main():
         out["batched"] = batched_compare()
         out["serving"] = serving_compare()
         out["selections"] = selections_compare(Rd, Md, omega)
+        out["quality"] = quality_compare()
     print(json.dumps(out), flush=True)
 
 
