@@ -18,8 +18,11 @@
 //   * the other ByRow selections TD, TD_B and SEQ, and the row orders PermR
 //     (rows by increasing minimum) and none                   Sec. 3.2.1, 3.3
 //   * ByElement with PermC (columns by increasing minimum), TD
-//     selection of k                          Sec. 3.2.2, supplementary
+//     selection of k                          Sec. 3.2.2, 3.3, supplementary
 //                                             ByElement pseudocode
+//   * ByMatrix without permutation, TD selection of k, a random operation
+//                                             Sec. 3.2.3, supplementary
+//                                             ByMatrix pseudocode
 //
 // Every routine is a template over the value type T.  T = double is "the FP64
 // oracle": all value arithmetic in double on exactly promoted FP32 inputs.
@@ -69,6 +72,16 @@
 //     per row visit (j = -1);
 //   - PermC: working columns by increasing minimum observed value, ties by
 //     the lower working index; V's columns are put back at the output.
+//   - ByMatrix: one iteration keys every observed cell by
+//     err = (td_row(i) + td_col(j)) - td(i, j) (FP64, td_row summed over j
+//     ascending, td_col over i ascending) in the iteration's state and tries
+//     the cells by err descending, ties in row-major order, with k = f(i, j)
+//     from that state; the operation of the c-th cell tried in the fit
+//     (no-op skips included) is F-URF if the top bit of the c-th output of
+//     SplitMix64 seeded with seed ^ 0xA0761D6478BD642F is set, else F-ULF
+//     (a uniform draw below 1/2 selects F-ULF); the first strict decrease
+//     ends the iteration; an iteration without one is a fixed point.  Log:
+//     one record per iteration (row = the accepted row, else -1).
 //
 // Parity of the TD_A counting scope, the candidate tie order, the Random-Acol
 // column count and the random stream is unpinned: the paper fixes none of
@@ -227,11 +240,12 @@ struct oracle_opts {
   int selection;         // 0 TD_A, 1 TD, 2 TD_B, 3 SEQ
   int perm_mode;         // 0 random, 1 PermR (increasing minimum), 2 none,
                          // 3 PermC (columns by increasing minimum, rows as given)
-  int strategy;          // 0 ByRow, 1 ByElement
+  int strategy;          // 0 ByRow, 1 ByElement, 2 ByMatrix
 };
 
 struct oracle_log {      // ByRow: one record per row visit; ByElement: one per
-                         // accepted update and one closing each row visit
+                         // accepted update and one closing each row visit;
+                         // ByMatrix: one per iteration (row = accepted row)
   int32_t iter, row, trials, noops, j, k, op;  // j = -1: nothing accepted
   int32_t pad;
   double e;
@@ -470,29 +484,60 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
   const int sel = o ? o->selection : 0;
   if (sel < 0 || sel > 3) return EINVAL_;
   const int strategy = o ? o->strategy : 0;
-  if (strategy < 0 || strategy > 1) return EINVAL_;
+  if (strategy < 0 || strategy > 2) return EINVAL_;
 
   int it_done = 0;
   bool stop = false;
   int rows_left = row_limit > 0 ? row_limit : -1;
-  for (int it = 1; it <= iters && !stop; ++it) {
-    int64_t acc_this_pass = 0;
-    for (int i = 0; i < m; ++i) {
-      if (rows_left == 0) { stop = true; break; }
+  if (strategy == 2) {
+    // ByMatrix: one iteration = every observed cell keyed by
+    // err = td_row(i) + td_col(j) - td(i, j) from the iteration's state,
+    // tried in decreasing order (ties: row-major order) with k = f(i, j) and
+    // one operation drawn per cell (F-ULF when the draw is below 1/2) until
+    // the first strict decrease; at most one accepted update per iteration.
+    SplitMix64 gop{seed ^ 0xA0761D6478BD642Full};
+    std::vector<double> tdr((size_t)m), tdc((size_t)n), tij((size_t)m * n), key((size_t)m * n);
+    std::vector<int32_t> fk((size_t)m * n);
+    std::vector<int64_t> order;
+    for (int it = 1; it <= iters && !stop; ++it) {
+      if (rows_left == 0) break;
       if (rows_left > 0) --rows_left;
-      oracle_log rec{it, i, 0, 0, -1, -1, -1, 0, e};
+      std::fill(tdr.begin(), tdr.end(), 0.0);
+      std::fill(tdc.begin(), tdc.end(), 0.0);
+      order.clear();
+      for (int t = 0; t < m; ++t)
+        for (int j = 0; j < n; ++j) {
+          const size_t q = (size_t)t * n + j;
+          T best = U[(size_t)t * r] + V[j];
+          int arg = 0;
+          for (int l = 1; l < r; ++l) {
+            T x = U[(size_t)t * r + l] + V[(size_t)l * n + j];
+            if (x > best) { best = x; arg = l; }
+          }
+          fk[q] = arg;
+          if (!M[q]) continue;
+          const T d = R[q] - best;
+          tij[q] = std::fabs((double)d);
+          tdr[t] += tij[q];
+          tdc[j] += tij[q];
+          order.push_back((int64_t)q);
+        }
+      for (int64_t q : order) key[q] = (tdr[q / n] + tdc[q % n]) - tij[q];
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int64_t a, int64_t b) { return key[a] > key[b]; });
+      oracle_log rec{it, -1, 0, 0, -1, -1, -1, 0, e};
       bool accepted = false;
-      // One trial on the current state (U, V changed; restore() undoes it).
-      // Returns false for a no-op skip, counted as a rejection.
-      auto try_op = [&](int j, int k, int op, double& e2) -> bool {
+      for (int64_t q : order) {
+        const int i = (int)(q / n), j = (int)(q % n), k = fk[q];
+        const int op = (gop.next() >> 63) ? 1 : 0;
         T* Uik = &U[(size_t)i * r + k];
         T* Vkj = &V[(size_t)k * n + j];
-        T Rij = R[(size_t)i * n + j];
+        const T Rij = R[q];
         if (noop_rule && closed[k]) {
-          bool same = op == 0 ? (T)(Rij - *Vkj) == *Uik : (T)(Rij - *Uik) == *Vkj;
-          if (same) { rec.noops++; S.noops++; return false; }
+          const bool same = op == 0 ? (T)(Rij - *Vkj) == *Uik : (T)(Rij - *Uik) == *Vkj;
+          if (same) { rec.noops++; S.noops++; continue; }
         }
-        e2 = op == 0
+        const double e2 = op == 0
             ? f_ulf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k,
                     Ubak.data(), Vbak.data(), td_try.data(), A_try.data())
             : f_urf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k,
@@ -500,157 +545,208 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
         rec.trials++;
         S.trials++;
         S.evaluated_cells += omega;
-        return true;
-      };
-      auto restore = [&](int k) {
+        if (e2 < e) {
+          e = e2;
+          td.swap(td_try);
+          A.swap(A_try);
+          closed[k] = 1;
+          accepted = true;
+          rec.row = i; rec.j = j; rec.k = k; rec.op = op; rec.e = e;
+          S.accepted++;
+          break;
+        }
         for (int t = 0; t < m; ++t) U[(size_t)t * r + k] = Ubak[t];
         for (int c = 0; c < n; ++c) V[(size_t)k * n + c] = Vbak[c];
-      };
-      auto accept = [&](int j, int k, int op, double e2) {
-        e = e2;
-        td.swap(td_try);
-        A.swap(A_try);
-        closed[k] = 1;
-        accepted = true;
-        rec.j = j; rec.k = k; rec.op = op; rec.e = e;
-        S.accepted++;
-        acc_this_pass++;
-      };
-      // (U (x) V)_tj of the current state
-      auto prod = [&](int t, int j) {
-        T best = U[(size_t)t * r + 0] + V[j];
-        for (int l = 1; l < r; ++l) {
-          T x = U[(size_t)t * r + l] + V[(size_t)l * n + j];
-          if (x > best) best = x;
-        }
-        return best;
-      };
-      if (strategy == 1) {
-        // ByElement: every observed (i, j) of the row in working column
-        // order, k = f(i, j), F-ULF then F-URF; a perfect entry (td = 0) is
-        // not updated; after an accepted update the visit goes on with the
-        // next element
-        for (int j = 0; j < n; ++j) {
-          if (!M[(size_t)i * n + j]) continue;
-          T best = U[(size_t)i * r] + V[j];
-          int k = 0;
-          for (int l = 1; l < r; ++l) {
-            T x = U[(size_t)i * r + l] + V[(size_t)l * n + j];
-            if (x > best) { best = x; k = l; }
-          }
-          if ((T)(R[(size_t)i * n + j] - best) == (T)0) continue;
-          accepted = false;
-          for (int op = 0; op < 2 && !accepted; ++op) {
-            double e2;
-            if (!try_op(j, k, op, e2)) continue;
-            if (e2 < e) accept(j, k, op, e2);
-            else restore(k);
-          }
-          if (accepted) {
-            if (log && nlog < log_cap) log[nlog] = rec;
-            nlog++;
-            rec = oracle_log{it, i, 0, 0, -1, -1, -1, 0, e};
-          }
-        }
-        rec.e = e;
-        if (log && nlog < log_cap) log[nlog] = rec;
-        nlog++;
-        continue;
       }
-      std::vector<int> cand;  // observed columns of row i
-      for (int j = 0; j < n; ++j)
-        if (M[(size_t)i * n + j]) cand.push_back(j);
-
-      if (sel == 3) {
-        // SEQ: every (j, k, operation), the smallest error below e wins
-        int bj = -1, bk = -1, bop = -1;
-        double be = e;
-        for (int j : cand)
-          for (int k = 0; k < r; ++k)
-            for (int op = 0; op < 2; ++op) {
-              double e2;
-              if (!try_op(j, k, op, e2)) continue;
-              if (e2 < be) { be = e2; bj = j; bk = k; bop = op; }
-              restore(k);
-            }
-        if (bj >= 0) {
-          // apply the chosen update again (the same arithmetic, the same result)
-          double e2 = bop == 0
-              ? f_ulf(R.data(), M, U.data(), V.data(), m, n, r, i, bj, bk,
-                      Ubak.data(), Vbak.data(), td_try.data(), A_try.data())
-              : f_urf(R.data(), M, U.data(), V.data(), m, n, r, i, bj, bk,
-                      Ubak.data(), Vbak.data(), td_try.data(), A_try.data());
-          accept(bj, bk, bop, e2);
-        }
-      } else {
-        // candidate order and the component of each candidate
-        std::vector<int> kof((size_t)n, 0);
-        if (sel == 1) {
-          // TD: entry error td(i, j) descending; k = f(i, j)
-          std::vector<double> tij((size_t)n, 0.0);
-          for (int j : cand) {
-            T d = R[(size_t)i * n + j] - prod(i, j);
-            tij[j] = std::fabs((double)d);
-            kof[j] = A[(size_t)i * n + j];
-          }
-          std::stable_sort(cand.begin(), cand.end(),
-                           [&](int a, int b) { return tij[a] > tij[b]; });
-        } else {
-          // TD_A and TD_B: td_col descending
-          std::stable_sort(cand.begin(), cand.end(),
-                           [&](int a, int b) { return td[a] > td[b]; });
-          if (sel == 0) {
-            // TD_A: the index counted most often in the two argmax multisets
-            std::vector<int> crow((size_t)r, 0);
-            for (int t = 0; t < n; ++t)
-              if (scope_all || M[(size_t)i * n + t]) crow[A[(size_t)i * n + t]]++;
-            for (int j : cand) {
-              std::vector<int> cnt(crow);
-              for (int t = 0; t < m; ++t)
-                if (scope_all || M[(size_t)t * n + j]) cnt[A[(size_t)t * n + j]]++;
-              int k = 0;
-              for (int l = 1; l < r; ++l)
-                if (cnt[l] > cnt[k]) k = l;
-              kof[j] = k;
-            }
-          } else {
-            // TD_B: j0 = largest td_col, i0 = the first working row
-            int j0 = 0;
-            for (int t = 1; t < n; ++t)
-              if (td[t] > td[j0]) j0 = t;
-            const int i0 = 0;
-            const T p_ij0 = prod(i, j0);
-            const int f_ij0 = A[(size_t)i * n + j0];
-            for (int j : cand)
-              kof[j] = p_ij0 >= prod(i0, j) ? f_ij0 : A[(size_t)i0 * n + j];
-          }
-        }
-        for (int j : cand) {
-          const int k = kof[j];
-          for (int op = 0; op < 2 && !accepted; ++op) {
-            double e2;
-            if (!try_op(j, k, op, e2)) continue;
-            if (e2 < e) accept(j, k, op, e2);
-            else restore(k);
-          }
-          if (accepted) break;
-        }
-      }
-      S.row_visits++;
       if (log && nlog < log_cap) log[nlog] = rec;
       nlog++;
+      it_done = it;
+      if (traj) traj[it] = e;
+      if (!accepted) {
+        if (traj)
+          for (int qq = it + 1; qq <= iters; ++qq) traj[qq] = e;
+        stop = true;
+      }
     }
-    if (stop && rows_left == 0) break;
-    it_done = it;
-    if (traj) traj[it] = e;
-    bool fixed_point = acc_this_pass == 0;
-    bool small_step = eps > 0.0 && traj && (traj[it - 1] - traj[it] < eps);
-    if (fixed_point || small_step) {
-      if (traj)
-        for (int q = it + 1; q <= iters; ++q) traj[q] = e;
-      stop = true;
+  } else {
+    for (int it = 1; it <= iters && !stop; ++it) {
+      int64_t acc_this_pass = 0;
+      for (int i = 0; i < m; ++i) {
+        if (rows_left == 0) { stop = true; break; }
+        if (rows_left > 0) --rows_left;
+        oracle_log rec{it, i, 0, 0, -1, -1, -1, 0, e};
+        bool accepted = false;
+        // One trial on the current state (U, V changed; restore() undoes it).
+        // Returns false for a no-op skip, counted as a rejection.
+        auto try_op = [&](int j, int k, int op, double& e2) -> bool {
+          T* Uik = &U[(size_t)i * r + k];
+          T* Vkj = &V[(size_t)k * n + j];
+          T Rij = R[(size_t)i * n + j];
+          if (noop_rule && closed[k]) {
+            bool same = op == 0 ? (T)(Rij - *Vkj) == *Uik : (T)(Rij - *Uik) == *Vkj;
+            if (same) { rec.noops++; S.noops++; return false; }
+          }
+          e2 = op == 0
+              ? f_ulf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k,
+                      Ubak.data(), Vbak.data(), td_try.data(), A_try.data())
+              : f_urf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k,
+                      Ubak.data(), Vbak.data(), td_try.data(), A_try.data());
+          rec.trials++;
+          S.trials++;
+          S.evaluated_cells += omega;
+          return true;
+        };
+        auto restore = [&](int k) {
+          for (int t = 0; t < m; ++t) U[(size_t)t * r + k] = Ubak[t];
+          for (int c = 0; c < n; ++c) V[(size_t)k * n + c] = Vbak[c];
+        };
+        auto accept = [&](int j, int k, int op, double e2) {
+          e = e2;
+          td.swap(td_try);
+          A.swap(A_try);
+          closed[k] = 1;
+          accepted = true;
+          rec.j = j; rec.k = k; rec.op = op; rec.e = e;
+          S.accepted++;
+          acc_this_pass++;
+        };
+        // (U (x) V)_tj of the current state
+        auto prod = [&](int t, int j) {
+          T best = U[(size_t)t * r + 0] + V[j];
+          for (int l = 1; l < r; ++l) {
+            T x = U[(size_t)t * r + l] + V[(size_t)l * n + j];
+            if (x > best) best = x;
+          }
+          return best;
+        };
+        if (strategy == 1) {
+          // ByElement: every observed (i, j) of the row in working column
+          // order, k = f(i, j), F-ULF then F-URF; a perfect entry (td = 0) is
+          // not updated; after an accepted update the visit goes on with the
+          // next element
+          for (int j = 0; j < n; ++j) {
+            if (!M[(size_t)i * n + j]) continue;
+            T best = U[(size_t)i * r] + V[j];
+            int k = 0;
+            for (int l = 1; l < r; ++l) {
+              T x = U[(size_t)i * r + l] + V[(size_t)l * n + j];
+              if (x > best) { best = x; k = l; }
+            }
+            if ((T)(R[(size_t)i * n + j] - best) == (T)0) continue;
+            accepted = false;
+            for (int op = 0; op < 2 && !accepted; ++op) {
+              double e2;
+              if (!try_op(j, k, op, e2)) continue;
+              if (e2 < e) accept(j, k, op, e2);
+              else restore(k);
+            }
+            if (accepted) {
+              if (log && nlog < log_cap) log[nlog] = rec;
+              nlog++;
+              rec = oracle_log{it, i, 0, 0, -1, -1, -1, 0, e};
+            }
+          }
+          rec.e = e;
+          if (log && nlog < log_cap) log[nlog] = rec;
+          nlog++;
+          continue;
+        }
+        std::vector<int> cand;  // observed columns of row i
+        for (int j = 0; j < n; ++j)
+          if (M[(size_t)i * n + j]) cand.push_back(j);
+
+        if (sel == 3) {
+          // SEQ: every (j, k, operation), the smallest error below e wins
+          int bj = -1, bk = -1, bop = -1;
+          double be = e;
+          for (int j : cand)
+            for (int k = 0; k < r; ++k)
+              for (int op = 0; op < 2; ++op) {
+                double e2;
+                if (!try_op(j, k, op, e2)) continue;
+                if (e2 < be) { be = e2; bj = j; bk = k; bop = op; }
+                restore(k);
+              }
+          if (bj >= 0) {
+            // apply the chosen update again (the same arithmetic, the same result)
+            double e2 = bop == 0
+                ? f_ulf(R.data(), M, U.data(), V.data(), m, n, r, i, bj, bk,
+                        Ubak.data(), Vbak.data(), td_try.data(), A_try.data())
+                : f_urf(R.data(), M, U.data(), V.data(), m, n, r, i, bj, bk,
+                        Ubak.data(), Vbak.data(), td_try.data(), A_try.data());
+            accept(bj, bk, bop, e2);
+          }
+        } else {
+          // candidate order and the component of each candidate
+          std::vector<int> kof((size_t)n, 0);
+          if (sel == 1) {
+            // TD: entry error td(i, j) descending; k = f(i, j)
+            std::vector<double> tij((size_t)n, 0.0);
+            for (int j : cand) {
+              T d = R[(size_t)i * n + j] - prod(i, j);
+              tij[j] = std::fabs((double)d);
+              kof[j] = A[(size_t)i * n + j];
+            }
+            std::stable_sort(cand.begin(), cand.end(),
+                             [&](int a, int b) { return tij[a] > tij[b]; });
+          } else {
+            // TD_A and TD_B: td_col descending
+            std::stable_sort(cand.begin(), cand.end(),
+                             [&](int a, int b) { return td[a] > td[b]; });
+            if (sel == 0) {
+              // TD_A: the index counted most often in the two argmax multisets
+              std::vector<int> crow((size_t)r, 0);
+              for (int t = 0; t < n; ++t)
+                if (scope_all || M[(size_t)i * n + t]) crow[A[(size_t)i * n + t]]++;
+              for (int j : cand) {
+                std::vector<int> cnt(crow);
+                for (int t = 0; t < m; ++t)
+                  if (scope_all || M[(size_t)t * n + j]) cnt[A[(size_t)t * n + j]]++;
+                int k = 0;
+                for (int l = 1; l < r; ++l)
+                  if (cnt[l] > cnt[k]) k = l;
+                kof[j] = k;
+              }
+            } else {
+              // TD_B: j0 = largest td_col, i0 = the first working row
+              int j0 = 0;
+              for (int t = 1; t < n; ++t)
+                if (td[t] > td[j0]) j0 = t;
+              const int i0 = 0;
+              const T p_ij0 = prod(i, j0);
+              const int f_ij0 = A[(size_t)i * n + j0];
+              for (int j : cand)
+                kof[j] = p_ij0 >= prod(i0, j) ? f_ij0 : A[(size_t)i0 * n + j];
+            }
+          }
+          for (int j : cand) {
+            const int k = kof[j];
+            for (int op = 0; op < 2 && !accepted; ++op) {
+              double e2;
+              if (!try_op(j, k, op, e2)) continue;
+              if (e2 < e) accept(j, k, op, e2);
+              else restore(k);
+            }
+            if (accepted) break;
+          }
+        }
+        S.row_visits++;
+        if (log && nlog < log_cap) log[nlog] = rec;
+        nlog++;
+      }
+      if (stop && rows_left == 0) break;
+      it_done = it;
+      if (traj) traj[it] = e;
+      bool fixed_point = acc_this_pass == 0;
+      bool small_step = eps > 0.0 && traj && (traj[it - 1] - traj[it] < eps);
+      if (fixed_point || small_step) {
+        if (traj)
+          for (int q = it + 1; q <= iters; ++q) traj[q] = e;
+        stop = true;
+      }
     }
   }
+
   S.iters_done = it_done;
   if (log_len) *log_len = nlog;
   if (st) *st = S;

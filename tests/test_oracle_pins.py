@@ -484,7 +484,7 @@ def test_selection_defaults_are_faststmf():
     np.testing.assert_array_equal(a.U, b.U); np.testing.assert_array_equal(a.traj, b.traj)
     assert oracle.fit(R, M, 3, 1, selection=4).status == 1
     assert oracle.fit(R, M, 3, 1, perm_mode=4).status == 1
-    assert oracle.fit(R, M, 3, 1, strategy=2).status == 1
+    assert oracle.fit(R, M, 3, 1, strategy=3).status == 1
 
 
 # ------------------------------------------------------------------ ByElement
@@ -710,3 +710,123 @@ def test_fixed_point_padding():
     assert a.stats["iters_done"] < 40
     d = a.stats["iters_done"]
     assert np.all(a.traj[d:] == a.traj[d])
+
+
+# ------------------------------------------------------------------ ByMatrix
+BYMATRIX_OP_STREAM = 0xA0761D6478BD642F  # seed XOR this: the operation draws
+
+
+def _brute_force_bymatrix(R, M, U, V, iters, prec, seed, noop_rule=True):
+    """Independent restatement of ByMatrix (Sec. 3.2.3 and its supplementary
+    pseudocode): per iteration, td(i, j) and f(i, j) from each entry's own
+    max-plus terms, td_row and td_col summed in plain loops, the key
+    td_row(i) + td_col(j) - td(i, j), cells sorted by key descending (ties
+    by row-major position), one operation per cell from the published
+    SplitMix64 stream (F-ULF when the top bit is 0), the pinned update
+    routine, the first strict decrease accepted and the iteration ended."""
+    m, n = R.shape; r = U.shape[1]
+    T = np.float32 if prec == "f32" else np.float64
+    e, _, _ = oracle.masked_error(R, M, U, V, prec)
+    draws = iter(int(x) for x in oracle.splitmix64(seed ^ BYMATRIX_OP_STREAM, 100000))
+    closed = [False] * r
+    recs, traj = [], [e]
+    for it in range(1, iters + 1):
+        td = {}
+        f = {}
+        for i in range(m):
+            for j in range(n):
+                if M[i, j]:
+                    td[(i, j)] = abs(float(T(T(R[i, j]) - _maxplus_entry(U, V, i, j, T))))
+                    f[(i, j)] = _argmax_entry(U, V, i, j, T)
+        tdr = [0.0] * m
+        tdc = [0.0] * n
+        for i in range(m):
+            for j in range(n):
+                if M[i, j]:
+                    tdr[i] += td[(i, j)]
+                    tdc[j] += td[(i, j)]
+        cells = sorted(td, key=lambda c: (-((tdr[c[0]] + tdc[c[1]]) - td[c]), c[0] * n + c[1]))
+        rec = [it, -1, 0, 0, -1, -1, -1, e]
+        accepted = False
+        for (i, j) in cells:
+            k = f[(i, j)]
+            op = "V" if next(draws) >> 63 else "U"
+            if noop_rule and closed[k]:
+                same = (T(T(R[i, j]) - T(V[k, j])) == T(U[i, k])) if op == "U" else \
+                       (T(T(R[i, j]) - T(U[i, k])) == T(V[k, j]))
+                if same:
+                    rec[3] += 1
+                    continue
+            U2, V2, e2, *_ = oracle.update(op, R, M, U, V, i, j, k, prec)
+            rec[2] += 1
+            if e2 < e:
+                U, V, e = U2, V2, e2
+                closed[k] = True
+                rec[1], rec[4], rec[5], rec[6], rec[7] = i, j, k, 0 if op == "U" else 1, e
+                accepted = True
+                break
+        recs.append(tuple(rec))
+        traj.append(e)
+        if not accepted:
+            traj += [e] * (iters - it)
+            break
+    return recs, U, V, traj
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("seed", range(4))
+def test_bymatrix_matches_brute_force(prec, seed):
+    m, n, r = 5, 7, 3
+    R, M = synth.tiny_int_case(m, n, r, 120 + seed, hi=9, missing=0.25, planted=seed % 2 == 0)
+    U0 = np.random.default_rng(seed).integers(0, 10, (m, r)).astype(np.float32)
+    iters = 8
+    res = oracle.fit(R, M, r, iters, seed=seed, prec=prec, init_mode=2, U0=U0, perm_mode=2,
+                     strategy=2, log_cap=100)
+    assert res.status == 0
+    U = U0.astype(np.float64); V = np.zeros((r, n))
+    for k in range(r):
+        V = oracle.col_res(R, M, U, V, k, prec)
+    recs, Ub, Vb, traj = _brute_force_bymatrix(R, M, U, V, iters, prec, seed)
+    got = [(int(x["iter"]), int(x["row"]), int(x["trials"]), int(x["noops"]), int(x["j"]),
+            int(x["k"]), int(x["op"]), float(x["e"])) for x in res.log]
+    assert got == recs
+    assert sum(1 for x in recs if x[4] >= 0) > 0
+    np.testing.assert_array_equal(res.U, Ub.astype(np.float32))
+    np.testing.assert_array_equal(res.V, Vb.astype(np.float32))
+    np.testing.assert_array_equal(res.traj, traj)
+
+
+def test_bymatrix_at_an_exact_factorization_tries_every_cell_once():
+    # e = 0: no trial can decrease it, so the first iteration tries (or skips
+    # as a no-op) every observed cell once and is a fixed point
+    rng = np.random.default_rng(4)
+    Us = rng.integers(0, 20, (5, 2)).astype(np.float32)
+    Vs = rng.integers(0, 20, (2, 8)).astype(np.float32)
+    R = np.max(Us[:, :, None] + Vs[None, :, :], axis=1).astype(np.float32)
+    M = np.ones_like(R, np.uint8)
+    a = oracle.fit(R, M, 2, 3, prec="f64", init_mode=2, U0=Us, perm_mode=2, strategy=2)
+    assert a.status == 0 and a.stats["accepted"] == 0 and a.stats["iters_done"] == 1
+    assert a.log[0]["trials"] + a.log[0]["noops"] == 40
+    np.testing.assert_array_equal(a.traj, [0.0] * 4)
+
+
+def test_bymatrix_one_update_per_iteration_and_seed_drives_operations():
+    R, M = synth.int_planted(12, 18, 2, seed=21, hi=30)
+    kw = dict(prec="f32", init_hi=30, perm_mode=2, strategy=2, log_cap=100)
+    a = oracle.fit(R, M, 2, 15, seed=1, **kw)
+    b = oracle.fit(R, M, 2, 15, seed=1, **kw)
+    assert a.status == 0
+    np.testing.assert_array_equal(a.traj, b.traj)
+    assert np.all(np.diff(a.traj) <= 0)
+    acc = [x for x in a.log if x["j"] >= 0]
+    assert len(acc) == a.stats["accepted"] <= 15
+    for x, prev in zip(a.log, a.traj[:-1]):
+        if x["j"] >= 0:
+            assert x["e"] < prev and x["row"] >= 0
+    # another seed draws other operations (same initial U via init_mode 2)
+    U0 = np.random.default_rng(0).integers(0, 30, (12, 2)).astype(np.float32)
+    c = oracle.fit(R, M, 2, 15, seed=1, init_mode=2, U0=U0, **kw)
+    d = oracle.fit(R, M, 2, 15, seed=2, init_mode=2, U0=U0, **kw)
+    ops_c = [int(x["op"]) for x in c.log]; ops_d = [int(x["op"]) for x in d.log]
+    assert ops_c != ops_d or not np.array_equal(c.traj, d.traj)
+
