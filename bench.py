@@ -20,8 +20,8 @@ launch and through the plain one-fit-at-a-time path (results compared bit
 for bit); "serving" replays a Poisson stream of completion jobs through the
 continuous-batching loop and through the plain sequential path (p50/p99
 latency, jobs/s); "selections" runs the other ByRow selections (TD, TD_B,
-SEQ), ByElement with PermC and the PermR row order on the headline matrix
-for a few passes each; "quality" measures completion quality (RMSE-A,
+SEQ), ByElement with PermC, ByMatrix (300 iterations of at most one update
+each) and the PermR row order on the headline matrix for a few passes each; "quality" measures completion quality (RMSE-A,
 RMSE-P, distance correlation on 20% held-out cells of R_lambda matrices)
 per strategy, and times the distance-correlation kernel on 600,000 cells.
 The first two are scaled down from the batched and serving
@@ -149,7 +149,7 @@ def serving_compare():
 
 SELECTIONS = [  # (name, strategy, selection, perm_mode, passes)
     ("TD_A, PermR", 0, 0, 1, 10), ("TD", 0, 1, 0, 10), ("TD_B", 0, 2, 0, 10), ("SEQ", 0, 3, 0, 1),
-    ("ByElement, PermC", 1, 0, 3, 1),
+    ("ByElement, PermC", 1, 0, 3, 1), ("ByMatrix, NoPerm", 2, 0, 2, 300),
 ]
 
 

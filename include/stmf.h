@@ -170,7 +170,24 @@ typedef struct {
                              the previous record of the visit) and one closing
                              each row visit (j = -1).  The paper's
                              STMF_ByElement_PermC_TD_W is strategy 1 with
-                             perm_mode 3.                                       */
+                             perm_mode 3.
+                           2 ByMatrix (Sec. 3.2.3 and its supplementary
+                             pseudocode): `iters` counts iterations, each with
+                             at most one accepted update: every observed cell
+                             is keyed by td_row(i) + td_col(j) - td(i, j) (FP64)
+                             and tried by that key descending (ties row-major)
+                             with k = f(i, j) and one operation drawn per cell
+                             tried (F-URF when the top bit of output c of
+                             SplitMix64 seeded with seed ^ 0xA0761D6478BD642F
+                             is set, c counting the fit's cells tried, no-op
+                             skips included) until the first strict decrease;
+                             an iteration without one ends the fit.
+                             decision_log: one record per iteration (row = the
+                             accepted row, else -1).  The paper's
+                             STMF_ByMatrix_NoPerm_TD_W is strategy 2 with
+                             perm_mode 2.  stmf_fit only (the batched and
+                             serving calls return STMF_EINVAL); the workspace
+                             grows by about 20 bytes per cell.                  */
 } stmf_options;
 
 /* Per-row-visit decision record (decision_log). */

@@ -45,7 +45,8 @@ namespace stmf {
 static constexpr float FINF = __builtin_huge_valf();
 static constexpr unsigned long long BARRIER_TIMEOUT = 400000000ull;  // 4 s at 100 MHz
 static constexpr int ST_TIMEOUT = 7;
-static constexpr int ST_INTERNAL = 8;   // a re-evaluated trial did not reproduce its error
+static constexpr int ST_INTERNAL = 8;   // an internal consistency check failed (a re-evaluated
+                                        // trial's error, a selection's count)
 static constexpr int RPW = TS / NWAVE;  // tile rows (or columns) per wave
 static constexpr int CQ_CAP = NTHR + CW + 128;
 static constexpr int KB = 8;            // components whose summaries are staged together
@@ -166,6 +167,7 @@ struct Smem {
   float uk[TS], vk[TS];      // new component values of the tile (refresh)
   double wsum[TMAX];         // per trial: this workgroup's partial error
   Trial trials[TMAX];
+  int trow[TMAX];            // ByMatrix: each trial's row (a batch mixes rows)
   int noops_before[TMAX];    // no-op skips preceding each trial in the batch
   int byk[TMAX];             // trial indices by key op * RMAX + k (stable)
   int kst[2 * RMAX + 1];     // key q: byk[kst[q] .. kst[q + 1])
@@ -174,6 +176,8 @@ struct Smem {
   float Ri[TS];              // R of the visited row at the tile columns
   // summaries of a block of up to KB components (kb0, kb0 + 1, ...) at the tile
   float colb[KB][TS];        // F-ULF: column residual without row i, excl(colst_kc, i)
+  float2 cmm[KB][TS];        // ByMatrix: colst_kc's (m1, m2), and a1 (the exclusion
+  int ca1[KB][TS];           // depends on each trial's row; selected as values)
   float2 rmm[KB][TS];        // F-URF: row residual summaries of the tile rows: (m1, m2)
   int ra1[KB][TS];           // and a1 (both values are read and one is selected)
   float urow_i[RMAX];        // U of the visited row, every component
@@ -205,6 +209,10 @@ struct Smem {
   float urow0[RMAX];
   float p_ij0;
   int f_ij0;
+  // ByMatrix selection
+  unsigned long long m_pref;
+  int m_want, m_count, m_used;
+  unsigned m_qpref;
 };
 
 static_assert(sizeof(Smem) <= 160 * 1024, "LDS layout exceeds a CU's 160 KB");
@@ -344,6 +352,7 @@ DEV void stage_ri(Grp& gp, Smem& S, int i, int c0) {
 // Summaries of components kb0 .. kb0 + nb - 1 (nb <= KB) at the tile, one
 // thread per component and tile index, all loads in one round: the column
 // summaries without row i (cols) and the row summaries (rows).
+template <bool MR = false>
 DEV void stage_block(Grp& gp, Smem& S, int kb0, int nb, bool cols, bool rows, int r0, int c0,
                      int i) {
   const FitDev& d = *gp.d;
@@ -352,7 +361,15 @@ DEV void stage_block(Grp& gp, Smem& S, int kb0, int nb, bool cols, bool rows, in
   const size_t ldm = d.ldm, ldn = d.ldn;
   const int b = gp.tid / TS, x = gp.tid % TS;
   if (b < nb) {
-    if (cols) S.colb[b][x] = excl(ld_top2(&colst[(kb0 + b) * ldn + c0 + x]), i);
+    if (cols) {
+      const Top2 t = ld_top2(&colst[(kb0 + b) * ldn + c0 + x]);
+      if (MR) {
+        S.cmm[b][x] = make_float2(t.m1, t.m2);
+        S.ca1[b][x] = t.a1;
+      } else {
+        S.colb[b][x] = excl(t, i);
+      }
+    }
     if (rows) {
       const Top2 t = ld_top2(&rowst[(kb0 + b) * ldm + r0 + x]);
       S.rmm[b][x] = make_float2(t.m1, t.m2);
@@ -374,31 +391,34 @@ DEV int list_at(const Smem& S, int p, int a0, int n0, int a1) {
 struct WaveTrials {
   int q, j, k, op;
   float val;
+  int i;                     // ByMatrix: the trial's row
 };
 // Chunk positions cs .. cs + cn - 1 of the trial list made of the byk ranges
 // [a0, a0 + n0) and [a1, ...).
-template <int NE>
+template <int NE, bool MR = false>
 DEV WaveTrials wave_trials(const Grp& gp, const Smem& S, int cs, int cn, int a0, int n0, int a1) {
   WaveTrials w;
-  w.q = -1; w.j = 0; w.k = 0; w.op = OP_NULL; w.val = 0.0f;
+  w.q = -1; w.j = 0; w.k = 0; w.op = OP_NULL; w.val = 0.0f; w.i = 0;
   const int sl = gp.wave + NWAVE * gp.lane;
   if (gp.lane < NE && sl < cn) {
     w.q = list_at(S, cs + sl, a0, n0, a1);
     const Trial tr = S.trials[w.q];
     w.j = tr.j; w.k = tr.k; w.op = tr.op; w.val = tr.val;
+    if (MR) w.i = S.trow[w.q];
   }
   return w;
 }
 // The same for the byk range [base, base + cn).
-template <int NE>
+template <int NE, bool MR = false>
 DEV WaveTrials wave_trials_range(const Grp& gp, const Smem& S, int base, int cn) {
   WaveTrials w;
-  w.q = -1; w.j = 0; w.k = 0; w.op = OP_NULL; w.val = 0.0f;
+  w.q = -1; w.j = 0; w.k = 0; w.op = OP_NULL; w.val = 0.0f; w.i = 0;
   const int sl = gp.wave + NWAVE * gp.lane;
   if (gp.lane < NE && sl < cn) {
     w.q = S.byk[base + sl];
     const Trial tr = S.trials[w.q];
     w.j = tr.j; w.k = tr.k; w.op = tr.op; w.val = tr.val;
+    if (MR) w.i = S.trow[w.q];
   }
   return w;
 }
@@ -413,6 +433,9 @@ DEV float lane_f(float v, int l) { return __int_as_float(__builtin_amdgcn_readla
 // of components the summaries are staged once; each trial then stages the
 // one first-residual vector it needs, 2 * TCH trials at a time (wave w takes
 // trials w, w + NWAVE, ...), every global load issued before any is used.
+// With MR (ByMatrix) the trials of a batch have rows of their own: the F-ULF
+// first residual takes R's row and the column summary's exclusion per trial.
+template <bool MR = false>
 DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
   const FitDev& d = *gp.d;
   // descriptor fields, read once (the atomics below would force reloads)
@@ -447,13 +470,30 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
         const int lo = S.kst[side * RMAX + kb0], hi = S.kst[side * RMAX + kb0 + nb];
         if (lo == hi) continue;
         __syncthreads();
-        stage_block(gp, S, kb0, nb, side == 0, side == 1, r0, c0, i);
+        stage_block<MR>(gp, S, kb0, nb, side == 0, side == 1, r0, c0, i);
 #pragma unroll 1
         for (int cs = lo; cs < hi; cs += 2 * TCH) {
           const int cn = hi - cs < 2 * TCH ? hi - cs : 2 * TCH;
           __syncthreads();
-          const WaveTrials w = wave_trials_range<NE>(gp, S, cs, cn);
-          if (side == 0) {
+          const WaveTrials w = wave_trials_range<NE, MR>(gp, S, cs, cn);
+          if (side == 0 && MR) {
+            float raw[NE];
+#pragma unroll
+            for (int m = 0; m < NE; ++m) {
+              const int sl = gp.wave + m * NWAVE;
+              if (sl < cn) raw[m] = Rw[lane_i(w.i, m) * ldn + c0 + x];
+            }
+#pragma unroll
+            for (int m = 0; m < NE; ++m) {
+              const int sl = gp.wave + m * NWAVE;
+              if (sl < cn) {
+                const int b = lane_i(w.k, m) - kb0;
+                const float2 mm = S.cmm[b][x];
+                const float ex = S.ca1[b][x] == lane_i(w.i, m) ? mm.y : mm.x;
+                S.u.b.v.sX[sl][x] = in ? vmin(ex, raw[m] - lane_f(w.val, m)) : 0.0f;
+              }
+            }
+          } else if (side == 0) {
             const float ri = S.Ri[x];
 #pragma unroll
             for (int m = 0; m < NE; ++m) {
@@ -559,7 +599,7 @@ DEV Chunk chunk_at(const Smem& S, int r, int k, int cs) {
 // Global loads of a chunk's trials (wave w: trials w, w + NWAVE, ...):
 // F-ULF: the second residual at the tile rows; F-URF: R's column j at the
 // tile rows and the second residual at the tile columns.
-template <int NE>
+template <int NE, bool MR = false>
 DEV void chunk_loads(Grp& gp, const WaveTrials& w, const Chunk& c, int par, int r0, int c0,
                      float (&rawA)[NE], unsigned (&rawB)[NE]) {
   const FitDev& d = *gp.d;
@@ -573,6 +613,7 @@ DEV void chunk_loads(Grp& gp, const WaveTrials& w, const Chunk& c, int par, int 
       const int q = lane_i(w.q, m), op = lane_i(w.op, m);
       if (op == OP_ULF) {
         rawB[m] = ld_atomic(&tv[q * ldx + r0 + x]);
+        if (MR) rawA[m] = d.Rw[(size_t)lane_i(w.i, m) * d.ldn + c0 + x];
       } else if (op == OP_URF) {
         rawA[m] = RwT[lane_i(w.j, m) * ldm + r0 + x];
         rawB[m] = ld_atomic(&tv[q * ldx + c0 + x]);
@@ -584,7 +625,7 @@ DEV void chunk_loads(Grp& gp, const WaveTrials& w, const Chunk& c, int par, int 
 // The trials' two vectors into LDS: the first residual from the staged
 // summaries (block b of the component), the second from the loads.  The null
 // trial of the initial evaluation (always alone) takes the current component.
-template <int NE>
+template <int NE, bool MR = false>
 DEV void chunk_stage(Grp& gp, Smem& S, const WaveTrials& w, const Chunk& c, int b, int r0, int c0,
                      const float (&rawA)[NE], const unsigned (&rawB)[NE]) {
   const FitDev& d = *gp.d;
@@ -609,7 +650,13 @@ DEV void chunk_stage(Grp& gp, Smem& S, const WaveTrials& w, const Chunk& c, int 
       float va, vb;
       if (lane_i(w.op, m) == OP_ULF) {
         va = funmap(rawB[m]);
-        vb = vmin(cb, ri - val);
+        if (MR) {
+          const float2 cm = S.cmm[b][x];
+          const float ex = S.ca1[b][x] == lane_i(w.i, m) ? cm.y : cm.x;
+          vb = vmin(ex, rawA[m] - val);
+        } else {
+          vb = vmin(cb, ri - val);
+        }
       } else {
         va = vmin(a1 == lane_i(w.j, m) ? m2 : m1, rawA[m] - val);
         vb = funmap(rawB[m]);
@@ -630,6 +677,7 @@ DEV void chunk_reduce(Grp& gp, Smem& S, const Chunk& c) {
   }
 }
 
+template <bool MR = false>
 DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
   const FitDev& d = *gp.d;
   const auto Rw = d.Rw;
@@ -662,8 +710,8 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
     unsigned rawB[NE];
     Chunk cur = chunk_at(S, dr, 0, 0), prev;
     prev.cn = 0;
-    WaveTrials wcur = wave_trials<NE>(gp, S, cur.cs, cur.cn, cur.a0, cur.n0, cur.a1);
-    chunk_loads<NE>(gp, wcur, cur, par, r0, c0, rawA, rawB);
+    WaveTrials wcur = wave_trials<NE, MR>(gp, S, cur.cs, cur.cn, cur.a0, cur.n0, cur.a1);
+    chunk_loads<NE, MR>(gp, wcur, cur, par, r0, c0, rawA, rawB);
     int kb0 = -KB, kcur = -1;
 #pragma unroll 1
     while (cur.k < dr) {
@@ -672,7 +720,7 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
         // chunk's barrier; the previous chunk's staging is done with them)
         if (cur.k >= kb0 + KB) {
           kb0 = cur.k;
-          stage_block(gp, S, kb0, dr - kb0 < KB ? dr - kb0 : KB, true, true, r0, c0, i);
+          stage_block<MR>(gp, S, kb0, dr - kb0 < KB ? dr - kb0 : KB, true, true, r0, c0, i);
         }
         // the product without k for this wave's rows and lane column, from
         // the staged U and V (each wave forms its own: no barrier)
@@ -696,11 +744,12 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
         kcur = cur.k;
       }
       __syncthreads();
-      chunk_stage<NE>(gp, S, wcur, cur, cur.k - kb0, r0, c0, rawA, rawB);
+      chunk_stage<NE, MR>(gp, S, wcur, cur, cur.k - kb0, r0, c0, rawA, rawB);
       chunk_reduce(gp, S, prev);
       const Chunk next = chunk_at(S, dr, cur.k, cur.cs + TCH);
-      const WaveTrials wnext = wave_trials<NE>(gp, S, next.cs, next.cn, next.a0, next.n0, next.a1);
-      chunk_loads<NE>(gp, wnext, next, par, r0, c0, rawA, rawB);
+      const WaveTrials wnext =
+          wave_trials<NE, MR>(gp, S, next.cs, next.cn, next.a0, next.n0, next.a1);
+      chunk_loads<NE, MR>(gp, wnext, next, par, r0, c0, rawA, rawB);
       __syncthreads();
 #pragma unroll 1
       for (int sl = gp.wave >> 1; sl < cur.cn; sl += NWAVE / 2) {
@@ -1213,6 +1262,70 @@ DEV void refill_candidates(Grp& gp, Smem& S, int i, int sel) {
   }
 }
 
+// Group the trials of S.trials[0 .. nt) for the two passes by key
+// op * RMAX + k (operation-major, then component, stable within a key):
+// S.byk and the key ranges S.kst.
+DEV void group_trials(Grp& gp, Smem& S) {
+  // Key counts first (LDS atomics), key starts by a scan; then, NTHR
+  // trials at a time in order, ranks within a wave by ballot and offsets
+  // from per-wave counts.
+  if (gp.tid < 2 * RMAX) S.kcnt[gp.tid] = 0;
+  __syncthreads();
+  for (int q = gp.tid; q < S.nt; q += NTHR) atomicAdd(&S.kcnt[S.trials[q].op * RMAX + S.trials[q].k], 1);
+  __syncthreads();
+  if (gp.wave == 0) {
+    // lane l: keys l and RMAX + l (F-ULF keys first)
+    const int t0 = S.kcnt[gp.lane], t1 = S.kcnt[RMAX + gp.lane];
+    int i0 = t0, i1 = t1;
+    for (int sft = 1; sft < 64; sft <<= 1) {
+      const int v0 = __shfl_up(i0, sft, 64), v1 = __shfl_up(i1, sft, 64);
+      if (gp.lane >= sft) { i0 += v0; i1 += v1; }
+    }
+    const int nulf = __shfl(i0, 63, 64);
+    S.kst[gp.lane] = S.kcnt[gp.lane] = i0 - t0;
+    S.kst[RMAX + gp.lane] = S.kcnt[RMAX + gp.lane] = nulf + i1 - t1;
+    if (gp.lane == 63) S.kst[2 * RMAX] = nulf + i1;
+  }
+  __syncthreads();
+  for (int base = 0; base < S.nt; base += NTHR) {
+    const int q = base + gp.tid;
+    const bool valid = q < S.nt;
+    const int key = valid ? S.trials[q].op * RMAX + S.trials[q].k : -1;
+    const unsigned long long below = (1ull << gp.lane) - 1ull;
+    int rank = 0, c0 = 0, c1 = 0;  // rank among the wave's trials of the key;
+                                   // lane l: the wave's trials of keys l, RMAX + l
+    unsigned long long rem = __ballot(valid);
+    while (rem) {
+      const int kl = __shfl(key, __ffsll((long long)rem) - 1, 64);
+      const unsigned long long m = __ballot(valid && key == kl);
+      if (valid && key == kl) rank = __popcll(m & below);
+      if (gp.lane == kl % RMAX) {
+        if (kl >= RMAX) c1 = __popcll(m); else c0 = __popcll(m);
+      }
+      rem &= ~m;
+    }
+    S.wk[gp.wave][gp.lane] = c0;
+    S.wk[gp.wave][RMAX + gp.lane] = c1;
+    __syncthreads();
+    if (gp.wave == 0) {
+      // every wave's share of each key starts after the earlier trials'
+      int run0 = S.kcnt[gp.lane], run1 = S.kcnt[RMAX + gp.lane];
+      for (int w = 0; w < NWAVE; ++w) {
+        const int a = S.wk[w][gp.lane], b = S.wk[w][RMAX + gp.lane];
+        S.wk[w][gp.lane] = run0;
+        S.wk[w][RMAX + gp.lane] = run1;
+        run0 += a;
+        run1 += b;
+      }
+      S.kcnt[gp.lane] = run0;
+      S.kcnt[RMAX + gp.lane] = run1;
+    }
+    __syncthreads();
+    if (valid) S.byk[S.wk[gp.wave][key] + rank] = q;
+    __syncthreads();
+  }
+}
+
 // Next batch of up to T trials from the cursor, in the method's order:
 // candidate by candidate, F-ULF then F-URF, skipping no-op trials.  Every
 // workgroup of the group computes the same list.
@@ -1393,77 +1506,18 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb, int sel) {
   }
   if (gp.tid == 0)
     S.exhausted = (S.cq_n - S.cq_head) == 0 && S.ord_pos >= (sel == SEL_SEQ ? d.n * d.r : d.n);
-  // Group the trials for the two passes by key op * RMAX + k (operation-
-  // major, then component, stable within a key): S.byk and the key ranges
-  // S.kst.  Key counts first (LDS atomics), key starts by a scan; then, NTHR
-  // trials at a time in order, ranks within a wave by ballot and offsets
-  // from per-wave counts.
-  if (gp.tid < 2 * RMAX) S.kcnt[gp.tid] = 0;
-  __syncthreads();
-  for (int q = gp.tid; q < S.nt; q += NTHR) atomicAdd(&S.kcnt[S.trials[q].op * RMAX + S.trials[q].k], 1);
-  __syncthreads();
-  if (gp.wave == 0) {
-    // lane l: keys l and RMAX + l (F-ULF keys first)
-    const int t0 = S.kcnt[gp.lane], t1 = S.kcnt[RMAX + gp.lane];
-    int i0 = t0, i1 = t1;
-    for (int sft = 1; sft < 64; sft <<= 1) {
-      const int v0 = __shfl_up(i0, sft, 64), v1 = __shfl_up(i1, sft, 64);
-      if (gp.lane >= sft) { i0 += v0; i1 += v1; }
-    }
-    const int nulf = __shfl(i0, 63, 64);
-    S.kst[gp.lane] = S.kcnt[gp.lane] = i0 - t0;
-    S.kst[RMAX + gp.lane] = S.kcnt[RMAX + gp.lane] = nulf + i1 - t1;
-    if (gp.lane == 63) S.kst[2 * RMAX] = nulf + i1;
-  }
-  __syncthreads();
-  for (int base = 0; base < S.nt; base += NTHR) {
-    const int q = base + gp.tid;
-    const bool valid = q < S.nt;
-    const int key = valid ? S.trials[q].op * RMAX + S.trials[q].k : -1;
-    const unsigned long long below = (1ull << gp.lane) - 1ull;
-    int rank = 0, c0 = 0, c1 = 0;  // rank among the wave's trials of the key;
-                                   // lane l: the wave's trials of keys l, RMAX + l
-    unsigned long long rem = __ballot(valid);
-    while (rem) {
-      const int kl = __shfl(key, __ffsll((long long)rem) - 1, 64);
-      const unsigned long long m = __ballot(valid && key == kl);
-      if (valid && key == kl) rank = __popcll(m & below);
-      if (gp.lane == kl % RMAX) {
-        if (kl >= RMAX) c1 = __popcll(m); else c0 = __popcll(m);
-      }
-      rem &= ~m;
-    }
-    S.wk[gp.wave][gp.lane] = c0;
-    S.wk[gp.wave][RMAX + gp.lane] = c1;
-    __syncthreads();
-    if (gp.wave == 0) {
-      // every wave's share of each key starts after the earlier trials'
-      int run0 = S.kcnt[gp.lane], run1 = S.kcnt[RMAX + gp.lane];
-      for (int w = 0; w < NWAVE; ++w) {
-        const int a = S.wk[w][gp.lane], b = S.wk[w][RMAX + gp.lane];
-        S.wk[w][gp.lane] = run0;
-        S.wk[w][RMAX + gp.lane] = run1;
-        run0 += a;
-        run1 += b;
-      }
-      S.kcnt[gp.lane] = run0;
-      S.kcnt[RMAX + gp.lane] = run1;
-    }
-    __syncthreads();
-    if (valid) S.byk[S.wk[gp.wave][key] + rank] = q;
-    __syncthreads();
-  }
+  group_trials(gp, S);
 }
 
 // Evaluate the batch in S.trials: residual pass, error pass, per-trial
 // reduction, and the decision (the first trial with e' < thr, or with `best`
 // the smallest such e') made by the last workgroup to arrive.
-template <typename Lap>
+template <bool MR = false, typename Lap>
 DEV bool run_batch(Grp& gp, Smem& S, int i, int par, double thr, bool best, Lap& lap) {
-  batch_residual_pass(gp, S, i, par);
+  batch_residual_pass<MR>(gp, S, i, par);
   if (!group_sync(gp, S)) return false;
   lap(2);
-  batch_eval_pass(gp, S, i, par);
+  batch_eval_pass<MR>(gp, S, i, par);
   clear_prev(gp, S, par ^ 1);
   if (!group_sync(gp, S)) return false;
   lap(6);
@@ -1559,6 +1613,399 @@ DEV void book(Grp& gp, int it, int i, long long trials, long long noops, long lo
   ctl->nlog += 1;
 }
 
+// ------------------------------------------------------------ ByMatrix
+// Sec. 3.2.3 and its supplementary pseudocode.  One iteration keys every
+// observed cell of the working matrix by
+//   err(i, j) = (td_row(i) + td_col(j)) - td(i, j)
+// (FP64; td_row summed over j ascending, td_col over i ascending, one thread
+// per line, the same order as a plain loop), and tries the cells by err
+// descending, ties in row-major order, each with k = f(i, j) of the
+// iteration's state and one operation drawn from a counter-based SplitMix64
+// stream, until the first strict decrease.  The candidates come in rounds of
+// up to T_max: a radix select over the group (8-bit digits of the order-mapped
+// key, then of the cell position among equal keys) finds the round's last
+// cell, the cells up to it are gathered and ranked, and the next round starts
+// after it.
+
+// SplitMix64 output mixing (Steele, Lea, Flood 2014).
+DEV unsigned long long sm_mix(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// Operation of the c-th cell tried in the fit (c from 0): the c-th output of
+// SplitMix64 seeded with seed_ops; F-URF when its top bit is set (a uniform
+// draw of at least 1/2), else F-ULF.
+DEV int matrix_op(unsigned long long seed_ops, long long c) {
+  return (int)(sm_mix(seed_ops + (unsigned long long)(c + 1) * 0x9E3779B97F4A7C15ull) >> 63);
+}
+// Order-preserving image of a double (0 is never an image of a key >= 0,
+// and marks an unobserved cell).
+DEV unsigned long long fmap64(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+// Keys of every cell for the iteration (three group barriers).
+DEV bool matrix_keys(Grp& gp, Smem& S) {
+  const FitDev& d = *gp.d;
+  const int m = d.m, n = d.n, r = d.r;
+  const size_t cells = (size_t)m * n, stride = (size_t)gp.G * NTHR;
+  const size_t first = (size_t)gp.g * NTHR + gp.tid;
+  for (size_t q = first; q < cells; q += stride) {
+    const int i = (int)(q / n), j = (int)(q % n);
+    const float rv = d.Rw[(size_t)i * d.ldn + j];
+    float best = ld_atomic(&d.Uc[i]) + ld_atomic(&d.V[j]);
+    int arg = 0;
+    for (int l = 1; l < r; ++l) {
+      const float x = ld_atomic(&d.Uc[(size_t)l * d.ldm + i]) + ld_atomic(&d.V[(size_t)l * d.ldn + j]);
+      if (x > best) { best = x; arg = l; }
+    }
+    st_coh(&d.mfk[q], arg);
+    st_coh(&d.mtd[q], rv == FINF ? -1.0 : (double)fabsf(rv - best));
+  }
+  if (!group_sync(gp, S)) return false;
+  for (size_t x = first; x < (size_t)(m + n); x += stride) {
+    double sum = 0.0;
+    if (x < (size_t)m) {
+      for (int j = 0; j < n; ++j) {
+        const double t = ld_atomic(&d.mtd[x * n + j]);
+        if (t >= 0.0) sum += t;
+      }
+      st_coh(&d.mtdr[x], sum);
+    } else {
+      const int j = (int)(x - m);
+      for (int i = 0; i < m; ++i) {
+        const double t = ld_atomic(&d.mtd[(size_t)i * n + j]);
+        if (t >= 0.0) sum += t;
+      }
+      st_coh(&d.mtdc[j], sum);
+    }
+  }
+  if (!group_sync(gp, S)) return false;
+  for (size_t q = first; q < cells; q += stride) {
+    const double t = ld_atomic(&d.mtd[q]);
+    unsigned long long u = 0;
+    if (t >= 0.0) u = fmap64((ld_atomic(&d.mtdr[q / n]) + ld_atomic(&d.mtdc[q % n])) - t);
+    st_coh(&d.mkey[q], u);
+  }
+  return group_sync(gp, S);
+}
+
+// A cell after the cursor (have, cu, cq) in the order (key desc, position asc).
+DEV bool after_cursor(unsigned long long u, long long q, bool have, unsigned long long cu,
+                      long long cq) {
+  return u != 0 && (!have || u < cu || (u == cu && q > cq));
+}
+
+// One radix-select pass: every workgroup counts the digits of its cells that
+// pass `in` into LDS and adds the counts into histogram h; after the barrier
+// one thread walks h (from the top digit down, or up with `up`) to the digit
+// holding the want-th cell (S.m_want), and want becomes the rank within that
+// digit.  The digit goes to `digit` (-1 if h holds fewer cells); false when
+// the fit was aborted.
+template <typename In>
+DEV bool radix_pass(Grp& gp, Smem& S, GA int* h, In in, bool up, int& want, int& digit) {
+  const FitDev& d = *gp.d;
+  const size_t cells = (size_t)d.m * d.n, stride = (size_t)gp.G * NTHR;
+  int* lh = S.u.s.idx;
+  if (gp.tid < 256) lh[gp.tid] = 0;
+  __syncthreads();
+  for (size_t q = (size_t)gp.g * NTHR + gp.tid; q < cells; q += stride) {
+    int dig;
+    if (in(q, dig)) atomicAdd(&lh[dig], 1);
+  }
+  __syncthreads();
+  if (gp.tid < 256 && lh[gp.tid]) atomic_add_g(&h[gp.tid], lh[gp.tid]);
+  if (!group_sync(gp, S)) return false;
+  if (gp.tid == 0) {
+    int w = S.m_want, found = -1;
+    for (int x = 0; x < 256; ++x) {
+      const int b = up ? x : 255 - x;
+      const int c = ld_atomic(&h[b]);
+      if (w <= c) { found = b; break; }
+      w -= c;
+    }
+    S.m_want = w;
+    S.m_count = found;
+  }
+  __syncthreads();
+  want = S.m_want;
+  digit = S.m_count;
+  __syncthreads();
+  return true;
+}
+
+// The next round of candidates after the cursor into mlist_q / mlist_k, in
+// order; S.m_count gets their number (0: none left).  The cursor moves to
+// the round's last cell.
+DEV bool matrix_select(Grp& gp, Smem& S, bool have) {
+  const FitDev& d = *gp.d;
+  GA FitCtl* ctl = gp.ctl;
+  const unsigned long long cu = have ? ld_atomic(&ctl->mlast_u) : 0ull;
+  const long long cq = have ? ld_atomic(&ctl->mlast_q) : -1ll;
+  const auto mkey = d.mkey;
+  {
+    int lo, hi;
+    slice(MATRIX_HIST * 256, gp.g, gp.G, lo, hi);
+    for (int x = lo + gp.tid; x < hi; x += NTHR) st_coh(&d.mhist[x], 0);
+    if (gp.g == 0 && gp.tid == 0) st_coh(&d.mcnt[0], 0);
+  }
+  if (!group_sync(gp, S)) return false;
+  // the eligible count first (pass 0 counts every digit), then the key of
+  // the round's last cell digit by digit
+  unsigned long long pref = 0;
+  int want = 0, digit = 0;
+  if (gp.tid == 0) S.m_want = 1;
+  __syncthreads();
+  for (int p = 0; p < 8; ++p) {
+    const int sh = 56 - 8 * p;
+    const unsigned long long pp = pref;
+    auto in = [&](size_t q, int& dig) {
+      const unsigned long long u = ld_atomic(&mkey[q]);
+      if (!after_cursor(u, (long long)q, have, cu, cq)) return false;
+      if (p > 0 && (u >> (sh + 8)) != (pp >> (sh + 8))) return false;
+      dig = (int)((u >> sh) & 255);
+      return true;
+    };
+    if (p == 0) {
+      // total of the first histogram: the round takes min(T_max, eligible)
+      if (!radix_pass(gp, S, d.mhist, in, false, want, digit)) return false;
+      if (gp.tid == 0) {
+        long long tot = 0;
+        for (int x = 0; x < 256; ++x) tot += ld_atomic(&d.mhist[x]);
+        S.m_pref = (unsigned long long)tot;
+      }
+      __syncthreads();
+      const long long tot = (long long)S.m_pref;
+      if (tot == 0) {
+        if (gp.tid == 0) S.m_count = 0;
+        __syncthreads();
+        return true;
+      }
+      // redo the walk of histogram 0 with the round's size
+      if (gp.tid == 0) {
+        int w = tot < d.tmax ? (int)tot : d.tmax, bb = 255;
+        for (; bb >= 0; --bb) {
+          const int c = ld_atomic(&d.mhist[bb]);
+          if (w <= c) break;
+          w -= c;
+        }
+        S.m_want = w;
+        S.m_count = bb;
+        S.m_used = tot < d.tmax ? (int)tot : d.tmax;  // the round's size
+      }
+      __syncthreads();
+      want = S.m_want;
+      pref |= (unsigned long long)S.m_count << sh;
+    } else {
+      if (!radix_pass(gp, S, d.mhist + p * 256, in, false, want, digit)) return false;
+      pref |= (unsigned long long)digit << sh;
+    }
+  }
+  const int round = S.m_used;
+  // among the cells with that key, the want-th smallest position
+  unsigned qpref = 0;
+  for (int p = 0; p < 4; ++p) {
+    const int sh = 24 - 8 * p;
+    const unsigned qp = qpref;
+    auto in = [&](size_t q, int& dig) {
+      const unsigned long long u = ld_atomic(&mkey[q]);
+      if (u != pref || !after_cursor(u, (long long)q, have, cu, cq)) return false;
+      if (p > 0 && ((unsigned)q >> (sh + 8)) != (qp >> (sh + 8))) return false;
+      dig = (int)(((unsigned)q >> sh) & 255u);
+      return true;
+    };
+    if (!radix_pass(gp, S, d.mhist + (8 + p) * 256, in, true, want, digit)) return false;
+    qpref |= (unsigned)digit << sh;
+  }
+  // gather the round's cells (any order), then rank them
+  {
+    const size_t cells = (size_t)d.m * d.n, stride = (size_t)gp.G * NTHR;
+    for (size_t q = (size_t)gp.g * NTHR + gp.tid; q < cells; q += stride) {
+      const unsigned long long u = ld_atomic(&mkey[q]);
+      if (!after_cursor(u, (long long)q, have, cu, cq)) continue;
+      if (u > pref || (u == pref && (unsigned)q <= qpref)) {
+        const int slot = __hip_atomic_fetch_add(&d.mcnt[0], 1, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        if (slot < round) {
+          st_coh(&d.mgat_u[slot], u);
+          st_coh(&d.mgat_q[slot], (int)q);
+        }
+      }
+    }
+  }
+  if (!group_sync(gp, S)) return false;
+  if (ld_atomic(&d.mcnt[0]) != round) {
+    // the gathered cells must be exactly the selected ones
+    if (gp.tid == 0) {
+      int zero = 0;
+      __hip_atomic_compare_exchange_strong(&ctl->status, &zero, ST_INTERNAL, __ATOMIC_RELAXED,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return false;
+  }
+  unsigned long long* ku = reinterpret_cast<unsigned long long*>(S.u.s.key);
+  int* kq = S.u.s.idx;
+  for (int e = gp.tid; e < round; e += NTHR) {
+    ku[e] = ld_atomic(&d.mgat_u[e]);
+    kq[e] = ld_atomic(&d.mgat_q[e]);
+  }
+  __syncthreads();
+  int lo, hi;
+  slice(round, gp.g, gp.G, lo, hi);
+  for (int e = lo + gp.tid; e < hi; e += NTHR) {
+    const unsigned long long u = ku[e];
+    const int q = kq[e];
+    int rank = 0;
+    for (int x = 0; x < round; ++x) rank += (ku[x] > u || (ku[x] == u && kq[x] < q)) ? 1 : 0;
+    st_coh(&d.mlist_q[rank], q);
+    st_coh(&d.mlist_k[rank], ld_atomic(&d.mfk[q]));
+    if (rank == round - 1) {
+      st_coh(&ctl->mlast_u, u);
+      st_coh(&ctl->mlast_q, (long long)q);
+    }
+  }
+  if (gp.tid == 0) S.m_count = round;
+  return group_sync(gp, S);
+}
+
+// Next batch of up to T trials from list position pos: one operation per
+// candidate (drawn by its position in the fit's draw sequence, draw0 being
+// that of position pos), no-op skips, trials in order with their rows in
+// S.trow.  Returns the candidates consumed.
+DEV int build_batch_matrix(Grp& gp, Smem& S, int pos, int L, int T, long long draw0) {
+  const FitDev& d = *gp.d;
+  if (T > d.tmax) T = d.tmax;
+  if (gp.tid == 0) { S.nt = 0; S.batch_noops = 0; S.m_used = 0; }
+  __syncthreads();
+  while (true) {
+    const int used = S.m_used, nt0 = S.nt, nn0 = S.batch_noops;
+    const int left = L - pos - used;
+    if (nt0 >= T || left <= 0) break;
+    const int x = gp.tid;
+    const bool valid = x < left;
+    bool noop = false;
+    Trial tr;
+    tr.j = 0; tr.k = 0; tr.op = OP_ULF; tr.val = 0.0f;
+    int row = 0;
+    if (valid) {
+      const int q = ld_atomic(&d.mlist_q[pos + used + x]);
+      const int k = ld_atomic(&d.mlist_k[pos + used + x]);
+      const int i = q / d.n, j = q - i * d.n;
+      const int op = matrix_op(d.seed_ops, draw0 + used + x);
+      const float Rij = d.Rw[(size_t)i * d.ldn + j];
+      const float Uik = ld_atomic(&d.Uc[(size_t)k * d.ldm + i]);
+      const float Vkj = ld_atomic(&d.V[(size_t)k * d.ldn + j]);
+      const float val = op == OP_ULF ? Rij - Vkj : Rij - Uik;
+      noop = d.noop_rule && S.closed_s[k] && (op == OP_ULF ? val == Uik : val == Vkj);
+      tr.j = j; tr.k = k; tr.op = op; tr.val = val;
+      row = i;
+    }
+    const bool kept = valid && !noop;
+    const unsigned long long mk = __ballot(kept);
+    const unsigned long long mn = __ballot(valid && noop);
+    const unsigned long long below = (1ull << gp.lane) - 1ull;
+    if (gp.lane == 0) { S.wcount[gp.wave] = __popcll(mk); S.wnoop[gp.wave] = __popcll(mn); }
+    __syncthreads();
+    int kept_before = __popcll(mk & below), noop_before = __popcll(mn & below);
+    for (int w = 0; w < gp.wave; ++w) { kept_before += S.wcount[w]; noop_before += S.wnoop[w]; }
+    const int room = T - nt0;
+    const bool consumed = valid && kept_before < room;
+    if (consumed && kept) {
+      S.trials[nt0 + kept_before] = tr;
+      S.trow[nt0 + kept_before] = row;
+      S.noops_before[nt0 + kept_before] = nn0 + noop_before;
+    }
+    const unsigned long long mc = __ballot(consumed);
+    const unsigned long long mcn = __ballot(consumed && noop);
+    if (gp.lane == 0) {
+      S.wlast[gp.wave] = mc ? gp.wave * 64 + 63 - __clzll(mc) : -1;
+      S.wcn[gp.wave] = __popcll(mcn);
+    }
+    __syncthreads();
+    if (gp.tid == 0) {
+      int last = -1, kt = 0, nn = 0;
+      for (int w = 0; w < NWAVE; ++w) {
+        last = S.wlast[w] > last ? S.wlast[w] : last;
+        kt += S.wcount[w];
+        nn += S.wcn[w];
+      }
+      S.nt = nt0 + (kt < room ? kt : room);
+      S.batch_noops = nn0 + nn;
+      S.m_used = used + last + 1;
+    }
+    __syncthreads();
+  }
+  if (gp.tid == 0) S.exhausted = pos + S.m_used >= L;
+  group_trials(gp, S);
+  return S.m_used;
+}
+
+// One ByMatrix iteration: keys, then rounds of candidates in batches until
+// the first accepted update or none is left (then *acc_iter stays false).
+template <typename Lap>
+DEV bool matrix_iteration(Grp& gp, Smem& S, int it, int& cb, int& par, double& e_cur,
+                          bool& acc_iter, int& seg_t, Lap& lap) {
+  const FitDev& d = *gp.d;
+  GA FitCtl* ctl = gp.ctl;
+  acc_iter = false;
+  if (gp.tid < d.r) S.closed_s[gp.tid] = ld_atomic(&d.closed[gp.tid]);
+  __syncthreads();
+  if (!matrix_keys(gp, S)) return false;
+  lap(0);
+  long long draws = ld_atomic(&ctl->mdraws);
+  long long trials = 0, noops = 0, spec = 0;
+  int acc_row = -1, acc_j = -1, acc_k = -1, acc_op = -1;
+  bool have = false;
+  while (!acc_iter) {
+    if (!matrix_select(gp, S, have)) return false;
+    have = true;
+    const int L = S.m_count;
+    lap(1);
+    if (L == 0) break;
+    int pos = 0, T = seg_t;
+    while (pos < L) {
+      const int used = build_batch_matrix(gp, S, pos, L, T, draws + pos);
+      lap(1);
+      const int nt = S.nt;
+      if (nt == 0) { noops += S.batch_noops; pos += used; continue; }
+      if (!run_batch<true>(gp, S, 0, par, e_cur, false, lap)) return false;
+      const int dec = ld_atomic(&ctl->decision);
+      spec += nt;
+      if (gp.tid == 0) S.prev_nt = nt;
+      if (dec >= 0) {
+        trials += dec + 1;
+        noops += S.noops_before[dec];
+        const Trial tr = S.trials[dec];
+        acc_row = S.trow[dec];
+        acc_j = tr.j; acc_k = tr.k; acc_op = tr.op;
+        draws += pos + dec + S.noops_before[dec] + 1;
+        e_cur = ld_atomic(&ctl->e_new);
+        if (!refresh(gp, S, tr.k, true, tr, par, dec, acc_row, true, cb ^ 1)) return false;
+        cb ^= 1;
+        lap(4);
+        par ^= 1;
+        acc_iter = true;
+        break;
+      }
+      trials += nt;
+      noops += S.batch_noops;
+      par ^= 1;
+      pos += used;
+      T = T * 2 > d.tmax ? d.tmax : T * 2;
+    }
+    if (!acc_iter) draws += L;
+    int t = 16;
+    while (t < trials) t *= 2;
+    seg_t = t > d.tmax ? d.tmax : t;
+  }
+  if (gp.g == 0 && gp.tid == 0) st_coh(&ctl->mdraws, draws);
+  book(gp, it, acc_row, trials, noops, spec, acc_j, acc_k, acc_op, e_cur);
+  return true;
+}
+
+
 // ByElement row visit (Sec. 3.2.2): the row's observed entries in working
 // column order, k = f(i, j), exact entries skipped, F-ULF then F-URF.  An
 // accepted update ends a segment (its record is written) and the visit goes
@@ -1617,16 +2064,17 @@ DEV bool elem_row_visit(Grp& gp, Smem& S, int i, int it, int& cb, int& par, doub
 
 // Run the fit from its saved state for at most max_rows row visits (0: no
 // limit).  All workgroups of the group execute the same control flow.
-// FastSTMF's TD_A (ANY_SEL false) is compiled on its own, without the code of
-// the other selections.  A ByRow row visit (Algorithm 3; the selections of
+// MODE 0 is FastSTMF's TD_A alone, compiled without the code of the other
+// selections; MODE 1 runs any ByRow selection or ByElement; MODE 2 ByMatrix
+// (batches of trials of different rows).  A ByRow row visit (Algorithm 3; the selections of
 // Sec. 3.2.1) runs batches of trials until the first accepted update (SEQ:
 // every trial, then the best), its refresh and the visit's record; it stays
 // written out here rather than in a function of its own, which measured
 // 1.3% slower on the TD_A fit (register allocation around the passes).
-template <bool ANY_SEL>
+template <int MODE>
 DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
   const FitDev& d = *gp.d;
-  const int sel = ANY_SEL ? d.sel : (int)SEL_TD_A;
+  const int sel = MODE == 0 ? (int)SEL_TD_A : MODE == 2 ? (int)SEL_MATRIX : d.sel;
   GA FitCtl* ctl = gp.ctl;
   if (gp.tid == 0) { S.prev_nt = 0; S.status = 0; }
   __syncthreads();
@@ -1653,8 +2101,31 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
     ticks[which] += (long long)(now - tmark);
     tmark = now;
   };
-  int seg_t = d.t0;  // ByElement: first batch of the next segment
-  while (phase == 1) {
+  int seg_t = d.t0;  // ByElement, ByMatrix: first batch of the next segment or round
+  while (MODE == 2 && phase == 1) {
+    // one ByMatrix iteration per step (counted as a row visit)
+    if (max_rows > 0 && rows_done >= max_rows) break;
+    bool acc_iter = false;
+    if (!matrix_iteration(gp, S, it, cb, par, e_cur, acc_iter, seg_t, lap)) return;
+    ++rows_done;
+    if (gp.g == 0 && gp.tid == 0) {
+      ctl->row_visits += 1;
+      st_coh(&d.traj[it], e_cur);
+    }
+    const bool small = d.eps > 0.0 && (ld_atomic(&d.traj[it - 1]) - e_cur) < d.eps;
+    if (!acc_iter || small || it == d.iters) {
+      if (gp.g == 0 && gp.tid == 0)
+        for (int q = it + 1; q <= d.iters; ++q) d.traj[q] = e_cur;
+      phase = 2;
+    }
+    if (gp.g == 0 && gp.tid == 0) {
+      ctl->iters_done = it;
+      ctl->it = it + 1; ctl->row = 0; ctl->acc_in_pass = 0; ctl->phase = phase; ctl->cbuf = cb;
+    }
+    ++it;
+    lap(5);
+  }
+  while (MODE != 2 && phase == 1) {
     if (max_rows > 0 && rows_done >= max_rows) break;
     const int i = row;
     if (sel == SEL_ELEM) {
@@ -1773,7 +2244,7 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
 
 // One fit per group of gsize workgroups.  With nfits > 1 every workgroup
 // takes fits from a queue, one workgroup per fit.
-template <bool ANY_SEL>
+template <int MODE>
 DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int gsize, int max_rows,
                          unsigned* __restrict__ queue) {
   extern __shared__ __align__(16) char smem_raw[];
@@ -1787,7 +2258,7 @@ DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int gsize, 
   if (nfits == 1 && gsize == (int)gridDim.x) {
     gp.d = &fits[0];
     gp.ctl = fits[0].ctl;
-    if (ld_atomic(&gp.ctl->phase) != 2) fit_run<ANY_SEL>(gp, S, max_rows);
+    if (ld_atomic(&gp.ctl->phase) != 2) fit_run<MODE>(gp, S, max_rows);
     return;
   }
   __shared__ int fid_s;
@@ -1801,7 +2272,7 @@ DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int gsize, 
     gp.ctl = fits[fid].ctl;
     gp.g = 0;
     gp.G = 1;
-    if (ld_atomic(&gp.ctl->phase) != 2) fit_run<ANY_SEL>(gp, S, max_rows);
+    if (ld_atomic(&gp.ctl->phase) != 2) fit_run<MODE>(gp, S, max_rows);
   }
 }
 
@@ -1809,14 +2280,21 @@ DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int gsize, 
 __global__ void __launch_bounds__(NTHR) fit_kernel(const FitDev* __restrict__ fits, int nfits,
                                                    int gsize, int max_rows,
                                                    unsigned* __restrict__ queue) {
-  fit_kernel_body<false>(fits, nfits, gsize, max_rows, queue);
+  fit_kernel_body<0>(fits, nfits, gsize, max_rows, queue);
 }
 
 // Fits with any ByRow selection (all fits of one launch share it).
 __global__ void __launch_bounds__(NTHR) fit_kernel_sel(const FitDev* __restrict__ fits, int nfits,
                                                        int gsize, int max_rows,
                                                        unsigned* __restrict__ queue) {
-  fit_kernel_body<true>(fits, nfits, gsize, max_rows, queue);
+  fit_kernel_body<1>(fits, nfits, gsize, max_rows, queue);
+}
+
+// ByMatrix fits.
+__global__ void __launch_bounds__(NTHR) fit_kernel_matrix(const FitDev* __restrict__ fits,
+                                                          int nfits, int gsize, int max_rows,
+                                                          unsigned* __restrict__ queue) {
+  fit_kernel_body<2>(fits, nfits, gsize, max_rows, queue);
 }
 
 size_t fit_smem_bytes() { return sizeof(Smem); }

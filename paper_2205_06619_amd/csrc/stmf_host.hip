@@ -17,6 +17,8 @@ namespace stmf {
 // kernels (stmf_fit.hip, stmf_prims.hip, stmf_setup.hip)
 __global__ void fit_kernel(const FitDev* fits, int nfits, int gsize, int max_rows, unsigned* queue);
 __global__ void fit_kernel_sel(const FitDev* fits, int nfits, int gsize, int max_rows, unsigned* queue);
+__global__ void fit_kernel_matrix(const FitDev* fits, int nfits, int gsize, int max_rows,
+                                  unsigned* queue);
 size_t fit_smem_bytes();
 size_t masked_error_ws(int m, int n);
 hipError_t launch_maxplus(const float*, const float*, int, int, int, float*, int32_t*, hipStream_t);
@@ -98,12 +100,16 @@ static int device_props(DevProps& out) {
                                (int)smem));
     HIPCHK(hipFuncSetAttribute((const void*)fit_kernel_sel,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-    // the two fit kernels share the LDS layout; the group size must suit both
-    int per = 0, per_sel = 0;
+    HIPCHK(hipFuncSetAttribute((const void*)fit_kernel_matrix,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    // the fit kernels share the LDS layout; the group size must suit all
+    int per = 0, per_sel = 0, per_mat = 0;
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)fit_kernel, NTHR, smem));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_sel, (const void*)fit_kernel_sel, NTHR,
                                                         smem));
-    p.coresident = std::min(per, per_sel) * p.cus;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_mat, (const void*)fit_kernel_matrix,
+                                                        NTHR, smem));
+    p.coresident = std::min(std::min(per, per_sel), per_mat) * p.cus;
     p.ok = true;
   }
   out = p;
@@ -131,7 +137,7 @@ static int check_options(const stmf_options& o) {
   if (o.group_size < 0 || o.log_cap < 0 || o.max_row_visits < 0) return STMF_EINVAL;
   if (!(o.eps >= 0.0)) return STMF_EINVAL;
   if (o.selection < 0 || o.selection > 3 || o.perm_mode < 0 || o.perm_mode > 3) return STMF_EINVAL;
-  if (o.strategy < 0 || o.strategy > 1) return STMF_EINVAL;
+  if (o.strategy < 0 || o.strategy > 2) return STMF_EINVAL;
   return STMF_OK;
 }
 
@@ -142,7 +148,8 @@ struct Layout {
   int transposed;
   size_t Rw, RwT, Uc, V, td, tdpart, crow, ccol, colst, rowst, colpart, rowpart, order, rowt,
       rord, tdrow, tvec, epart, eprime, closed, traj, ctl, dev, perm, cperm, stage, check, rowc,
-      colc;
+      colc, mtd, mfk, mkey, mtdr, mtdc, mhist, mcnt, mgat_u, mgat_q, mlist_q, mlist_k;
+  bool matrix;
   size_t total;
 };
 
@@ -156,8 +163,9 @@ static int auto_batch_max(int tiles, int G) {
   return t;
 }
 
+// `matrix`: room for the ByMatrix buffers (per cell of the working matrix).
 static void make_layout(int m, int n, int r, int iters, int G, int acol_p, int batch_max,
-                        Layout& L) {
+                        Layout& L, bool matrix = false) {
   L.m = m; L.n = n; L.r = r; L.iters = iters; L.G = G; L.acol_p = acol_p;
   L.transposed = m > n;
   L.mw = L.transposed ? n : m;
@@ -199,6 +207,19 @@ static void make_layout(int m, int n, int r, int iters, int G, int acol_p, int b
   L.check = take(sizeof(CheckOut));
   L.rowc = take((size_t)m * 4);
   L.colc = take((size_t)n * 4);
+  L.matrix = matrix;
+  const size_t cells = matrix ? (size_t)L.mw * L.nw : 0, mt = matrix ? (size_t)L.tmax : 0;
+  L.mtd = take(cells * 8);
+  L.mfk = take(cells * 4);
+  L.mkey = take(cells * 8);
+  L.mtdr = take(matrix ? (size_t)L.mw * 8 : 0);
+  L.mtdc = take(matrix ? (size_t)L.nw * 8 : 0);
+  L.mhist = take(matrix ? (size_t)MATRIX_HIST * 256 * 4 : 0);
+  L.mcnt = take(matrix ? 16 : 0);
+  L.mgat_u = take(mt * 8);
+  L.mgat_q = take(mt * 4);
+  L.mlist_q = take(mt * 4);
+  L.mlist_k = take(mt * 4);
   L.total = o;
 }
 
@@ -217,7 +238,7 @@ static int auto_batch_first(const Layout& L) {
 
 // What the fit kernel runs: a ByRow selection, or ByElement.
 static int kernel_sel(const stmf_options& o) {
-  return o.strategy == 1 ? (int)SEL_ELEM : o.selection;
+  return o.strategy == 2 ? (int)SEL_MATRIX : o.strategy == 1 ? (int)SEL_ELEM : o.selection;
 }
 
 static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int observed) {
@@ -258,6 +279,19 @@ static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int o
   d.ctl = (FitCtl*)(base + L.ctl);
   d.ldmax = L.ldmax;
   d.gsize = L.G;
+  if (L.matrix) {
+    d.mtd = (double*)(base + L.mtd);
+    d.mfk = (int*)(base + L.mfk);
+    d.mkey = (unsigned long long*)(base + L.mkey);
+    d.mtdr = (double*)(base + L.mtdr);
+    d.mtdc = (double*)(base + L.mtdc);
+    d.mhist = (int*)(base + L.mhist);
+    d.mcnt = (int*)(base + L.mcnt);
+    d.mgat_u = (unsigned long long*)(base + L.mgat_u);
+    d.mgat_q = (int*)(base + L.mgat_q);
+    d.mlist_q = (int*)(base + L.mlist_q);
+    d.mlist_k = (int*)(base + L.mlist_k);
+  }
   return d;
 }
 
@@ -416,13 +450,17 @@ static int launch_fit_kernel(const FitDev* dev_fits, int nfits, int G, int grid,
   const size_t smem = fit_smem_bytes();
   if (G > 1) {
     void* args[] = {(void*)&dev_fits, (void*)&nfits, (void*)&G, (void*)&max_rows, (void*)&queue};
-    HIPCHK(hipLaunchCooperativeKernel(sel == SEL_TD_A ? (const void*)fit_kernel
-                                                      : (const void*)fit_kernel_sel,
-                                      dim3(grid), dim3(NTHR), args, (unsigned)smem, s));
+    const void* k = sel == SEL_TD_A     ? (const void*)fit_kernel
+                    : sel == SEL_MATRIX ? (const void*)fit_kernel_matrix
+                                        : (const void*)fit_kernel_sel;
+    HIPCHK(hipLaunchCooperativeKernel(k, dim3(grid), dim3(NTHR), args, (unsigned)smem, s));
   } else {
     if (sel == SEL_TD_A)
       hipLaunchKernelGGL(fit_kernel, dim3(grid), dim3(NTHR), smem, s, dev_fits, nfits, G, max_rows,
                          queue);
+    else if (sel == SEL_MATRIX)
+      hipLaunchKernelGGL(fit_kernel_matrix, dim3(grid), dim3(NTHR), smem, s, dev_fits, nfits, G,
+                         max_rows, queue);
     else
       hipLaunchKernelGGL(fit_kernel_sel, dim3(grid), dim3(NTHR), smem, s, dev_fits, nfits, G,
                          max_rows, queue);
@@ -547,9 +585,9 @@ size_t stmf_fit_workspace(int m, int n, int rank, int iters, const stmf_options*
   DevProps P;
   if (device_props(P)) return 0;
   Layout L;
-  make_layout(m, n, rank, iters, 1, o.acol_p, o.batch_max, L);
+  make_layout(m, n, rank, iters, 1, o.acol_p, o.batch_max, L, o.strategy == 2);
   const int G = auto_group(L, P, o.group_size);
-  make_layout(m, n, rank, iters, G, o.acol_p, o.batch_max, L);
+  make_layout(m, n, rank, iters, G, o.acol_p, o.batch_max, L, o.strategy == 2);
   return L.total;
 }
 
@@ -589,9 +627,9 @@ int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters
   st = device_props(P);
   if (st) return st;
   Layout L;
-  make_layout(m, n, rank, iters, 1, o.acol_p, o.batch_max, L);
+  make_layout(m, n, rank, iters, 1, o.acol_p, o.batch_max, L, o.strategy == 2);
   const int G = auto_group(L, P, o.group_size);
-  make_layout(m, n, rank, iters, G, o.acol_p, o.batch_max, L);
+  make_layout(m, n, rank, iters, G, o.acol_p, o.batch_max, L, o.strategy == 2);
   if (!ws || ((uintptr_t)ws & 255) || ws_bytes < L.total) return STMF_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   char* base = (char*)ws;
@@ -605,6 +643,7 @@ int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters
   st = prepare_fit(R, M, L, base, o, perm, U0, cols, s);
   if (st) return st;
   FitDev d = make_dev(L, base, o, observed);
+  d.seed_ops = seed ^ MATRIX_OP_STREAM;
   HIPCHK(hipMemcpyAsync(base + L.dev, &d, sizeof(d), hipMemcpyHostToDevice, s));
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   HIPCHK(hipEventCreate(&ev0));
@@ -687,6 +726,7 @@ int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts, const stmf_op
   if (st) return st;
   if (!probs || nprob < 1 || restarts < 1) return STMF_EINVAL;
   if (o.decision_log || o.perm || o.init_mode == 2 || o.max_row_visits) return STMF_EINVAL;
+  if (o.strategy == 2) return STMF_EINVAL;  // ByMatrix runs through stmf_fit only
   for (int p = 0; p < nprob; ++p)
     if (!probs[p].R || !probs[p].M || !probs[p].U_out || !probs[p].V_out || probs[p].m < 1 ||
         probs[p].n < 1 || probs[p].rank < 1 || probs[p].rank > RMAX || probs[p].iters < 0)
@@ -838,6 +878,7 @@ int stmf_engine_create(void* ws, size_t ws_bytes, int max_slots, const stmf_opti
   if (st) return st;
   if (o.decision_log || o.perm || o.init_mode == 2 || o.max_row_visits || o.group_size > 1)
     return STMF_EINVAL;
+  if (o.strategy == 2) return STMF_EINVAL;  // ByMatrix runs through stmf_fit only
   if (!ws || ((uintptr_t)ws & 255)) return STMF_ENOMEM;
   const size_t table = al256((size_t)max_slots * sizeof(FitDev));
   if (ws_bytes < table + 256 + 256) return STMF_ENOMEM;

@@ -36,8 +36,14 @@ struct Top2 {
 enum Op : int { OP_ULF = 0, OP_URF = 1, OP_NULL = 2 };
 
 // ByRow selections of (j, k) within a row visit (Sec. 3.2.1), and the
-// ByElement strategy (Sec. 3.2.2), which the fit kernel runs as a fifth.
-enum Sel : int { SEL_TD_A = 0, SEL_TD = 1, SEL_TD_B = 2, SEL_SEQ = 3, SEL_ELEM = 4 };
+// ByElement (Sec. 3.2.2) and ByMatrix (Sec. 3.2.3) strategies, which the fit
+// kernel runs as two more.
+enum Sel : int { SEL_TD_A = 0, SEL_TD = 1, SEL_TD_B = 2, SEL_SEQ = 3, SEL_ELEM = 4, SEL_MATRIX = 5 };
+
+// ByMatrix: the operation of the c-th cell tried in a fit comes from the
+// SplitMix64 stream seeded with the fit's seed XOR this constant.
+constexpr unsigned long long MATRIX_OP_STREAM = 0xA0761D6478BD642Full;
+constexpr int MATRIX_HIST = 12;  // radix-select passes: 8 key digits, 4 position digits
 
 struct Trial {
   int j, k, op;
@@ -87,6 +93,9 @@ struct FitCtl {
   int nlog;
   int cbuf;              // which of the two argmax-count buffers is current
   long long phase_ticks[8];  // leader's wall time per phase (100 MHz ticks)
+  long long mdraws;      // ByMatrix: operation draws consumed so far
+  unsigned long long mlast_u;  // ByMatrix: key and position of the last
+  long long mlast_q;           // selected cell (the next selection's cursor)
 };
 
 // Device-side descriptor of one fit.  All arrays live in the caller's
@@ -103,6 +112,7 @@ struct FitDev {
   int omega;             // number of observed cells
   int sel;               // Sel
   double eps;
+  unsigned long long seed_ops;  // ByMatrix: seed ^ MATRIX_OP_STREAM
   STMF_G(const float) Rw;    // ldm x ldn, +inf at unobserved and padding cells
   STMF_G(const float) RwT;   // ldn x ldm, the transpose
   STMF_G(float) Uc;          // r x ldm: Uc[l*ldm + t] = U_tl
@@ -118,6 +128,20 @@ struct FitDev {
   STMF_G(int) order;         // ldn: columns by (td_col desc, index asc)
   STMF_G(int) rord;          // ldn: TD order of the visited row's columns
   STMF_G(double) tdrow;      // ldn: TD keys of the visited row (wide matrices)
+  // ByMatrix (null otherwise): per cell of the m x n working matrix (row-major,
+  // unpadded) td (-1 unobserved), f and the order-mapped key; line sums;
+  // radix-select histograms; the gathered and the ordered candidates
+  STMF_G(double) mtd;
+  STMF_G(int) mfk;
+  STMF_G(unsigned long long) mkey;
+  STMF_G(double) mtdr;       // m
+  STMF_G(double) mtdc;       // n
+  STMF_G(int) mhist;         // MATRIX_HIST x 256
+  STMF_G(int) mcnt;          // 1: gathered count
+  STMF_G(unsigned long long) mgat_u;  // tmax
+  STMF_G(int) mgat_q;        // tmax
+  STMF_G(int) mlist_q;       // tmax: candidates in order (cell position)
+  STMF_G(int) mlist_k;       // tmax: their component f(i, j)
   STMF_G(unsigned) tvec;     // 2 x TMAX x ldmax: atomic-min targets (order-mapped floats)
   STMF_G(double) epart;      // TMAX x gsize: per-workgroup partial errors
   STMF_G(double) eprime;     // TMAX: error of every trial of the batch

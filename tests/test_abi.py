@@ -75,7 +75,7 @@ def test_argument_errors_before_any_gpu_work(stmf):
     assert L.stmf_fit(dummy, dummy, 4, 4, 2, 1, 0, dummy, dummy, None, C.byref(o), None,
                       C.c_void_p(256), 1 << 30, None) == stmf.STMF_EINVAL
     for bad in (dict(selection=4), dict(selection=-1), dict(perm_mode=4), dict(perm_mode=-1),
-                dict(strategy=2), dict(strategy=-1)):
+                dict(strategy=3), dict(strategy=-1)):
         o = stmf.options(**bad)
         assert L.stmf_fit(dummy, dummy, 4, 4, 2, 1, 0, dummy, dummy, None, C.byref(o), None,
                           C.c_void_p(256), 1 << 30, None) == stmf.STMF_EINVAL

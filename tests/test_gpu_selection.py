@@ -162,7 +162,7 @@ def test_selection_batched_equals_plain(S):
 def test_selection_bad_options(S):
     print("selection options", flush=True)
     R, M = synth.int_planted(10, 12, 2, 0.2, seed=14)
-    for kw in (dict(selection=4), dict(selection=-1), dict(perm_mode=4), dict(strategy=2)):
+    for kw in (dict(selection=4), dict(selection=-1), dict(perm_mode=4), dict(strategy=3)):
         with pytest.raises(S.StmfError):
             S.stmf_fit(_t(R), _t(M), 2, 1, **kw)
 
@@ -238,3 +238,82 @@ def test_byelement_batched_equals_oracle(S):
         np.testing.assert_array_equal(U[0].cpu().numpy(), o.U)
         np.testing.assert_array_equal(V[0].cpu().numpy(), o.V)
         np.testing.assert_array_equal(T[0].cpu().numpy(), o.traj)
+
+
+# ------------------------------------------------------------------ ByMatrix
+MAT_CASES = [  # m, n, rank, iters, seed, missing
+    (20, 30, 3, 12, 31, 0.3), (40, 70, 3, 15, 32, 0.3), (70, 150, 4, 10, 33, 0.4),
+    (150, 70, 2, 10, 34, 0.3), (1, 40, 2, 5, 35, 0.2),
+]
+
+
+@pytest.mark.parametrize("m,n,rank,iters,seed,miss", MAT_CASES)
+@pytest.mark.parametrize("group", [0, 1])
+def test_bymatrix_integer(S, m, n, rank, iters, seed, miss, group):
+    print(f"ByMatrix int {m}x{n} r={rank} it={iters} group={group}", flush=True)
+    R, M = synth.int_planted(m, n, rank, miss, seed=seed, hi=30)
+    o = oracle.fit(R, M, rank, iters, seed=seed, prec="f32", init_hi=30, strategy=2, perm_mode=2,
+                   log_cap=iters + 1)
+    assert o.status == 0
+    g = S.stmf_fit(_t(R), _t(M), rank, iters, seed=seed, init_hi=30.0, group_size=group,
+                   strategy=2, perm_mode=2, log_cap=iters + 1)
+    _compare(g, o)
+
+
+@pytest.mark.parametrize("batch_max", [4, 16])
+def test_bymatrix_rounds_of_candidates(S, batch_max):
+    # rounds of at most batch_max candidates: the selection's cursor carries
+    # across rounds, ties of integer keys included
+    print(f"ByMatrix rounds batch_max={batch_max}", flush=True)
+    R, M = synth.int_planted(24, 40, 3, 0.3, seed=36, hi=12)
+    o = oracle.fit(R, M, 3, 20, seed=36, prec="f32", init_hi=12, strategy=2, perm_mode=2,
+                   log_cap=32)
+    g = S.stmf_fit(_t(R), _t(M), 3, 20, seed=36, init_hi=12.0, strategy=2, perm_mode=2,
+                   batch_max=batch_max, batch_first=batch_max, log_cap=32)
+    _compare(g, o)
+
+
+def test_bymatrix_exact_start_tries_every_cell(S):
+    print("ByMatrix exact start", flush=True)
+    rng = np.random.default_rng(6)
+    Us = rng.integers(0, 20, (30, 2)).astype(np.float32)
+    Vs = rng.integers(0, 20, (2, 50)).astype(np.float32)
+    R = np.max(Us[:, :, None] + Vs[None, :, :], axis=1).astype(np.float32)
+    M = np.ones_like(R, np.uint8)
+    o = oracle.fit(R, M, 2, 3, prec="f32", init_mode=2, U0=Us, perm_mode=2, strategy=2, seed=6)
+    g = S.stmf_fit(_t(R), _t(M), 2, 3, seed=6, U0=Us, perm_mode=2, strategy=2, log_cap=8,
+                   batch_max=64)
+    assert g.info["accepted"] == 0 and g.info["trials"] + g.info["noops"] == 1500
+    assert g.info["trials"] == o.stats["trials"] and g.info["noops"] == o.stats["noops"]
+    np.testing.assert_array_equal(g.traj, [0.0] * 4)
+
+
+def test_bymatrix_real(S):
+    print("ByMatrix real 60x150", flush=True)
+    R, M = synth.gene_expr(60, 150, 4, 0.5, seed=2)
+    o = oracle.fit(R, M, 4, 12, seed=2, prec="f32", init_mode=1, strategy=2, perm_mode=2,
+                   log_cap=16)
+    g = S.stmf_fit(_t(R), _t(M), 4, 12, seed=2, init_mode=1, strategy=2, perm_mode=2, log_cap=16)
+    _compare(g, o, exact=False)
+
+
+def test_bymatrix_gene_expression_prefix(S):
+    # the full gene-expression-shaped workload in the cooperative launch: the
+    # first 3 iterations (each keys and orders 500,000 cells), record by record
+    print("ByMatrix real 500x2000 prefix", flush=True)
+    R, M = synth.gene_expr()
+    o = oracle.fit(R, M, 5, 50, seed=2, prec="f32", init_mode=1, row_limit=3, strategy=2,
+                   perm_mode=2, log_cap=8)
+    g = S.stmf_fit(_t(R), _t(M), 5, 50, seed=2, init_mode=1, max_row_visits=3, log_cap=8,
+                   strategy=2, perm_mode=2)
+    assert _log_rows(g.log) == _log_rows(o.log)
+    np.testing.assert_allclose(g.log["e"], o.log["e"], rtol=1e-9)
+
+
+def test_bymatrix_not_batched(S):
+    print("ByMatrix batched refused", flush=True)
+    probs = synth.batched_problems(1, seed=72, integer=True, m_range=(12, 20), n_range=(12, 20),
+                                   r_range=(2, 2), miss_range=(0.2, 0.3))
+    dev = [dict(R=_t(p.R), M=_t(p.M), rank=p.rank, iters=2, seed=1) for p in probs]
+    with pytest.raises(S.StmfError):
+        S.stmf_fit_batched(dev, restarts=1, strategy=2)
