@@ -137,6 +137,22 @@ def test_fit_gene_expression_prefix(S):
     assert g.traj[0] == pytest.approx(o.traj[0], rel=1e-12)
 
 
+def test_fit_large_prefix(S):
+    # the large single factorization at full size (2000 x 20000, planted rank
+    # 20, 70% missing with row-dependent rates, rank 20, Random Acol): the
+    # first 3 row visits in the cooperative launch, decision by decision; the
+    # working matrix is wider than one workgroup's sort (column order through
+    # device memory) and each workgroup sweeps about 40 tiles
+    print("fit real 2000x20000 prefix", flush=True)
+    R, M = synth.large()
+    o = oracle.fit(R, M, 20, 100, seed=3, prec="f32", init_mode=1, row_limit=3, log_cap=8)
+    assert o.status == 0
+    g = S.stmf_fit(_t(R), _t(M), 20, 100, seed=3, init_mode=1, max_row_visits=3, log_cap=8)
+    assert _log_rows(g.log) == _log_rows(o.log)
+    np.testing.assert_allclose(g.log["e"], o.log["e"], rtol=1e-9)
+    assert g.traj[0] == pytest.approx(o.traj[0], rel=1e-12)
+
+
 def test_fit_nan_in_unobserved_cells(S):
     R, M = synth.int_planted(30, 40, 2, 0.3, seed=41)
     Rn = R.copy(); Rn[M == 0] = np.nan
