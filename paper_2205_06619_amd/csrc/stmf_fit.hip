@@ -1109,27 +1109,48 @@ DEV void sort_small(Grp& gp, Smem& S) {
 
 // Order of wide matrices: every workgroup ranks its slice of columns against
 // all the keys (descending, index ascending on ties), staged through LDS in
-// chunks; out[rank] = column.
+// chunks of SORT_MAX; 64 columns at a time, lane = column, wave w counting
+// the keys x = w, w + NWAVE, ... of each chunk, the eight counts added at
+// the end; out[rank] = column.
 DEV void sort_by_rank(Grp& gp, Smem& S, const GA double* keys, GA int* out) {
   const FitDev& d = *gp.d;
+  const int n = d.n;
   int lo, hi;
-  slice(d.n, gp.g, gp.G, lo, hi);
-  for (int base = lo; base < hi; base += NTHR) {
-    const int c = base + gp.tid;
-    const double key = c < hi ? ld_atomic(&keys[c]) : 0.0;
-    int rank = 0;
-    for (int x0 = 0; x0 < d.n; x0 += SORT_MAX) {
-      const int len = d.n - x0 < SORT_MAX ? d.n - x0 : SORT_MAX;
+  slice(n, gp.g, gp.G, lo, hi);
+  // the wave counts live beside the staged keys (SORT_MAX doubles)
+  int* part = S.u.s.idx;
+  for (int cb = lo; cb < hi; cb += 64) {
+    const int c = cb + gp.lane;
+    const bool valid = c < hi;
+    const double kc = valid ? ld_atomic(&keys[c]) : 0.0;
+    int cnt = 0;
+    for (int x0 = 0; x0 < n; x0 += SORT_MAX) {
+      const int len = n - x0 < SORT_MAX ? n - x0 : SORT_MAX;
       __syncthreads();
       for (int x = gp.tid; x < len; x += NTHR) S.u.s.key[x] = ld_atomic(&keys[x0 + x]);
       __syncthreads();
-      if (c < hi)
-        for (int x = 0; x < len; ++x) {
-          const double o = S.u.s.key[x];
-          rank += (o > key || (o == key && x0 + x < c)) ? 1 : 0;
-        }
+      int x = gp.wave;
+      for (; x + 3 * NWAVE < len; x += 4 * NWAVE) {
+        const double o0 = S.u.s.key[x], o1 = S.u.s.key[x + NWAVE];
+        const double o2 = S.u.s.key[x + 2 * NWAVE], o3 = S.u.s.key[x + 3 * NWAVE];
+        cnt += (o0 > kc || (o0 == kc && x0 + x < c)) ? 1 : 0;
+        cnt += (o1 > kc || (o1 == kc && x0 + x + NWAVE < c)) ? 1 : 0;
+        cnt += (o2 > kc || (o2 == kc && x0 + x + 2 * NWAVE < c)) ? 1 : 0;
+        cnt += (o3 > kc || (o3 == kc && x0 + x + 3 * NWAVE < c)) ? 1 : 0;
+      }
+      for (; x < len; x += NWAVE) {
+        const double o = S.u.s.key[x];
+        cnt += (o > kc || (o == kc && x0 + x < c)) ? 1 : 0;
+      }
     }
-    if (c < hi) st_coh(&out[rank], c);
+    part[gp.wave * 64 + gp.lane] = cnt;
+    __syncthreads();
+    if (gp.wave == 0 && valid) {
+      int rank = 0;
+      for (int w = 0; w < NWAVE; ++w) rank += part[w * 64 + gp.lane];
+      st_coh(&out[rank], c);
+    }
+    __syncthreads();
   }
 }
 
