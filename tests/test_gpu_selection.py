@@ -317,3 +317,21 @@ def test_bymatrix_not_batched(S):
     dev = [dict(R=_t(p.R), M=_t(p.M), rank=p.rank, iters=2, seed=1) for p in probs]
     with pytest.raises(S.StmfError):
         S.stmf_fit_batched(dev, restarts=1, strategy=2)
+
+
+# ------------------------------------------------------------------ maximum rank
+@pytest.mark.parametrize("strategy,sel,pm,iters", [
+    (0, 0, 0, 3), (0, 1, 0, 3), (0, 2, 0, 3), (0, 3, 0, 1), (1, 0, 3, 2), (2, 0, 2, 12),
+])
+def test_every_strategy_at_rank_64(S, strategy, sel, pm, iters):
+    # rank 64 (the largest supported): eight blocks of eight staged
+    # components, sixteen per candidate thread in the batch list
+    print(f"rank 64 strategy={strategy} selection={sel}", flush=True)
+    R, M = synth.int_planted(20, 30, 64, 0.25, seed=40 + strategy * 4 + sel, hi=40)
+    cap = int(M.sum()) * iters + 64
+    o = oracle.fit(R, M, 64, iters, seed=5, prec="f32", init_hi=40, strategy=strategy,
+                   selection=sel, perm_mode=pm, log_cap=cap)
+    assert o.status == 0
+    g = S.stmf_fit(_t(R), _t(M), 64, iters, seed=5, init_hi=40.0, strategy=strategy, selection=sel,
+                   perm_mode=pm, log_cap=cap)
+    _compare(g, o)
