@@ -349,10 +349,10 @@ def main():
     ap.add_argument("--large-only", action="store_true",
                     help="run only the large-factorization measurement (one JSON line)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched, serving, selection and quality comparisons")
+                    help="skip the batched, serving, selection, quality and large comparisons")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build runs a fit on a single MI355X "
+        print(f"bench.py measures one GPU: a fit runs on a single MI355X "
               f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
