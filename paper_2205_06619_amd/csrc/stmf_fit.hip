@@ -2003,7 +2003,8 @@ DEV bool matrix_iteration(Grp& gp, Smem& S, int it, int& cb, int& par, double& e
         acc_j = tr.j; acc_k = tr.k; acc_op = tr.op;
         draws += pos + dec + S.noops_before[dec] + 1;
         e_cur = ld_atomic(&ctl->e_new);
-        if (!refresh(gp, S, tr.k, true, tr, par, dec, acc_row, true, cb ^ 1)) return false;
+        // the keys of the next iteration are computed afresh: no counts or order
+        if (!refresh(gp, S, tr.k, true, tr, par, dec, acc_row, false, cb ^ 1)) return false;
         cb ^= 1;
         lap(4);
         par ^= 1;
@@ -2060,7 +2061,8 @@ DEV bool elem_row_visit(Grp& gp, Smem& S, int i, int it, int& cb, int& par, doub
         const Trial tr = S.trials[dec];
         acc_j = tr.j; acc_k = tr.k; acc_op = tr.op;
         e_cur = ld_atomic(&ctl->e_new);
-        if (!refresh(gp, S, tr.k, true, tr, par, dec, i, true, cb ^ 1)) return false;
+        // ByElement needs neither the argmax counts nor the column order
+        if (!refresh(gp, S, tr.k, true, tr, par, dec, i, false, cb ^ 1)) return false;
         cb ^= 1;
         lap(4);
         par ^= 1;
@@ -2197,7 +2199,10 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
           const Trial tr = S.trials[dec];
           acc_j = tr.j; acc_k = tr.k; acc_op = tr.op;
           e_cur = ld_atomic(&ctl->e_new);
-          if (!refresh(gp, S, tr.k, true, tr, par, dec, i, true, cb ^ 1)) return;
+          // the argmax counts and the column order serve TD_A and TD_B only
+          if (!refresh(gp, S, tr.k, true, tr, par, dec, i, sel == SEL_TD_A || sel == SEL_TD_B,
+                       cb ^ 1))
+            return;
           cb ^= 1;
           lap(4);
           par ^= 1;
@@ -2226,7 +2231,7 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
         }
         acc_j = best_tr.j; acc_k = best_tr.k; acc_op = best_tr.op;
         e_cur = e_best;
-        if (!refresh(gp, S, best_tr.k, true, best_tr, par, 0, i, true, cb ^ 1)) return;
+        if (!refresh(gp, S, best_tr.k, true, best_tr, par, 0, i, false, cb ^ 1)) return;
         cb ^= 1;
         lap(4);
         par ^= 1;
