@@ -96,6 +96,20 @@ def batched_compare():
             same = same and bool(torch.equal(U[q], g.U)) and bool(torch.equal(V[q], g.V))
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
+    # the autotuned launch shape (timed on the 16 largest problems, 2 passes)
+    from paper_2205_06619_amd import autotune
+    t0 = time.perf_counter()
+    tuned = autotune.tune_batched(dev, sample=16, iters=2, integer_exact=1)
+    tune_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs_t, statuses_t, _ = stmf.stmf_fit_batched(dev, restarts=b["restarts"], integer_exact=1,
+                                                  **tuned)
+    torch.cuda.synchronize()
+    t_tuned = time.perf_counter() - t0
+    same_tuned = statuses_t == statuses and all(
+        bool(torch.equal(Ua, Ub)) and bool(torch.equal(Va, Vb)) and bool(torch.equal(Ta, Tb))
+        for (Ua, Va, Ta), (Ub, Vb, Tb) in zip(outs, outs_t))
     fits = len(probs) * b["restarts"]
     return {
         "config": {"workload": f"{b['count']} integer planted problems x {b['restarts']} restarts, "
@@ -111,6 +125,9 @@ def batched_compare():
         "speedup": t_plain / t_batched,
         "trials": plain_trials,
         "identical": same,
+        "autotuned": {"options": tuned, "tune_s": tune_s, "batched_s": t_tuned,
+                      "speedup_vs_plain": t_plain / t_tuned, "speedup_vs_default": t_batched / t_tuned,
+                      "identical": same_tuned},
     }
 
 

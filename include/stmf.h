@@ -306,6 +306,13 @@ int stmf_engine_admit(stmf_engine* eng, const float* R, const uint8_t* M, int m,
  * synchronising the stream to see which jobs finished. */
 int stmf_batch_tick(stmf_engine* eng, int max_rows, void* stream);
 
+/* Ticks as a captured HIP graph (on = 1, the default) or as eager launches
+ * (on = 0).  A graph holds the queue reset (a fill kernel) and the fit kernel;
+ * it is captured again when the number of resident jobs or max_rows changes,
+ * and the device table of resident jobs is uploaded only when that set
+ * changes.  Both give the same results. */
+int stmf_engine_set_graph(stmf_engine* eng, int on);
+
 /* Synchronous: *done = 1 when the job in `slot` has finished. */
 int stmf_engine_poll(stmf_engine* eng, int slot, int* done, void* stream);
 

@@ -829,6 +829,20 @@ struct stmf_engine {
   std::vector<Slot> slots;
   std::vector<std::pair<size_t, size_t>> free_list;  // (offset, length), by offset
   std::mutex mu;
+  // A tick is a captured graph (queue reset by a fill kernel, then the fit
+  // kernel), re-captured when its launch shape changes; the device table of
+  // resident jobs is uploaded only when the resident set changes.
+  bool use_graph = true;
+  std::vector<FitDev> uploaded;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int g_nfits = -1, g_grid = -1, g_rows = -1, g_sel = -1;
+  ~stmf_engine() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
 };
 
 static bool arena_alloc(stmf_engine* e, size_t len, size_t& off) {
@@ -933,11 +947,18 @@ int stmf_engine_admit(stmf_engine* e, const float* R, const uint8_t* M, int m, i
   return STMF_OK;
 }
 
+// The tick's work on stream s: queue reset, then the fit kernel.
+static int tick_work(stmf_engine* e, int nfits, int grid, int max_rows, hipStream_t s) {
+  int st = fill_u32(e->arena + e->queue_off, 1, 0, s);
+  if (st) return st;
+  return launch_fit_kernel((const FitDev*)(e->arena + e->table_off), nfits, 1, grid, max_rows,
+                           (unsigned*)(e->arena + e->queue_off), kernel_sel(e->opt), s);
+}
+
 int stmf_batch_tick(stmf_engine* e, int max_rows, void* stream) {
   if (!e || max_rows < 0) return STMF_EINVAL;
   std::lock_guard<std::mutex> lk(e->mu);
-  static thread_local std::vector<FitDev> table;
-  table.clear();
+  std::vector<FitDev> table;
   for (auto& S : e->slots)
     if (S.used) table.push_back(S.dev);
   if (table.empty()) return STMF_OK;
@@ -945,16 +966,45 @@ int stmf_batch_tick(stmf_engine* e, int max_rows, void* stream) {
   int st = device_props(P);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
-  HIPCHK(hipMemcpyAsync(e->arena + e->table_off, table.data(), table.size() * sizeof(FitDev),
-                        hipMemcpyHostToDevice, s));
-  st = fill_u32(e->arena + e->queue_off, 1, 0, s);
-  if (st) return st;
-  const int grid = std::min<int>((int)table.size(), P.coresident);
-  st = launch_fit_kernel((const FitDev*)(e->arena + e->table_off), (int)table.size(), 1, grid,
-                         max_rows, (unsigned*)(e->arena + e->queue_off), kernel_sel(e->opt), s);
-  if (st) return st;
-  // the table is read by the launch: wait for it before the host array changes
+  const int nfits = (int)table.size();
+  if (table.size() != e->uploaded.size() ||
+      std::memcmp(table.data(), e->uploaded.data(), table.size() * sizeof(FitDev)) != 0) {
+    HIPCHK(hipMemcpyAsync(e->arena + e->table_off, table.data(), table.size() * sizeof(FitDev),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    e->uploaded = table;
+  }
+  const int grid = std::min<int>(nfits, P.coresident);
+  if (!e->use_graph) {
+    st = tick_work(e, nfits, grid, max_rows, s);
+    if (st) return st;
+  } else {
+    const int sel = kernel_sel(e->opt);
+    if (!e->gexec || e->g_nfits != nfits || e->g_grid != grid || e->g_rows != max_rows ||
+        e->g_sel != sel) {
+      if (e->gexec) { HIPCHK(hipGraphExecDestroy(e->gexec)); e->gexec = nullptr; }
+      if (e->graph) { HIPCHK(hipGraphDestroy(e->graph)); e->graph = nullptr; }
+      if (!e->cap) HIPCHK(hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking));
+      HIPCHK(hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal));
+      st = tick_work(e, nfits, grid, max_rows, e->cap);
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(e->cap, &g);
+      if (st) { if (g) (void)hipGraphDestroy(g); return st; }
+      if (ec != hipSuccess) return STMF_EHIP;
+      e->graph = g;
+      HIPCHK(hipGraphInstantiate(&e->gexec, e->graph, nullptr, nullptr, 0));
+      e->g_nfits = nfits; e->g_grid = grid; e->g_rows = max_rows; e->g_sel = sel;
+    }
+    HIPCHK(hipGraphLaunch(e->gexec, s));
+  }
   HIPCHK(hipStreamSynchronize(s));
+  return STMF_OK;
+}
+
+int stmf_engine_set_graph(stmf_engine* e, int on) {
+  if (!e) return STMF_EINVAL;
+  std::lock_guard<std::mutex> lk(e->mu);
+  e->use_graph = on != 0;
   return STMF_OK;
 }
 

@@ -27,7 +27,7 @@ EXPORTS = (
     "stmf_options_default", "stmf_fit_workspace", "stmf_fit", "stmf_draw_init",
     "stmf_fit_batched_workspace", "stmf_fit_batched", "stmf_engine_create", "stmf_engine_destroy",
     "stmf_job_footprint", "stmf_engine_admit", "stmf_batch_tick", "stmf_engine_poll",
-    "stmf_engine_retire", "stmf_dcor_workspace", "stmf_distance_correlation",
+    "stmf_engine_retire", "stmf_engine_set_graph", "stmf_dcor_workspace", "stmf_distance_correlation",
     "stmf_completion_metrics_workspace", "stmf_completion_metrics",
 )
 
@@ -103,6 +103,7 @@ def _load():
         "stmf_batch_tick": ([P, I, P], I),
         "stmf_engine_poll": ([P, I, P, P], I),
         "stmf_engine_retire": ([P, I, P, P, P, P, P], I),
+        "stmf_engine_set_graph": ([P, I], I),
         "stmf_dcor_workspace": ([I], Z),
         "stmf_distance_correlation": ([P, P, I, P, P, P, Z, P], I),
         "stmf_completion_metrics_workspace": ([I, I, I], Z),
@@ -390,6 +391,11 @@ def stmf_engine_admit(eng: Engine, R, M, rank, iters, seed=0, stream=None) -> Op
 def stmf_batch_tick(eng: Engine, max_rows: int, stream=None):
     """Advance every resident job by at most max_rows row visits (one launch)."""
     _chk(lib.stmf_batch_tick(eng.handle, max_rows, _stream(stream)), "stmf_batch_tick")
+
+
+def stmf_engine_set_graph(eng: Engine, on: bool):
+    """Ticks as a captured HIP graph (default) or as eager launches."""
+    _chk(lib.stmf_engine_set_graph(eng.handle, 1 if on else 0), "stmf_engine_set_graph")
 
 
 def stmf_engine_poll(eng: Engine, slot: int, stream=None) -> bool:

@@ -1,0 +1,41 @@
+"""Host logic of the launch-shape autotuner: buckets, the choice rule and
+the JSON cache (no GPU)."""
+import json
+
+from paper_2205_06619_amd import autotune
+
+
+def test_bucket_rounds_the_working_shape_up():
+    assert autotune.bucket(200, 100, 3) == "128x256r4"
+    assert autotune.bucket(100, 200, 3) == "128x256r4"
+    assert autotune.bucket(500, 2000, 5) == "512x2048r8"
+    assert autotune.bucket(1, 1, 1) == "1x1r1"
+
+
+def test_choose_takes_the_fastest_and_the_first_on_ties():
+    t = {(0, 0): 5.0, (16, 0): 3.0, (64, 0): 3.0, (0, 256): 4.0}
+    best, times = autotune.choose(list(t), lambda bf, bm: t[(bf, bm)])
+    assert best == (16, 0)
+    assert times == {"0,0": 5.0, "16,0": 3.0, "64,0": 3.0, "0,256": 4.0}
+
+
+def test_choose_keeps_the_best_of_repeats():
+    seq = iter([9.0, 2.0, 4.0, 3.0])
+    best, times = autotune.choose([(0, 0), (16, 0)], lambda bf, bm: next(seq), repeats=2)
+    assert best == (0, 0) and times["0,0"] == 2.0 and times["16,0"] == 3.0
+
+
+def test_cache_round_trip(tmp_path):
+    path = tmp_path / "sub" / "tune.json"
+    c = autotune.Cache(str(path))
+    assert c.get("fit:8x8r2") is None
+    c.put("fit:8x8r2", {"batch_first": 16, "batch_max": 256, "times_ms": {"16,256": 1.0}})
+    again = autotune.Cache(str(path))
+    assert again.get("fit:8x8r2")["batch_max"] == 256
+    assert json.loads(path.read_text())["fit:8x8r2"]["batch_first"] == 16
+
+
+def test_candidates_are_valid_options():
+    for bf, bm in autotune.CANDIDATES:
+        assert 0 <= bf and 0 <= bm <= 1024
+        assert bm == 0 or bf <= bm

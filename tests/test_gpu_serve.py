@@ -140,3 +140,41 @@ def test_serve_loop_results_match_alone(S):
         assert j.finished >= j.arrival
         ref = S.stmf_fit(j.R, j.M, j.rank, j.iters, seed=j.seed, group_size=1)
         _same(j.result, ref)
+
+
+def test_engine_graph_ticks_equal_eager_ticks(S):
+    # the same stream of admissions and ticks through an engine whose ticks
+    # replay a captured graph and one that launches eagerly: every job's
+    # result is identical (the graph is replayed many times, re-captured as
+    # the resident set changes, with host polls between the replays)
+    print("engine graph vs eager", flush=True)
+    jobs = _jobs(65, 5)
+    engs = [S.stmf_engine_create(256 << 20, 8), S.stmf_engine_create(256 << 20, 8)]
+    S.stmf_engine_set_graph(engs[1], False)
+    try:
+        slots = [[], []]
+        results = [{}, {}]
+        for e, eng in enumerate(engs):
+            for j in jobs[:2]:
+                slots[e].append(S.stmf_engine_admit(eng, j["R"], j["M"], j["rank"], j["iters"], j["seed"]))
+        for step in range(400):
+            if step == 3:
+                for e, eng in enumerate(engs):
+                    for j in jobs[2:]:
+                        slots[e].append(S.stmf_engine_admit(eng, j["R"], j["M"], j["rank"], j["iters"],
+                                                            j["seed"]))
+            for e, eng in enumerate(engs):
+                S.stmf_batch_tick(eng, 2)
+                for s in slots[e]:
+                    if s not in results[e] and S.stmf_engine_poll(eng, s):
+                        results[e][s] = S.stmf_engine_retire(eng, s)
+            if all(len(results[e]) == len(jobs) for e in range(2)):
+                break
+        assert all(len(results[e]) == len(jobs) for e in range(2))
+    finally:
+        for eng in engs:
+            S.stmf_engine_destroy(eng)
+    for q, j in enumerate(jobs):
+        a, b = results[0][slots[0][q]], results[1][slots[1][q]]
+        _same(a, b)
+        _same(a, _alone(S, j))
