@@ -565,8 +565,10 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
 template <int CTRL>
 DEV double dpp_add(double a) {
   const unsigned long long b = __double_as_longlong(a);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  // every lane reads a lane of its own 16-lane row: no lane keeps an old
+  // value, so the moves need none (no zeroing before each exchange)
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
   return a + __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 // Sum over a 16-lane row, in lane 16 * row: quad exchanges (permutations
