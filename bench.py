@@ -18,8 +18,9 @@ Three smaller comparisons follow the headline step (skipped with --no-extras):
 "batched" runs uneven integer problems with restarts in one persistent
 launch and through the plain one-fit-at-a-time path (results compared bit
 for bit); "serving" replays a Poisson stream of completion jobs through the
-continuous-batching loop and through the plain sequential path (p50/p99
-latency, jobs/s); "selections" runs the other ByRow selections (TD, TD_B,
+continuous-batching loop (each job on as many workgroups as it has tiles,
+and with one workgroup per job) and through the plain sequential path
+(p50/p99 latency, jobs/s); "selections" runs the other ByRow selections (TD, TD_B,
 SEQ), ByElement with PermC, ByMatrix (300 iterations of at most one update
 each) and the PermR row order on the headline matrix for a few passes each; "quality" measures completion quality (RMSE-A,
 RMSE-P, distance correlation on 20% held-out cells of R_lambda matrices)
@@ -54,7 +55,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fit_kernel_gene_expr_500x2000_tra
 BATCHED = dict(count=64, restarts=2, iters=5, m=(50, 250), n=(50, 500), rank=(2, 8),
                missing=(0.2, 0.8), seed=4)
 SERVING = dict(count=48, rate_per_s=100.0, iters=5, m=(50, 250), n=(50, 500), rank=(2, 8),
-               missing=(0.2, 0.8), seed=5, rows_per_tick=16, slots=256)
+               missing=(0.2, 0.8), seed=5, rows_per_tick=48, slots=256)
 
 
 def splitmix64(seed: int, count: int):
@@ -132,36 +133,52 @@ def batched_compare():
 
 
 def serving_compare():
-    """Continuous batching vs the plain sequential path on one Poisson stream."""
+    """Continuous batching (each job on as many workgroups as it has tiles,
+    then one workgroup per job) vs the plain sequential path on one Poisson
+    stream."""
     import numpy as np
     from paper_2205_06619_amd import serve, stmf
     c = SERVING
-    jobs = serve.synthetic_jobs(c["count"], c["rate_per_s"], seed=c["seed"], m_range=c["m"],
-                                n_range=c["n"], r_range=c["rank"], miss_range=c["missing"],
-                                iters=c["iters"])
-    need = sum(stmf.stmf_job_footprint(j.R.shape[0], j.R.shape[1], j.rank, j.iters) for j in jobs)
-    backend = serve.EngineBackend(need + (64 << 20), c["slots"])
-    try:
-        st = serve.Server(backend, rows_per_tick=c["rows_per_tick"]).run(jobs)
-    finally:
-        backend.close()
-    served = {j.jid: j.result for j in jobs}
-    seq_jobs = serve.synthetic_jobs(c["count"], c["rate_per_s"], seed=c["seed"], m_range=c["m"],
+
+    def stream():
+        return serve.synthetic_jobs(c["count"], c["rate_per_s"], seed=c["seed"], m_range=c["m"],
                                     n_range=c["n"], r_range=c["rank"], miss_range=c["missing"],
                                     iters=c["iters"])
+
+    def continuous(group_size):
+        jobs = stream()
+        backend = serve.EngineBackend(64 << 20, c["slots"], group_size=group_size)
+        need = sum(backend.footprint(j) for j in jobs)
+        backend.close()
+        backend = serve.EngineBackend(need + (64 << 20), c["slots"], group_size=group_size)
+        try:
+            st = serve.Server(backend, rows_per_tick=c["rows_per_tick"]).run(jobs)
+        finally:
+            backend.close()
+        return jobs, st
+
+    grouped, st = continuous(0)
+    single, st1 = continuous(1)
+    seq_jobs = stream()
     sq = serve.sequential(seq_jobs, lambda j: stmf.stmf_fit(j.R, j.M, j.rank, j.iters, seed=j.seed))
-    # the plain path spreads a fit over several workgroups (another FP64
-    # summation order): trajectories agree to rounding
-    worst = max(float(np.max(np.abs(served[j.jid].traj - j.result.traj) / np.abs(j.result.traj)))
-                for j in seq_jobs)
+    # the grouped engine reproduces the plain path bit for bit; one workgroup
+    # per job sums the errors in another FP64 order: trajectories agree to
+    # rounding
+    same = all(np.array_equal(a.result.traj, b.result.traj) and
+               bool((a.result.U == b.result.U).all()) and bool((a.result.V == b.result.V).all())
+               for a, b in zip(grouped, seq_jobs))
+    worst = max(float(np.max(np.abs(a.result.traj - b.result.traj) / np.abs(b.result.traj)))
+                for a, b in zip(single, seq_jobs))
     return {
         "config": {"workload": f"{c['count']} FP32 noisy planted completion jobs, Poisson arrivals "
                                f"at {c['rate_per_s']} jobs/s, m in {list(c['m'])}, n in {list(c['n'])}, "
                                f"rank in {list(c['rank'])}, {c['iters']} passes, "
                                f"{c['rows_per_tick']} row visits per tick"},
         "continuous": st.as_dict(),
+        "continuous_one_workgroup_per_job": st1.as_dict(),
         "sequential": sq.as_dict(),
-        "max_traj_rel_diff": worst,
+        "grouped_equals_plain": same,
+        "one_workgroup_max_traj_rel_diff": worst,
     }
 
 
@@ -365,6 +382,8 @@ def main():
                     help="run only the completion-quality comparison (one JSON line)")
     ap.add_argument("--large-only", action="store_true",
                     help="run only the large-factorization measurement (one JSON line)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving comparison (one JSON line)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, serving, selection, quality and large comparisons")
     args = ap.parse_args()
@@ -397,6 +416,9 @@ def main():
         return
     if args.large_only:
         print(json.dumps(large_compare()), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps(serving_compare()), flush=True)
         return
 
     def step():

@@ -285,14 +285,25 @@ typedef struct stmf_engine stmf_engine;
 
 /* A continuous-batching engine over a caller-owned device arena (ws, bytes).
  * Up to max_slots fits are resident at once; each holds its working matrix,
- * factors and state in the arena from admission to retirement. */
+ * factors and state in the arena from admission to retirement.
+ * opt->group_size is the most workgroups one job runs on (0: no limit but
+ * the co-resident workgroup count): a job gets the smaller of it and its tile
+ * count (64 x 64 tiles of the working matrix), fixed at admission, and its
+ * result is that of stmf_fit with that group_size and the same seed and
+ * options (with group_size 0, stmf_fit's own result).  Options decision_log, perm,
+ * init_mode 2, max_row_visits and strategy 2 are rejected (STMF_EINVAL). */
 int stmf_engine_create(void* ws, size_t ws_bytes, int max_slots,
                        const stmf_options* opt, stmf_engine** out);
 void stmf_engine_destroy(stmf_engine* eng);
 
 /* Arena bytes one job of this shape needs (admission footprint), with the
- * default options (acol_p 5, batch_max 0). */
+ * default options (acol_p 5, batch_max 0) and one workgroup per job. */
 size_t stmf_job_footprint(int m, int n, int rank, int iters);
+
+/* The same for a job of this engine (its options and group size); 0 for an
+ * invalid shape. */
+size_t stmf_engine_job_footprint(const stmf_engine* eng, int m, int n, int rank,
+                                 int iters);
 
 /* Admit a job: copies R/M (device) into the arena and initialises the fit.
  * STMF_EBUSY if no slot or not enough contiguous arena memory is free.
@@ -301,16 +312,21 @@ int stmf_engine_admit(stmf_engine* eng, const float* R, const uint8_t* M, int m,
                       int n, int rank, int iters, uint64_t seed, int* slot,
                       void* stream);
 
-/* Advance every active job by at most max_rows row visits, in one launch
- * (one workgroup per job).  Stream-ordered; call stmf_engine_poll after
- * synchronising the stream to see which jobs finished. */
+/* Advance every active job by at most max_rows row visits.  With one
+ * workgroup per job this is one launch whose workgroups take jobs from a
+ * queue; with larger groups the jobs (in slot order) are laid side by side
+ * over as many launches as the co-resident workgroups need.  Stream-ordered;
+ * call stmf_engine_poll after synchronising the stream to see which jobs
+ * finished.  STMF_ETIMEOUT from poll: a group barrier waited more than its
+ * bound (another kernel held the device's compute units). */
 int stmf_batch_tick(stmf_engine* eng, int max_rows, void* stream);
 
 /* Ticks as a captured HIP graph (on = 1, the default) or as eager launches
- * (on = 0).  A graph holds the queue reset (a fill kernel) and the fit kernel;
- * it is captured again when the number of resident jobs or max_rows changes,
- * and the device table of resident jobs is uploaded only when that set
- * changes.  Both give the same results. */
+ * (on = 0).  A graph holds the tick's launches (with one workgroup per job, a
+ * fill kernel resetting the queue and the fit kernel); it is captured again
+ * when the launch plan (jobs per launch and their groups) or max_rows
+ * changes, and the device table of resident jobs is uploaded only when that
+ * set changes.  Both give the same results. */
 int stmf_engine_set_graph(stmf_engine* eng, int on);
 
 /* Synchronous: *done = 1 when the job in `slot` has finished. */

@@ -2270,10 +2270,14 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
   group_sync(gp, S);
 }
 
-// One fit per group of gsize workgroups.  With nfits > 1 every workgroup
-// takes fits from a queue, one workgroup per fit.
+// Which fit each workgroup works on.  With a queue (batched fits), every
+// workgroup takes fits from it one after another, one workgroup per fit.
+// Without one, the fits own consecutive ranges of the grid, fits[f].gsize
+// workgroups each in table order (one fit over the whole grid, or several
+// fits side by side), and a workgroup beyond the last range has nothing to do.
+// fit_run has one call site, so it is expanded once per kernel.
 template <int MODE>
-DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int gsize, int max_rows,
+DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int max_rows,
                          unsigned* __restrict__ queue) {
   extern __shared__ __align__(16) char smem_raw[];
   Smem& S = *reinterpret_cast<Smem*>(smem_raw);
@@ -2281,48 +2285,51 @@ DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int gsize, 
   gp.tid = threadIdx.x;
   gp.lane = threadIdx.x & 63;
   gp.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  gp.g = blockIdx.x % gsize;
-  gp.G = gsize;
-  if (nfits == 1 && gsize == (int)gridDim.x) {
-    gp.d = &fits[0];
-    gp.ctl = fits[0].ctl;
-    if (ld_atomic(&gp.ctl->phase) != 2) fit_run<MODE>(gp, S, max_rows);
-    return;
-  }
   __shared__ int fid_s;
+  int b = (int)blockIdx.x;
   while (true) {
-    if (gp.tid == 0) fid_s = (int)atomicAdd(queue, 1u);
-    __syncthreads();
-    const int fid = fid_s;
-    __syncthreads();
+    int fid;
+    if (queue) {
+      if (gp.tid == 0) fid_s = (int)atomicAdd(queue, 1u);
+      __syncthreads();
+      fid = fid_s;
+      __syncthreads();
+      gp.g = 0;
+      gp.G = 1;
+    } else {
+      if (b < 0) break;
+      fid = 0;
+      while (fid < nfits && b >= fits[fid].gsize) b -= fits[fid].gsize, ++fid;
+      gp.g = b;
+      gp.G = fid < nfits ? fits[fid].gsize : 1;
+      b = -1;
+    }
     if (fid >= nfits) break;
     gp.d = &fits[fid];
     gp.ctl = fits[fid].ctl;
-    gp.g = 0;
-    gp.G = 1;
     if (ld_atomic(&gp.ctl->phase) != 2) fit_run<MODE>(gp, S, max_rows);
   }
 }
 
 // FastSTMF (TD_A) fits.
 __global__ void __launch_bounds__(NTHR) fit_kernel(const FitDev* __restrict__ fits, int nfits,
-                                                   int gsize, int max_rows,
+                                                   int max_rows,
                                                    unsigned* __restrict__ queue) {
-  fit_kernel_body<0>(fits, nfits, gsize, max_rows, queue);
+  fit_kernel_body<0>(fits, nfits, max_rows, queue);
 }
 
 // Fits with any ByRow selection (all fits of one launch share it).
 __global__ void __launch_bounds__(NTHR) fit_kernel_sel(const FitDev* __restrict__ fits, int nfits,
-                                                       int gsize, int max_rows,
+                                                       int max_rows,
                                                        unsigned* __restrict__ queue) {
-  fit_kernel_body<1>(fits, nfits, gsize, max_rows, queue);
+  fit_kernel_body<1>(fits, nfits, max_rows, queue);
 }
 
 // ByMatrix fits.
 __global__ void __launch_bounds__(NTHR) fit_kernel_matrix(const FitDev* __restrict__ fits,
-                                                          int nfits, int gsize, int max_rows,
+                                                          int nfits, int max_rows,
                                                           unsigned* __restrict__ queue) {
-  fit_kernel_body<2>(fits, nfits, gsize, max_rows, queue);
+  fit_kernel_body<2>(fits, nfits, max_rows, queue);
 }
 
 size_t fit_smem_bytes() { return sizeof(Smem); }

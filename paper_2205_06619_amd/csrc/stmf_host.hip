@@ -15,10 +15,9 @@
 namespace stmf {
 
 // kernels (stmf_fit.hip, stmf_prims.hip, stmf_setup.hip)
-__global__ void fit_kernel(const FitDev* fits, int nfits, int gsize, int max_rows, unsigned* queue);
-__global__ void fit_kernel_sel(const FitDev* fits, int nfits, int gsize, int max_rows, unsigned* queue);
-__global__ void fit_kernel_matrix(const FitDev* fits, int nfits, int gsize, int max_rows,
-                                  unsigned* queue);
+__global__ void fit_kernel(const FitDev* fits, int nfits, int max_rows, unsigned* queue);
+__global__ void fit_kernel_sel(const FitDev* fits, int nfits, int max_rows, unsigned* queue);
+__global__ void fit_kernel_matrix(const FitDev* fits, int nfits, int max_rows, unsigned* queue);
 size_t fit_smem_bytes();
 size_t masked_error_ws(int m, int n);
 hipError_t launch_maxplus(const float*, const float*, int, int, int, float*, int32_t*, hipStream_t);
@@ -444,28 +443,22 @@ static int launch_output(const Layout& L, char* base, float* U_out, float* V_out
 }
 
 // sel: the ByRow selection of every fit of the launch (TD_A runs the kernel
-// compiled for it alone).
-static int launch_fit_kernel(const FitDev* dev_fits, int nfits, int G, int grid, int max_rows,
-                             unsigned* queue, int sel, hipStream_t s) {
+// compiled for it alone).  queue: batched launches (one workgroup per fit,
+// fits taken from the queue); null: the fits own consecutive ranges of
+// gsize workgroups.  A cooperative launch has the runtime check that the
+// whole grid is resident at once; other launches with group barriers keep
+// the grid within the co-resident count.
+static int launch_fit_kernel(const FitDev* dev_fits, int nfits, int grid, int max_rows,
+                             unsigned* queue, int sel, bool cooperative, hipStream_t s) {
   const size_t smem = fit_smem_bytes();
-  if (G > 1) {
-    void* args[] = {(void*)&dev_fits, (void*)&nfits, (void*)&G, (void*)&max_rows, (void*)&queue};
-    const void* k = sel == SEL_TD_A     ? (const void*)fit_kernel
-                    : sel == SEL_MATRIX ? (const void*)fit_kernel_matrix
-                                        : (const void*)fit_kernel_sel;
+  const void* k = sel == SEL_TD_A     ? (const void*)fit_kernel
+                  : sel == SEL_MATRIX ? (const void*)fit_kernel_matrix
+                                      : (const void*)fit_kernel_sel;
+  void* args[] = {(void*)&dev_fits, (void*)&nfits, (void*)&max_rows, (void*)&queue};
+  if (cooperative)
     HIPCHK(hipLaunchCooperativeKernel(k, dim3(grid), dim3(NTHR), args, (unsigned)smem, s));
-  } else {
-    if (sel == SEL_TD_A)
-      hipLaunchKernelGGL(fit_kernel, dim3(grid), dim3(NTHR), smem, s, dev_fits, nfits, G, max_rows,
-                         queue);
-    else if (sel == SEL_MATRIX)
-      hipLaunchKernelGGL(fit_kernel_matrix, dim3(grid), dim3(NTHR), smem, s, dev_fits, nfits, G,
-                         max_rows, queue);
-    else
-      hipLaunchKernelGGL(fit_kernel_sel, dim3(grid), dim3(NTHR), smem, s, dev_fits, nfits, G,
-                         max_rows, queue);
-    HIPCHK(hipGetLastError());
-  }
+  else
+    HIPCHK(hipLaunchKernel(k, dim3(grid), dim3(NTHR), args, smem, s));
   return STMF_OK;
 }
 
@@ -649,8 +642,8 @@ int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters
   HIPCHK(hipEventCreate(&ev0));
   HIPCHK(hipEventCreate(&ev1));
   HIPCHK(hipEventRecord(ev0, s));
-  st = launch_fit_kernel((const FitDev*)(base + L.dev), 1, G, G, o.max_row_visits, nullptr,
-                         kernel_sel(o), s);
+  st = launch_fit_kernel((const FitDev*)(base + L.dev), 1, G, o.max_row_visits, nullptr,
+                         kernel_sel(o), G > 1, s);
   if (st) { (void)hipEventDestroy(ev0); (void)hipEventDestroy(ev1); return st; }
   HIPCHK(hipEventRecord(ev1, s));
   FitCtl c;
@@ -774,8 +767,8 @@ int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts, const stmf_op
     st = fill_u32(base + B.queue, 1, 0, s);
     if (st) return st;
     const int grid = std::min<int>((int)table.size(), P.coresident);
-    st = launch_fit_kernel((const FitDev*)(base + B.table), (int)table.size(), 1, grid, 0,
-                           (unsigned*)(base + B.queue), kernel_sel(o), s);
+    st = launch_fit_kernel((const FitDev*)(base + B.table), (int)table.size(), grid, 0,
+                           (unsigned*)(base + B.queue), kernel_sel(o), false, s);
     if (st) return st;
   }
   HIPCHK(hipStreamSynchronize(s));  // host staging vectors go out of scope after this
@@ -809,13 +802,21 @@ int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts, const stmf_op
 // ================================================================ serving
 // A continuous-batching engine: jobs are admitted into slots of a
 // caller-owned arena (first-fit over a free list, by footprint), each tick
-// advances every active job by a bounded number of row visits in one launch
-// (one workgroup per job, state kept in the arena between ticks), and
-// finished jobs are retired to free their memory for new admissions.
+// advances every active job by a bounded number of row visits (state kept in
+// the arena between ticks), and finished jobs are retired to free their
+// memory for new admissions.  A job runs on a group of G workgroups, G the
+// smaller of the engine's group size (0: the co-resident count) and the
+// job's tile count, fixed at admission: its result is that of stmf_fit with
+// group_size G, which is stmf_fit's own choice when the group size is 0.  With G = 1
+// for every job a tick is one launch whose workgroups take jobs from a
+// queue; otherwise the jobs are laid side by side over the grid, as many
+// per launch as the co-resident workgroups hold, in slot order.
 struct stmf_engine {
   char* arena = nullptr;
   size_t bytes = 0;
   int max_slots = 0;
+  int gcap = 1;        // workgroups per job, at most
+  int coresident = 0;  // fit-kernel workgroups resident at once
   stmf_options opt;
   size_t table_off = 0, queue_off = 0, heap_off = 0;
   struct Slot {
@@ -823,21 +824,24 @@ struct stmf_engine {
     size_t off = 0, len = 0;
     Layout L;
     FitDev dev;
+    int G = 1;
     std::vector<int32_t> perm, cols;
     std::vector<float> U0;
   };
   std::vector<Slot> slots;
   std::vector<std::pair<size_t, size_t>> free_list;  // (offset, length), by offset
   std::mutex mu;
-  // A tick is a captured graph (queue reset by a fill kernel, then the fit
-  // kernel), re-captured when its launch shape changes; the device table of
-  // resident jobs is uploaded only when the resident set changes.
+  // A tick is a captured graph (queue reset by a fill kernel and one fit
+  // launch, or one fit launch per pack of jobs), re-captured when its launch
+  // plan changes; the device table of resident jobs is uploaded only when the
+  // resident set changes.
   bool use_graph = true;
   std::vector<FitDev> uploaded;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  int g_nfits = -1, g_grid = -1, g_rows = -1, g_sel = -1;
+  std::vector<int> g_plan;  // the captured plan (first, count, grid per launch)
+  int g_rows = -1, g_sel = -1;
   ~stmf_engine() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -884,14 +888,22 @@ size_t stmf_job_footprint(int m, int n, int rank, int iters) {
   return L.total;
 }
 
+size_t stmf_engine_job_footprint(const stmf_engine* e, int m, int n, int rank, int iters) {
+  if (!e || m < 1 || n < 1 || rank < 1 || rank > RMAX || iters < 0) return 0;
+  Layout L;
+  make_layout(m, n, rank, iters, 1, e->opt.acol_p, e->opt.batch_max, L);
+  const int G = std::min(e->gcap, L.nrt * L.nct);
+  if (G > 1) make_layout(m, n, rank, iters, G, e->opt.acol_p, e->opt.batch_max, L);
+  return L.total;
+}
+
 int stmf_engine_create(void* ws, size_t ws_bytes, int max_slots, const stmf_options* opt,
                        stmf_engine** out) {
   if (!out || max_slots < 1) return STMF_EINVAL;
   stmf_options o;
   int st = resolve(opt, o);
   if (st) return st;
-  if (o.decision_log || o.perm || o.init_mode == 2 || o.max_row_visits || o.group_size > 1)
-    return STMF_EINVAL;
+  if (o.decision_log || o.perm || o.init_mode == 2 || o.max_row_visits) return STMF_EINVAL;
   if (o.strategy == 2) return STMF_EINVAL;  // ByMatrix runs through stmf_fit only
   if (!ws || ((uintptr_t)ws & 255)) return STMF_ENOMEM;
   const size_t table = al256((size_t)max_slots * sizeof(FitDev));
@@ -904,6 +916,9 @@ int stmf_engine_create(void* ws, size_t ws_bytes, int max_slots, const stmf_opti
   e->arena = (char*)ws;
   e->bytes = ws_bytes;
   e->max_slots = max_slots;
+  // group_size 0: as stmf_fit, every job on as many workgroups as it has tiles
+  e->gcap = o.group_size > 0 ? std::min(o.group_size, P.coresident) : P.coresident;
+  e->coresident = P.coresident;
   e->opt = o;
   e->table_off = 0;
   e->queue_off = table;
@@ -927,6 +942,8 @@ int stmf_engine_admit(stmf_engine* e, const float* R, const uint8_t* M, int m, i
   if (sidx < 0) return STMF_EBUSY;
   stmf_engine::Slot& S = e->slots[sidx];
   make_layout(m, n, rank, iters, 1, e->opt.acol_p, e->opt.batch_max, S.L);
+  const int G = std::min(e->gcap, S.L.nrt * S.L.nct);
+  if (G > 1) make_layout(m, n, rank, iters, G, e->opt.acol_p, e->opt.batch_max, S.L);
   size_t off = 0;
   if (!arena_alloc(e, S.L.total, off)) return STMF_EBUSY;
   hipStream_t s = (hipStream_t)stream;
@@ -940,6 +957,7 @@ int stmf_engine_admit(stmf_engine* e, const float* R, const uint8_t* M, int m, i
     return st;
   }
   S.used = true;
+  S.G = G;
   S.off = off;
   S.len = S.L.total;
   S.dev = make_dev(S.L, base, e->opt, observed);
@@ -947,24 +965,37 @@ int stmf_engine_admit(stmf_engine* e, const float* R, const uint8_t* M, int m, i
   return STMF_OK;
 }
 
-// The tick's work on stream s: queue reset, then the fit kernel.
-static int tick_work(stmf_engine* e, int nfits, int grid, int max_rows, hipStream_t s) {
-  int st = fill_u32(e->arena + e->queue_off, 1, 0, s);
-  if (st) return st;
-  return launch_fit_kernel((const FitDev*)(e->arena + e->table_off), nfits, 1, grid, max_rows,
-                           (unsigned*)(e->arena + e->queue_off), kernel_sel(e->opt), s);
+// The tick's launches on stream s.  plan: (first, count, grid) per launch;
+// a grid of -1 marks the queue launch of one-workgroup jobs (queue reset by
+// a fill kernel, then the fit kernel over every job).
+static int tick_work(stmf_engine* e, const std::vector<int>& plan, int max_rows, hipStream_t s) {
+  const FitDev* table = (const FitDev*)(e->arena + e->table_off);
+  const int sel = kernel_sel(e->opt);
+  for (size_t q = 0; q < plan.size(); q += 3) {
+    const int first = plan[q], count = plan[q + 1], grid = plan[q + 2];
+    int st;
+    if (grid < 0) {
+      st = fill_u32(e->arena + e->queue_off, 1, 0, s);
+      if (!st)
+        st = launch_fit_kernel(table + first, count, std::min(count, e->coresident), max_rows,
+                               (unsigned*)(e->arena + e->queue_off), sel, false, s);
+    } else {
+      // every group of the launch is resident at once: grid <= coresident
+      st = launch_fit_kernel(table + first, count, grid, max_rows, nullptr, sel, false, s);
+    }
+    if (st) return st;
+  }
+  return STMF_OK;
 }
 
 int stmf_batch_tick(stmf_engine* e, int max_rows, void* stream) {
   if (!e || max_rows < 0) return STMF_EINVAL;
   std::lock_guard<std::mutex> lk(e->mu);
   std::vector<FitDev> table;
+  std::vector<int> gs;
   for (auto& S : e->slots)
-    if (S.used) table.push_back(S.dev);
+    if (S.used) { table.push_back(S.dev); gs.push_back(S.G); }
   if (table.empty()) return STMF_OK;
-  DevProps P;
-  int st = device_props(P);
-  if (st) return st;
   hipStream_t s = (hipStream_t)stream;
   const int nfits = (int)table.size();
   if (table.size() != e->uploaded.size() ||
@@ -974,26 +1005,41 @@ int stmf_batch_tick(stmf_engine* e, int max_rows, void* stream) {
     HIPCHK(hipStreamSynchronize(s));
     e->uploaded = table;
   }
-  const int grid = std::min<int>(nfits, P.coresident);
+  std::vector<int> plan;
+  if (e->gcap == 1) {
+    plan = {0, nfits, -1};
+  } else {
+    int first = 0, grid = 0;
+    for (int f = 0; f < nfits; ++f) {
+      if (grid + gs[f] > e->coresident) {
+        plan.insert(plan.end(), {first, f - first, grid});
+        first = f;
+        grid = 0;
+      }
+      grid += gs[f];
+    }
+    plan.insert(plan.end(), {first, nfits - first, grid});
+  }
+  int st;
   if (!e->use_graph) {
-    st = tick_work(e, nfits, grid, max_rows, s);
+    st = tick_work(e, plan, max_rows, s);
     if (st) return st;
   } else {
     const int sel = kernel_sel(e->opt);
-    if (!e->gexec || e->g_nfits != nfits || e->g_grid != grid || e->g_rows != max_rows ||
-        e->g_sel != sel) {
+    if (!e->gexec || e->g_plan != plan || e->g_rows != max_rows || e->g_sel != sel) {
       if (e->gexec) { HIPCHK(hipGraphExecDestroy(e->gexec)); e->gexec = nullptr; }
       if (e->graph) { HIPCHK(hipGraphDestroy(e->graph)); e->graph = nullptr; }
+      e->g_plan.clear();
       if (!e->cap) HIPCHK(hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking));
       HIPCHK(hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal));
-      st = tick_work(e, nfits, grid, max_rows, e->cap);
+      st = tick_work(e, plan, max_rows, e->cap);
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(e->cap, &g);
       if (st) { if (g) (void)hipGraphDestroy(g); return st; }
       if (ec != hipSuccess) return STMF_EHIP;
       e->graph = g;
       HIPCHK(hipGraphInstantiate(&e->gexec, e->graph, nullptr, nullptr, 0));
-      e->g_nfits = nfits; e->g_grid = grid; e->g_rows = max_rows; e->g_sel = sel;
+      e->g_plan = plan; e->g_rows = max_rows; e->g_sel = sel;
     }
     HIPCHK(hipGraphLaunch(e->gexec, s));
   }

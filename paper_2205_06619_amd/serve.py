@@ -5,18 +5,20 @@ time.  Each tick of the loop:
 
   1. moves the jobs whose arrival time has passed into a FIFO wait queue;
   2. admits waiting jobs, oldest first, while the engine has a free slot and
-     arena room for the job's footprint (``stmf_job_footprint``): R, the mask,
-     the factors and the fit state stay resident in device memory from
-     admission to retirement;
-  3. advances every resident job by at most ``rows_per_tick`` row visits in
-     one launch (``stmf_batch_tick``: one workgroup per job, so jobs that
-     arrived while others were running share the device with them);
+     arena room for the job's footprint (``stmf_engine_job_footprint``): R,
+     the mask, the factors and the fit state stay resident in device memory
+     from admission to retirement;
+  3. advances every resident job by at most ``rows_per_tick`` row visits
+     (``stmf_batch_tick``: each job on a group of workgroups, by default as
+     many as it has 64 x 64 tiles, the jobs side by side over the device, so
+     jobs that arrived while others were running share it with them);
   4. retires the jobs that finished and records their latency (finish time
      minus arrival time).
 
-Every job's result is the one ``stmf_fit`` gives alone with ``group_size=1``
-and the same seed: a job's arithmetic never depends on which other jobs share
-its launches.  ``sequential`` runs the same stream through the plain
+Every job's result is the one ``stmf_fit`` gives alone with the job's group
+size and the same seed (with the default group size, ``stmf_fit``'s own
+result): a job's arithmetic never depends on which other jobs share its
+launches.  ``sequential`` runs the same stream through the plain
 one-fit-at-a-time path for comparison.
 
 The device calls go through a small backend object so that the queueing and
@@ -103,7 +105,7 @@ class EngineBackend:
 
     def footprint(self, job: Job) -> int:
         m, n = job.shape
-        return self.S.stmf_job_footprint(m, n, job.rank, job.iters)
+        return self.S.stmf_engine_job_footprint(self.eng, m, n, job.rank, job.iters)
 
     def admit(self, job: Job) -> Optional[int]:
         return self.S.stmf_engine_admit(self.eng, job.R, job.M, job.rank, job.iters, job.seed,

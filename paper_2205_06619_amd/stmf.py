@@ -28,7 +28,7 @@ EXPORTS = (
     "stmf_fit_batched_workspace", "stmf_fit_batched", "stmf_engine_create", "stmf_engine_destroy",
     "stmf_job_footprint", "stmf_engine_admit", "stmf_batch_tick", "stmf_engine_poll",
     "stmf_engine_retire", "stmf_engine_set_graph", "stmf_dcor_workspace", "stmf_distance_correlation",
-    "stmf_completion_metrics_workspace", "stmf_completion_metrics",
+    "stmf_completion_metrics_workspace", "stmf_completion_metrics", "stmf_engine_job_footprint",
 )
 
 
@@ -79,6 +79,11 @@ LOG_DTYPE = np.dtype([("iter", "<i4"), ("row", "<i4"), ("trials", "<i4"), ("noop
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2205_06619_amd.build")
+    # torch first: its wheel carries its own HIP runtime under the same
+    # soname, and the library must bind to that one.  Loaded the other way
+    # round, a process holds two HIP runtimes, torch's streams and memory are
+    # foreign to the library's, and the library's first device query fails.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P, I, Z = C.c_void_p, C.c_int, C.c_size_t
     sig = {
@@ -99,6 +104,7 @@ def _load():
         "stmf_engine_create": ([P, Z, I, P, P], I),
         "stmf_engine_destroy": ([P], None),
         "stmf_job_footprint": ([I, I, I, I], Z),
+        "stmf_engine_job_footprint": ([P, I, I, I, I], Z),
         "stmf_engine_admit": ([P, P, P, I, I, I, I, C.c_uint64, P, P], I),
         "stmf_batch_tick": ([P, I, P], I),
         "stmf_engine_poll": ([P, I, P, P], I),
@@ -343,6 +349,11 @@ def stmf_job_footprint(m, n, rank, iters) -> int:
     return int(lib.stmf_job_footprint(m, n, rank, iters))
 
 
+def stmf_engine_job_footprint(eng: "Engine", m, n, rank, iters) -> int:
+    """The same for a job of this engine (its options and group size)."""
+    return int(lib.stmf_engine_job_footprint(eng.handle, m, n, rank, iters))
+
+
 class Engine:
     """Handle of a continuous-batching engine (stmf_engine_create) and the
     arena tensor it lives in."""
@@ -389,7 +400,7 @@ def stmf_engine_admit(eng: Engine, R, M, rank, iters, seed=0, stream=None) -> Op
 
 
 def stmf_batch_tick(eng: Engine, max_rows: int, stream=None):
-    """Advance every resident job by at most max_rows row visits (one launch)."""
+    """Advance every resident job by at most max_rows row visits."""
     _chk(lib.stmf_batch_tick(eng.handle, max_rows, _stream(stream)), "stmf_batch_tick")
 
 

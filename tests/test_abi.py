@@ -148,3 +148,18 @@ def test_library_acol_draws_equal_oracle(stmf):
                     s_ += v
                 want = np.float32(s_ / len(obs))
             assert oU0[t, l] == want
+
+
+def test_binding_shares_torchs_hip_runtime(stmf):
+    # imported before torch in a fresh process, the binding still leaves one
+    # HIP runtime mapped: torch's, which the library binds to
+    import subprocess
+    import sys
+    code = ("import paper_2205_06619_amd.stmf\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "libs = {l.split()[-1] for l in maps if 'libamdhip64' in l}\n"
+            "print(len(libs), int(any('torch' in p for p in libs)))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["1", "1"]
