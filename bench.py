@@ -72,7 +72,9 @@ def splitmix64(seed: int, count: int):
 
 
 def batched_compare():
-    """Batched persistent launch vs the plain path, same fits."""
+    """Batched fits (each on as many workgroups as it has tiles, in rounds of
+    launches; then one workgroup per fit in one persistent launch) vs the
+    plain path, same fits."""
     import numpy as np
     import torch
     from paper_2205_06619_amd import stmf, synth
@@ -87,6 +89,15 @@ def batched_compare():
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
     assert statuses == [0] * len(probs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs1, statuses1, _ = stmf.stmf_fit_batched(dev, restarts=b["restarts"], integer_exact=1,
+                                                group_size=1)
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    same_one = statuses1 == statuses and all(
+        bool(torch.equal(Ua, Ub)) and bool(torch.equal(Va, Vb)) and bool(torch.equal(Ta, Tb))
+        for (Ua, Va, Ta), (Ub, Vb, Tb) in zip(outs, outs1))
     t0 = time.perf_counter()
     plain_trials, updates, same = 0, 0, True
     for p, d, (U, V, T) in zip(probs, dev, outs):
@@ -126,6 +137,8 @@ def batched_compare():
         "speedup": t_plain / t_batched,
         "trials": plain_trials,
         "identical": same,
+        "one_workgroup_per_fit": {"batched_s": t_one, "speedup_vs_plain": t_plain / t_one,
+                                  "identical": same_one},
         "autotuned": {"options": tuned, "tune_s": tune_s, "batched_s": t_tuned,
                       "speedup_vs_plain": t_plain / t_tuned, "speedup_vs_default": t_batched / t_tuned,
                       "identical": same_tuned},
@@ -384,6 +397,8 @@ def main():
                     help="run only the large-factorization measurement (one JSON line)")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving comparison (one JSON line)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched comparison (one JSON line)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, serving, selection, quality and large comparisons")
     args = ap.parse_args()
@@ -419,6 +434,9 @@ def main():
         return
     if args.serving_only:
         print(json.dumps(serving_compare()), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps(batched_compare()), flush=True)
         return
 
     def step():

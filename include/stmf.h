@@ -269,12 +269,18 @@ typedef struct {
 size_t stmf_fit_batched_workspace(const stmf_problem* probs, int nprob, int restarts,
                                   const stmf_options* opt);
 
-/* Many independent fits in one persistent launch (one workgroup per fit,
- * longest fits first).  With one restart a problem's fit uses its seed; with
- * several, restart q uses output q of SplitMix64 seeded with the problem's
- * seed.  Synchronous.  info (host, nullable) gets the summed counters.
- * Results equal stmf_fit with the same seed and group_size 1.  Options
- * decision_log, perm, init_mode 2 and max_row_visits are rejected. */
+/* Many independent fits.  Each fit runs on a group of workgroups: the
+ * smaller of opt->group_size (0: no limit but the co-resident workgroup
+ * count) and its tile count (64 x 64 tiles of the working matrix), and its
+ * result equals stmf_fit with that group_size and the same seed (with
+ * group_size 0, stmf_fit's own result).  With group_size 1 the fits run in
+ * one persistent launch whose workgroups take fits from a queue, longest
+ * fits first; otherwise in rounds of launches, the unfinished fits side by
+ * side (longest first), each advanced by at most 64 row visits per round.
+ * With one restart a problem's fit uses its seed; with several, restart q
+ * uses output q of SplitMix64 seeded with the problem's seed.  Synchronous.
+ * info (host, nullable) gets the summed counters.  Options decision_log,
+ * perm, init_mode 2, max_row_visits and strategy 2 are rejected. */
 int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts,
                      const stmf_options* opt, stmf_fit_info* info, void* ws,
                      size_t ws_bytes, void* stream);

@@ -2,9 +2,10 @@
 // (ByRow, random row permutation, TD_A, wide orientation) on device, with no
 // host round trip per trial.
 //
-// A "group" of G workgroups owns one fit (G = 1 for the batched and serving
-// paths, up to the whole chip for one large fit).  The working matrix is cut
-// into 64 x 64 tiles; workgroup g of the group takes tiles g, g + G, ...
+// A "group" of G workgroups owns one fit (G = 1 for batched fits, up to one
+// per tile for a served job or one fit, at most the whole chip).  The working
+// matrix is cut into 64 x 64 tiles; workgroup g of the group takes tiles
+// g, g + G, ...
 //
 // Every trial of a row visit starts from the same state (a rejected F-ULF or
 // F-URF restores U_.k and V_k., Algorithm 3), so the trials of a row are

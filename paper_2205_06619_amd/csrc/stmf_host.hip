@@ -42,6 +42,7 @@ __global__ void output_kernel(const float*, const float*, int, int, int, int, in
                               const int*,
                               float*, float*);
 __global__ void copy_f64_kernel(const double*, double*, int);
+__global__ void fit_done_kernel(const FitDev*, int, int*);
 
 // ---------------------------------------------------------------- randomness
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): a Weyl sequence with step
@@ -674,17 +675,27 @@ struct BatchPlan {
   std::vector<size_t> off;     // workspace offset of each fit
   std::vector<int> prob;       // problem of each fit
   std::vector<uint64_t> seed;  // seed of each fit
-  size_t table, queue, total;
+  bool grouped = false;        // some fit runs on more than one workgroup
+  size_t table, queue, done, total;
 };
 
+// A fit's group: the smaller of group_size (0: the co-resident count) and
+// its tile count, as stmf_fit chooses it.
 static void plan_batched(const stmf_problem* probs, int nprob, int restarts, const stmf_options& o,
-                         BatchPlan& B) {
+                         int coresident, BatchPlan& B) {
+  const int gcap = o.group_size > 0 ? std::min(o.group_size, coresident) : coresident;
   size_t o_ = 0;
   for (int p = 0; p < nprob; ++p) {
     Rng g{probs[p].seed};
     for (int q = 0; q < restarts; ++q) {
       Layout L;
       make_layout(probs[p].m, probs[p].n, probs[p].rank, probs[p].iters, 1, o.acol_p, o.batch_max, L);
+      const int G = std::min(gcap, L.nrt * L.nct);
+      if (G > 1) {
+        make_layout(probs[p].m, probs[p].n, probs[p].rank, probs[p].iters, G, o.acol_p,
+                    o.batch_max, L);
+        B.grouped = true;
+      }
       B.L.push_back(L);
       B.off.push_back(o_);
       B.prob.push_back(p);
@@ -696,7 +707,56 @@ static void plan_batched(const stmf_problem* probs, int nprob, int restarts, con
   o_ += al256(B.L.size() * sizeof(FitDev));
   B.queue = o_;
   o_ += 256;
+  B.done = o_;
+  o_ += al256(B.L.size() * sizeof(int));
   B.total = o_;
+}
+
+// Grouped fits to completion in rounds: each round packs the unfinished fits
+// (longest first) side by side into launches of at most the co-resident
+// workgroups, advances each by at most BATCH_ROUND_ROWS row visits, and
+// drops the fits that finished.  A fit's result does not depend on the
+// rounds (its state is kept between launches).  The device table holds the
+// unfinished fits, rewritten when that set changes.
+static constexpr int BATCH_ROUND_ROWS = 64;
+
+static int run_grouped(std::vector<FitDev> active, int coresident, char* table_dev, int* done_dev,
+                       int sel, hipStream_t s) {
+  std::vector<int> done;
+  bool upload = true;
+  while (!active.empty()) {
+    const int n = (int)active.size();
+    if (upload) {
+      HIPCHK(hipMemcpyAsync(table_dev, active.data(), (size_t)n * sizeof(FitDev),
+                            hipMemcpyHostToDevice, s));
+      upload = false;
+    }
+    const FitDev* t = (const FitDev*)table_dev;
+    int first = 0, grid = 0;
+    for (int f = 0; f <= n; ++f) {
+      if (f == n || grid + active[f].gsize > coresident) {
+        int st = launch_fit_kernel(t + first, f - first, grid, BATCH_ROUND_ROWS, nullptr, sel,
+                                   false, s);
+        if (st) return st;
+        first = f;
+        grid = 0;
+      }
+      if (f < n) grid += active[f].gsize;
+    }
+    hipLaunchKernelGGL(fit_done_kernel, dim3((n + 255) / 256), dim3(256), 0, s, t, n, done_dev);
+    HIPCHK(hipGetLastError());
+    done.assign(n, 0);
+    HIPCHK(hipMemcpyAsync(done.data(), done_dev, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<FitDev> left;
+    for (int f = 0; f < n; ++f)
+      if (!done[f]) left.push_back(active[f]);
+    if ((int)left.size() != n) {
+      active.swap(left);
+      upload = true;
+    }
+  }
+  return STMF_OK;
 }
 
 size_t stmf_fit_batched_workspace(const stmf_problem* probs, int nprob, int restarts,
@@ -707,8 +767,10 @@ size_t stmf_fit_batched_workspace(const stmf_problem* probs, int nprob, int rest
     if (probs[p].m < 1 || probs[p].n < 1 || probs[p].rank < 1 || probs[p].rank > RMAX ||
         probs[p].iters < 0)
       return 0;
+  DevProps P;
+  if (device_props(P)) return 0;
   BatchPlan B;
-  plan_batched(probs, nprob, restarts, o, B);
+  plan_batched(probs, nprob, restarts, o, P.coresident, B);
   return B.total;
 }
 
@@ -728,7 +790,7 @@ int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts, const stmf_op
   st = device_props(P);
   if (st) return st;
   BatchPlan B;
-  plan_batched(probs, nprob, restarts, o, B);
+  plan_batched(probs, nprob, restarts, o, P.coresident, B);
   if (!ws || ((uintptr_t)ws & 255) || ws_bytes < B.total) return STMF_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   char* base = (char*)ws;
@@ -761,7 +823,10 @@ int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts, const stmf_op
     return (double)A.mw * A.nw * A.r > (double)C.mw * C.nw * C.r;
   });
   for (int f : fit_ids) table.push_back(make_dev(B.L[f], base + B.off[f], o, observed[B.prob[f]]));
-  if (!table.empty()) {
+  if (!table.empty() && B.grouped) {
+    st = run_grouped(table, P.coresident, base + B.table, (int*)(base + B.done), kernel_sel(o), s);
+    if (st) return st;
+  } else if (!table.empty()) {
     HIPCHK(hipMemcpyAsync(base + B.table, table.data(), table.size() * sizeof(FitDev),
                           hipMemcpyHostToDevice, s));
     st = fill_u32(base + B.queue, 1, 0, s);

@@ -1,8 +1,9 @@
 """GPU tests of the batched path (stmf_fit_batched): many fits of uneven shape
-and several restarts in one persistent launch.  Batching changes where a fit
-runs, never its arithmetic: every fit equals stmf_fit alone with
-group_size=1 and the restart's seed, bit for bit (integer and real data),
-and on integer data equals the oracle."""
+and several restarts, in one persistent launch (one workgroup per fit) or in
+rounds of launches (fits on groups of workgroups side by side).  Batching
+changes where a fit runs, never its arithmetic: every fit equals stmf_fit
+alone with the fit's group size and the restart's seed, bit for bit
+(integer and real data), and on integer data equals the oracle."""
 import numpy as np
 import pytest
 
@@ -37,22 +38,31 @@ def _restart_seeds(seed, restarts):
     return [int(x) for x in oracle.splitmix64(seed, restarts)]
 
 
+def _group(gcap, m, n):
+    # a fit's workgroups: the group size (0: no limit), at most its 64 x 64
+    # tiles of the working orientation (fewer than the device holds at once)
+    tiles = -(-min(m, n) // 64) * -(-max(m, n) // 64)
+    return tiles if gcap == 0 else max(1, min(gcap, tiles))
+
+
 def _dev(probs, iters):
     return [dict(R=_t(p.R), M=_t(p.M), rank=p.rank, iters=iters, seed=1000 + p.pid) for p in probs]
 
 
+@pytest.mark.parametrize("gcap", [1, 0, 3])
 @pytest.mark.parametrize("integer", [True, False])
-def test_batched_equals_plain_group1(S, integer):
-    print(f"batched vs plain integer={integer}", flush=True)
+def test_batched_equals_plain(S, integer, gcap):
+    print(f"batched vs plain integer={integer} group={gcap}", flush=True)
     probs = _problems(integer, 6, seed=40 + int(integer))
     iters, restarts = 3, 2
     dev = _dev(probs, iters)
-    outs, statuses, info = S.stmf_fit_batched(dev, restarts=restarts)
+    outs, statuses, info = S.stmf_fit_batched(dev, restarts=restarts, group_size=gcap)
     assert statuses == [0] * len(probs)
     total_trials = 0
     for p, d, (U, V, T) in zip(probs, dev, outs):
         for q, sd in enumerate(_restart_seeds(d["seed"], restarts)):
-            g = S.stmf_fit(d["R"], d["M"], p.rank, iters, seed=sd, group_size=1)
+            g = S.stmf_fit(d["R"], d["M"], p.rank, iters, seed=sd,
+                           group_size=_group(gcap, p.m, p.n))
             total_trials += g.info["trials"]
             np.testing.assert_array_equal(U[q].cpu().numpy(), g.U.cpu().numpy())
             np.testing.assert_array_equal(V[q].cpu().numpy(), g.V.cpu().numpy())
@@ -83,7 +93,7 @@ def test_batched_single_restart_uses_problem_seed(S):
     outs, statuses, _ = S.stmf_fit_batched(dev, restarts=1)
     assert statuses == [0, 0, 0]
     for p, d, (U, V, T) in zip(probs, dev, outs):
-        g = S.stmf_fit(d["R"], d["M"], p.rank, 2, seed=d["seed"], group_size=1)
+        g = S.stmf_fit(d["R"], d["M"], p.rank, 2, seed=d["seed"])
         np.testing.assert_array_equal(U[0].cpu().numpy(), g.U.cpu().numpy())
         np.testing.assert_array_equal(T[0].cpu().numpy(), g.traj)
 
@@ -101,7 +111,7 @@ def test_batched_bad_problem_is_isolated(S):
     for idx in (0, 2):
         p, d = probs[idx], dev[idx]
         sd = _restart_seeds(d["seed"], 2)[1]
-        g = S.stmf_fit(d["R"], d["M"], p.rank, 2, seed=sd, group_size=1)
+        g = S.stmf_fit(d["R"], d["M"], p.rank, 2, seed=sd)
         np.testing.assert_array_equal(outs[idx][0][1].cpu().numpy(), g.U.cpu().numpy())
 
 
@@ -113,3 +123,25 @@ def test_batched_rejects_bad_arguments(S):
         S.stmf_fit_batched(dev, restarts=0)
     with pytest.raises(S.StmfError):
         S.stmf_fit_batched(dev, restarts=1, max_row_visits=3)
+
+
+def test_batched_groups_over_several_launches(S):
+    # three fits of 4 x 66 tiles, each on as many workgroups as the device
+    # holds at once (or its tile count): every round runs one launch per fit
+    print("batched groups over launches", flush=True)
+    rng = np.random.default_rng(51)
+    dev = []
+    for q in range(3):
+        R = rng.random((200, 4200)).astype(np.float32)
+        M = (rng.random((200, 4200)) < 0.5).astype(np.uint8)
+        M[:, 0] = 1
+        M[0, :] = 1
+        dev.append(dict(R=_t(R), M=_t(M), rank=2, iters=1, seed=60 + q))
+    outs, statuses, info = S.stmf_fit_batched(dev, restarts=1)
+    assert statuses == [0, 0, 0]
+    for d, (U, V, T) in zip(dev, outs):
+        g = S.stmf_fit(d["R"], d["M"], 2, 1, seed=d["seed"])
+        assert g.info["group_size"] >= 64
+        np.testing.assert_array_equal(U[0].cpu().numpy(), g.U.cpu().numpy())
+        np.testing.assert_array_equal(V[0].cpu().numpy(), g.V.cpu().numpy())
+        np.testing.assert_array_equal(T[0].cpu().numpy(), g.traj)
