@@ -1056,33 +1056,74 @@ DEV void combine_summaries(Grp& gp, Smem& S, int k, bool with_td) {
   __syncthreads();
 }
 
-// Rank sort of the keys S.u.s.key[0 .. n) (n <= SORT_MAX), descending,
-// index ascending on ties, in every workgroup at once: each workgroup ranks
-// its slice (wave w counts the keys before a column among keys w, w + NWAVE,
-// ...; the eight counts are added) and writes out[rank] = column and, if
-// keys_out is given, keys_out[column] = key.
+// Ranking by counting: the rank of key c is the number of keys x with
+// key[x] > key[c], or key[x] == key[c] and x < c (descending, index
+// ascending on ties).  A workgroup ranks up to 64 of its keys at a time:
+// with w = their count rounded up to a power of two, thread t counts for key
+// t % w over the keys x = t / w, t / w + P, ... (P = NTHR / w partitions), so
+// every thread has work however few keys the slice holds; the counts of one
+// key are summed over a wave's lanes (xor shuffles) and then over the waves.
+struct RankChunk {
+  int nk, lg, j, p, P;
+};
+
+DEV RankChunk rank_chunk(const Grp& gp, int cb, int hi) {
+  RankChunk q;
+  q.nk = hi - cb < 64 ? hi - cb : 64;
+  q.lg = q.nk <= 1 ? 0 : 32 - __builtin_clz((unsigned)(q.nk - 1));
+  q.j = gp.lane & ((1 << q.lg) - 1);
+  q.p = gp.tid >> q.lg;
+  q.P = NTHR >> q.lg;
+  return q;
+}
+
+// Counts of the staged keys key_lds[0 .. len) (global indices x0 + x) that
+// precede key kc of index c.
+DEV int rank_count(const double* key_lds, int len, int x0, int p, int P, double kc, int c) {
+  int cnt = 0;
+  int x = p;
+  for (; x + 3 * P < len; x += 4 * P) {
+    const double o0 = key_lds[x], o1 = key_lds[x + P];
+    const double o2 = key_lds[x + 2 * P], o3 = key_lds[x + 3 * P];
+    cnt += (o0 > kc || (o0 == kc && x0 + x < c)) ? 1 : 0;
+    cnt += (o1 > kc || (o1 == kc && x0 + x + P < c)) ? 1 : 0;
+    cnt += (o2 > kc || (o2 == kc && x0 + x + 2 * P < c)) ? 1 : 0;
+    cnt += (o3 > kc || (o3 == kc && x0 + x + 3 * P < c)) ? 1 : 0;
+  }
+  for (; x < len; x += P) {
+    const double o = key_lds[x];
+    cnt += (o > kc || (o == kc && x0 + x < c)) ? 1 : 0;
+  }
+  return cnt;
+}
+
+// Sum of the chunk's counts per key; out[rank] = cb + j for its keys.
+DEV void rank_write(Grp& gp, Smem& S, const RankChunk& q, int cb, int cnt, GA int* out) {
+  int* part = S.u.s.idx;  // NWAVE x 64 counts
+  for (int off = 1 << q.lg; off < 64; off <<= 1) cnt += __shfl_xor(cnt, off);
+  if (gp.lane < (1 << q.lg)) part[gp.wave * 64 + gp.lane] = cnt;
+  __syncthreads();
+  if (gp.tid < q.nk) {
+    int rank = 0;
+    for (int w = 0; w < NWAVE; ++w) rank += part[w * 64 + gp.tid];
+    st_coh(&out[rank], cb + gp.tid);
+  }
+  __syncthreads();
+}
+
+// Rank sort of the keys S.u.s.key[0 .. n) (n <= SORT_MAX), in every
+// workgroup at once: each workgroup ranks its slice and writes out[rank] =
+// column and, if keys_out is given, keys_out[column] = key.
 DEV void rank_slice_lds(Grp& gp, Smem& S, int n, GA int* out, GA double* keys_out) {
   int lo, hi;
   slice(n, gp.g, gp.G, lo, hi);
-  int* part = S.u.s.idx;  // NWAVE x 64 counts
   for (int cb = lo; cb < hi; cb += 64) {
-    const int c = cb + gp.lane;
-    const bool valid = c < hi;
-    const double kc = valid ? S.u.s.key[c] : 0.0;
+    const RankChunk q = rank_chunk(gp, cb, hi);
+    const int c = cb + q.j;
     int cnt = 0;
-    for (int x = gp.wave; x < n; x += NWAVE) {
-      const double o = S.u.s.key[x];
-      cnt += (o > kc || (o == kc && x < c)) ? 1 : 0;
-    }
-    part[gp.wave * 64 + gp.lane] = cnt;
-    __syncthreads();
-    if (gp.wave == 0 && valid) {
-      int rank = 0;
-      for (int w = 0; w < NWAVE; ++w) rank += part[w * 64 + gp.lane];
-      st_coh(&out[rank], c);
-      if (keys_out) st_coh(&keys_out[c], kc);
-    }
-    __syncthreads();
+    if (q.j < q.nk) cnt = rank_count(S.u.s.key, n, 0, q.p, q.P, S.u.s.key[c], c);
+    if (keys_out && gp.tid < q.nk) st_coh(&keys_out[cb + gp.tid], S.u.s.key[cb + gp.tid]);
+    rank_write(gp, S, q, cb, cnt, out);
   }
 }
 
