@@ -223,16 +223,21 @@ static void make_layout(int m, int n, int r, int iters, int G, int acol_p, int b
   L.total = o;
 }
 
-// First batch of a row visit when the caller leaves it to the library: a
-// batch costs a fixed latency (barriers, staging) plus a per-trial part that
-// grows with the tiles each workgroup sweeps, so the first batch shrinks as
-// the workgroups' share of tiles grows: 512 / tiles per workgroup, a power of
-// two, at least 4, at most the largest batch.
+// First batch of a row visit when the caller leaves it to the library.  A
+// batch costs its synchronisation and, for every tile a workgroup sweeps,
+// the tile's staging plus the trials' evaluation; trials after the accepted
+// one are wasted.  The first batch shrinks as each workgroup's share of
+// tiles grows: 512 / tiles per workgroup, a power of two, at least 4.  A
+// group also pays three group barriers per batch, which fewer than 64 trials
+// do not amortise: its first batch is at least 64.  Never above the largest
+// batch.  (On the 2000 x 20000 rank-20 fit, 40 tiles per workgroup, a first
+// batch of 64 rather than 8 took a pass from 5.2-5.4 s to 4.7-4.9 s.)
 static int auto_batch_first(const Layout& L) {
   const int tiles = L.nrt * L.nct;
   const int per = (tiles + L.G - 1) / L.G;
   int t = 4;
   while (t * 2 <= 512 / per && t * 2 <= L.tmax) t *= 2;
+  if (L.G > 1 && t < 64) t = 64;
   return std::min(t, L.tmax);
 }
 
