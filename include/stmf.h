@@ -265,7 +265,10 @@ typedef struct {
   int pad;
 } stmf_problem;
 
-/* Workspace bytes of stmf_fit_batched. */
+/* Workspace bytes of stmf_fit_batched with these problems and options on the
+ * current device (each fit's group size, and with it its layout, depends on
+ * group_size and on how many fit-kernel workgroups the device holds at
+ * once); 0 for invalid arguments or when the device cannot be queried. */
 size_t stmf_fit_batched_workspace(const stmf_problem* probs, int nprob, int restarts,
                                   const stmf_options* opt);
 
