@@ -145,3 +145,26 @@ def test_batched_groups_over_several_launches(S):
         np.testing.assert_array_equal(U[0].cpu().numpy(), g.U.cpu().numpy())
         np.testing.assert_array_equal(V[0].cpu().numpy(), g.V.cpu().numpy())
         np.testing.assert_array_equal(T[0].cpu().numpy(), g.traj)
+
+
+@pytest.mark.parametrize("gcap", [1, 0])
+def test_batched_zero_passes_and_tiny_problems(S, gcap):
+    # a fit of zero passes (its initial error only) and 1 x n / m x 1
+    # problems beside ordinary ones, through the queue launch and the rounds
+    print(f"batched edge problems group={gcap}", flush=True)
+    probs = _problems(True, 3, seed=52)
+    dev = _dev(probs, 2)
+    dev[0]["iters"] = 0
+    for shape, seed in (((1, 70), 53), ((90, 1), 54)):
+        R, M = synth.int_planted(shape[0], shape[1], 1, 0.0, seed=seed)
+        dev.append(dict(R=_t(R), M=_t(M), rank=1, iters=2, seed=seed))
+    outs, statuses, _ = S.stmf_fit_batched(dev, restarts=2, group_size=gcap)
+    assert statuses == [0] * len(dev)
+    for d, (U, V, T) in zip(dev, outs):
+        m, n = d["R"].shape
+        for q, sd in enumerate(_restart_seeds(d["seed"], 2)):
+            g = S.stmf_fit(d["R"], d["M"], d["rank"], d["iters"], seed=sd,
+                           group_size=_group(gcap, m, n))
+            np.testing.assert_array_equal(U[q].cpu().numpy(), g.U.cpu().numpy())
+            np.testing.assert_array_equal(V[q].cpu().numpy(), g.V.cpu().numpy())
+            np.testing.assert_array_equal(T[q].cpu().numpy(), g.traj)

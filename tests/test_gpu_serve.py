@@ -261,3 +261,22 @@ def test_engine_groups_over_several_launches(S):
         ref = _alone(S, j, G)
         assert ref.info["group_size"] == G
         _same(res[s], ref)
+
+
+@pytest.mark.parametrize("gcap", [1, 0])
+def test_engine_zero_passes_and_tiny_jobs(S, gcap):
+    print(f"engine edge jobs group={gcap}", flush=True)
+    jobs = _wide_jobs(68, 2)
+    jobs[0]["iters"] = 0
+    for shape, seed in (((1, 70), 55), ((90, 1), 56)):
+        R, M = synth.int_planted(shape[0], shape[1], 1, 0.0, seed=seed)
+        jobs.append(dict(R=_t(R), M=_t(M), rank=1, iters=2, seed=seed))
+    eng = S.stmf_engine_create(256 << 20, 8, group_size=gcap)
+    try:
+        slots = [S.stmf_engine_admit(eng, j["R"], j["M"], j["rank"], j["iters"], j["seed"]) for j in jobs]
+        assert None not in slots
+        res = _drain(S, eng, slots, rows=3)
+    finally:
+        S.stmf_engine_destroy(eng)
+    for j, s in zip(jobs, slots):
+        _same(res[s], _alone(S, j, _group(gcap, *j["R"].shape)))
