@@ -1198,8 +1198,42 @@ DEV void sort_by_rank(Grp& gp, Smem& S, const GA double* keys, GA int* out) {
   }
 }
 
+// The same order with every thread counting (the ranking of up to 4096
+// columns above) and four staged loads in flight per thread.  Compiled only
+// into the kernel for matrices wider than SORT_MAX, so that the register
+// allocation of the others stays as it is.
+DEV void sort_by_rank_all(Grp& gp, Smem& S, const GA double* keys, GA int* out) {
+  const FitDev& d = *gp.d;
+  const int n = d.n;
+  int lo, hi;
+  slice(n, gp.g, gp.G, lo, hi);
+  for (int cb = lo; cb < hi; cb += 64) {
+    const RankChunk q = rank_chunk(gp, cb, hi);
+    const int c = cb + q.j;
+    const double kc = q.j < q.nk ? ld_atomic(&keys[c]) : 0.0;
+    int cnt = 0;
+    for (int x0 = 0; x0 < n; x0 += SORT_MAX) {
+      const int len = n - x0 < SORT_MAX ? n - x0 : SORT_MAX;
+      __syncthreads();
+      for (int x = gp.tid; x < len; x += 4 * NTHR) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          v[u] = x + u * NTHR < len ? ld_atomic(&keys[x0 + x + u * NTHR]) : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (x + u * NTHR < len) S.u.s.key[x + u * NTHR] = v[u];
+      }
+      __syncthreads();
+      if (q.j < q.nk) cnt += rank_count(S.u.s.key, len, x0, q.p, q.P, kc, c);
+    }
+    rank_write(gp, S, q, cb, cnt, out);
+  }
+}
+
 // Whole refresh: tile pass, barrier, summaries (and, for matrices up to
 // SORT_MAX columns, the column order), barrier.
+template <bool WIDE = false>
 DEV bool refresh(Grp& gp, Smem& S, int k, bool has_acc, Trial acc, int par, int slot, int i, bool full,
                  int cb) {
   const FitDev& d = *gp.d;
@@ -1210,7 +1244,10 @@ DEV bool refresh(Grp& gp, Smem& S, int k, bool has_acc, Trial acc, int par, int 
   if (full && small) sort_small(gp, S);
   if (!group_sync(gp, S)) return false;
   if (full && !small) {
-    sort_by_rank(gp, S, d.td, d.order);
+    if (WIDE)
+      sort_by_rank_all(gp, S, d.td, d.order);
+    else
+      sort_by_rank(gp, S, d.td, d.order);
     if (!group_sync(gp, S)) return false;
   }
   return true;
@@ -1617,6 +1654,7 @@ DEV void clear_trial_vectors(Grp& gp) {
 // Initial state: residual summaries of every component, counts, td_col,
 // the order, and the error of the current state through the same pass as
 // every trial (a null trial).
+template <bool WIDE = false>
 DEV bool fit_init(Grp& gp, Smem& S) {
   const FitDev& d = *gp.d;
   clear_trial_vectors(gp);
@@ -1629,7 +1667,7 @@ DEV bool fit_init(Grp& gp, Smem& S) {
   }
   if (!group_sync(gp, S)) return false;
   for (int k = 0; k < d.r; ++k)
-    if (!refresh(gp, S, k, false, Trial{}, 0, 0, 0, k == d.r - 1, 0)) return false;
+    if (!refresh<WIDE>(gp, S, k, false, Trial{}, 0, 0, 0, k == d.r - 1, 0)) return false;
   if (gp.tid == 0) {
     Trial tr; tr.j = 0; tr.k = 0; tr.op = OP_NULL; tr.val = 0.0f;
     S.trials[0] = tr; S.nt = 1;
@@ -2132,8 +2170,9 @@ DEV bool elem_row_visit(Grp& gp, Smem& S, int i, int it, int& cb, int& par, doub
 // Run the fit from its saved state for at most max_rows row visits (0: no
 // limit).  All workgroups of the group execute the same control flow.
 // MODE 0 is FastSTMF's TD_A alone, compiled without the code of the other
-// selections; MODE 1 runs any ByRow selection or ByElement; MODE 2 ByMatrix
-// (batches of trials of different rows).  A ByRow row visit (Algorithm 3; the selections of
+// selections (MODE 3: the same for matrices wider than SORT_MAX, with the
+// all-thread ranking of the column order); MODE 1 runs any ByRow selection
+// or ByElement; MODE 2 ByMatrix (batches of trials of different rows).  A ByRow row visit (Algorithm 3; the selections of
 // Sec. 3.2.1) runs batches of trials until the first accepted update (SEQ:
 // every trial, then the best), its refresh and the visit's record; it stays
 // written out here rather than in a function of its own, which measured
@@ -2141,12 +2180,12 @@ DEV bool elem_row_visit(Grp& gp, Smem& S, int i, int it, int& cb, int& par, doub
 template <int MODE>
 DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
   const FitDev& d = *gp.d;
-  const int sel = MODE == 0 ? (int)SEL_TD_A : MODE == 2 ? (int)SEL_MATRIX : d.sel;
+  const int sel = MODE == 0 || MODE == 3 ? (int)SEL_TD_A : MODE == 2 ? (int)SEL_MATRIX : d.sel;
   GA FitCtl* ctl = gp.ctl;
   if (gp.tid == 0) { S.prev_nt = 0; S.status = 0; }
   __syncthreads();
   if (ld_atomic(&ctl->phase) == 0) {
-    if (!fit_init(gp, S)) return;
+    if (!fit_init<MODE == 3>(gp, S)) return;
   } else {
     // a resumed launch: the trial vectors of both parities must start clean
     clear_trial_vectors(gp);
@@ -2244,7 +2283,7 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
           acc_j = tr.j; acc_k = tr.k; acc_op = tr.op;
           e_cur = ld_atomic(&ctl->e_new);
           // the argmax counts and the column order serve TD_A and TD_B only
-          if (!refresh(gp, S, tr.k, true, tr, par, dec, i, sel == SEL_TD_A || sel == SEL_TD_B,
+          if (!refresh<MODE == 3>(gp, S, tr.k, true, tr, par, dec, i, sel == SEL_TD_A || sel == SEL_TD_B,
                        cb ^ 1))
             return;
           cb ^= 1;
@@ -2365,6 +2404,14 @@ __global__ void __launch_bounds__(NTHR) fit_kernel_sel(const FitDev* __restrict_
                                                        int max_rows,
                                                        unsigned* __restrict__ queue) {
   fit_kernel_body<1>(fits, nfits, max_rows, queue);
+}
+
+// FastSTMF (TD_A) fits on matrices wider than SORT_MAX columns (the same
+// fit; the column order ranked with every thread counting).
+__global__ void __launch_bounds__(NTHR) fit_kernel_wide(const FitDev* __restrict__ fits, int nfits,
+                                                        int max_rows,
+                                                        unsigned* __restrict__ queue) {
+  fit_kernel_body<3>(fits, nfits, max_rows, queue);
 }
 
 // ByMatrix fits.

@@ -18,6 +18,7 @@ namespace stmf {
 __global__ void fit_kernel(const FitDev* fits, int nfits, int max_rows, unsigned* queue);
 __global__ void fit_kernel_sel(const FitDev* fits, int nfits, int max_rows, unsigned* queue);
 __global__ void fit_kernel_matrix(const FitDev* fits, int nfits, int max_rows, unsigned* queue);
+__global__ void fit_kernel_wide(const FitDev* fits, int nfits, int max_rows, unsigned* queue);
 size_t fit_smem_bytes();
 size_t masked_error_ws(int m, int n);
 hipError_t launch_maxplus(const float*, const float*, int, int, int, float*, int32_t*, hipStream_t);
@@ -102,14 +103,18 @@ static int device_props(DevProps& out) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
     HIPCHK(hipFuncSetAttribute((const void*)fit_kernel_matrix,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    HIPCHK(hipFuncSetAttribute((const void*)fit_kernel_wide,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
     // the fit kernels share the LDS layout; the group size must suit all
-    int per = 0, per_sel = 0, per_mat = 0;
+    int per = 0, per_sel = 0, per_mat = 0, per_wide = 0;
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)fit_kernel, NTHR, smem));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_sel, (const void*)fit_kernel_sel, NTHR,
                                                         smem));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_mat, (const void*)fit_kernel_matrix,
                                                         NTHR, smem));
-    p.coresident = std::min(std::min(per, per_sel), per_mat) * p.cus;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_wide, (const void*)fit_kernel_wide,
+                                                        NTHR, smem));
+    p.coresident = std::min(std::min(per, per_sel), std::min(per_mat, per_wide)) * p.cus;
     p.ok = true;
   }
   out = p;
@@ -449,15 +454,16 @@ static int launch_output(const Layout& L, char* base, float* U_out, float* V_out
 }
 
 // sel: the ByRow selection of every fit of the launch (TD_A runs the kernel
-// compiled for it alone).  queue: batched launches (one workgroup per fit,
+// compiled for it alone, in its own build for launches with a fit wider than
+// SORT_MAX columns: `wide`).  queue: batched launches (one workgroup per fit,
 // fits taken from the queue); null: the fits own consecutive ranges of
 // gsize workgroups.  A cooperative launch has the runtime check that the
 // whole grid is resident at once; other launches with group barriers keep
 // the grid within the co-resident count.
 static int launch_fit_kernel(const FitDev* dev_fits, int nfits, int grid, int max_rows,
-                             unsigned* queue, int sel, bool cooperative, hipStream_t s) {
+                             unsigned* queue, int sel, bool wide, bool cooperative, hipStream_t s) {
   const size_t smem = fit_smem_bytes();
-  const void* k = sel == SEL_TD_A     ? (const void*)fit_kernel
+  const void* k = sel == SEL_TD_A     ? (wide ? (const void*)fit_kernel_wide : (const void*)fit_kernel)
                   : sel == SEL_MATRIX ? (const void*)fit_kernel_matrix
                                       : (const void*)fit_kernel_sel;
   void* args[] = {(void*)&dev_fits, (void*)&nfits, (void*)&max_rows, (void*)&queue};
@@ -649,7 +655,7 @@ int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters
   HIPCHK(hipEventCreate(&ev1));
   HIPCHK(hipEventRecord(ev0, s));
   st = launch_fit_kernel((const FitDev*)(base + L.dev), 1, G, o.max_row_visits, nullptr,
-                         kernel_sel(o), G > 1, s);
+                         kernel_sel(o), L.nw > SORT_MAX, G > 1, s);
   if (st) { (void)hipEventDestroy(ev0); (void)hipEventDestroy(ev1); return st; }
   HIPCHK(hipEventRecord(ev1, s));
   FitCtl c;
@@ -717,6 +723,13 @@ static void plan_batched(const stmf_problem* probs, int nprob, int restarts, con
   B.total = o_;
 }
 
+// Whether a launch over these fits takes the wide build of the TD_A kernel.
+static bool any_wide(const FitDev* fits, int n) {
+  for (int f = 0; f < n; ++f)
+    if (fits[f].n > SORT_MAX) return true;
+  return false;
+}
+
 // Grouped fits to completion in rounds: each round packs the unfinished fits
 // (longest first) side by side into launches of at most the co-resident
 // workgroups, advances each by at most BATCH_ROUND_ROWS row visits, and
@@ -741,7 +754,7 @@ static int run_grouped(std::vector<FitDev> active, int coresident, char* table_d
     for (int f = 0; f <= n; ++f) {
       if (f == n || grid + active[f].gsize > coresident) {
         int st = launch_fit_kernel(t + first, f - first, grid, BATCH_ROUND_ROWS, nullptr, sel,
-                                   false, s);
+                                   any_wide(active.data() + first, f - first), false, s);
         if (st) return st;
         first = f;
         grid = 0;
@@ -838,7 +851,8 @@ int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts, const stmf_op
     if (st) return st;
     const int grid = std::min<int>((int)table.size(), P.coresident);
     st = launch_fit_kernel((const FitDev*)(base + B.table), (int)table.size(), grid, 0,
-                           (unsigned*)(base + B.queue), kernel_sel(o), false, s);
+                           (unsigned*)(base + B.queue), kernel_sel(o),
+                           any_wide(table.data(), (int)table.size()), false, s);
     if (st) return st;
   }
   HIPCHK(hipStreamSynchronize(s));  // host staging vectors go out of scope after this
@@ -910,7 +924,7 @@ struct stmf_engine {
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  std::vector<int> g_plan;  // the captured plan (first, count, grid per launch)
+  std::vector<int> g_plan;  // the captured plan (first, count, grid, wide per launch)
   int g_rows = -1, g_sel = -1;
   ~stmf_engine() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -1035,23 +1049,24 @@ int stmf_engine_admit(stmf_engine* e, const float* R, const uint8_t* M, int m, i
   return STMF_OK;
 }
 
-// The tick's launches on stream s.  plan: (first, count, grid) per launch;
-// a grid of -1 marks the queue launch of one-workgroup jobs (queue reset by
-// a fill kernel, then the fit kernel over every job).
+// The tick's launches on stream s.  plan: (first, count, grid, wide) per
+// launch; a grid of -1 marks the queue launch of one-workgroup jobs (queue
+// reset by a fill kernel, then the fit kernel over every job).
 static int tick_work(stmf_engine* e, const std::vector<int>& plan, int max_rows, hipStream_t s) {
   const FitDev* table = (const FitDev*)(e->arena + e->table_off);
   const int sel = kernel_sel(e->opt);
-  for (size_t q = 0; q < plan.size(); q += 3) {
+  for (size_t q = 0; q < plan.size(); q += 4) {
     const int first = plan[q], count = plan[q + 1], grid = plan[q + 2];
+    const bool wide = plan[q + 3] != 0;
     int st;
     if (grid < 0) {
       st = fill_u32(e->arena + e->queue_off, 1, 0, s);
       if (!st)
         st = launch_fit_kernel(table + first, count, std::min(count, e->coresident), max_rows,
-                               (unsigned*)(e->arena + e->queue_off), sel, false, s);
+                               (unsigned*)(e->arena + e->queue_off), sel, wide, false, s);
     } else {
       // every group of the launch is resident at once: grid <= coresident
-      st = launch_fit_kernel(table + first, count, grid, max_rows, nullptr, sel, false, s);
+      st = launch_fit_kernel(table + first, count, grid, max_rows, nullptr, sel, wide, false, s);
     }
     if (st) return st;
   }
@@ -1077,18 +1092,18 @@ int stmf_batch_tick(stmf_engine* e, int max_rows, void* stream) {
   }
   std::vector<int> plan;
   if (e->gcap == 1) {
-    plan = {0, nfits, -1};
+    plan = {0, nfits, -1, any_wide(table.data(), nfits) ? 1 : 0};
   } else {
     int first = 0, grid = 0;
-    for (int f = 0; f < nfits; ++f) {
-      if (grid + gs[f] > e->coresident) {
-        plan.insert(plan.end(), {first, f - first, grid});
+    for (int f = 0; f <= nfits; ++f) {
+      if (f == nfits || grid + gs[f] > e->coresident) {
+        plan.insert(plan.end(),
+                    {first, f - first, grid, any_wide(table.data() + first, f - first) ? 1 : 0});
         first = f;
         grid = 0;
       }
-      grid += gs[f];
+      if (f < nfits) grid += gs[f];
     }
-    plan.insert(plan.end(), {first, nfits - first, grid});
   }
   int st;
   if (!e->use_graph) {
