@@ -79,17 +79,23 @@ class Cache:
 
 
 def tune_fit(R, M, rank: int, passes: int = 2, seed: int = 0, cache: Optional[Cache] = None,
-             candidates: Sequence[Tuple[int, int]] = CANDIDATES, **opts) -> dict:
+             candidates: Sequence[Tuple[int, int]] = CANDIDATES, visits: Optional[int] = None,
+             **opts) -> dict:
     """Launch shape for one fit of this shape (device tensors R, M): each
-    candidate runs the first `passes` passes' worth of row visits; the kernel
-    time decides.  Returns {batch_first, batch_max} (cached per bucket)."""
+    candidate runs the first `passes` passes' worth of row visits (or the
+    first `visits` row visits: a short prefix keeps tuning a large matrix
+    cheap); the kernel time decides.  Returns {batch_first, batch_max}
+    (cached per bucket)."""
     from . import stmf
     m, n = R.shape
     key = "fit:" + bucket(m, n, rank)
     if cache is not None and cache.get(key):
         c = cache.get(key)
         return {"batch_first": c["batch_first"], "batch_max": c["batch_max"]}
-    visits = passes * min(m, n)
+    if visits is None:
+        visits = passes * min(m, n)
+    if visits < 1:
+        raise ValueError("the tuning prefix needs at least one row visit")
 
     def timer(bf, bm):
         g = stmf.stmf_fit(R, M, rank, passes, seed=seed, batch_first=bf, batch_max=bm,

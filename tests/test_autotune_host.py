@@ -39,3 +39,34 @@ def test_candidates_are_valid_options():
     for bf, bm in autotune.CANDIDATES:
         assert 0 <= bf and 0 <= bm <= 1024
         assert bm == 0 or bf <= bm
+
+
+class _Info:
+    def __init__(self, ms):
+        self.info = {"kernel_ms": ms}
+
+
+class _Shape:
+    shape = (300, 4000)
+
+
+def test_tune_fit_prefix_and_cache(tmp_path, monkeypatch):
+    # the fit itself is replaced by a timer of the candidate; what is checked
+    # is the prefix each candidate runs, the choice and the cache entry
+    from paper_2205_06619_amd import stmf
+    seen = []
+
+    def fake_fit(R, M, rank, passes, seed=0, batch_first=0, batch_max=0, max_row_visits=0, **kw):
+        seen.append((batch_first, batch_max, max_row_visits))
+        return _Info(10.0 - (batch_first == 64 and batch_max == 0))
+
+    monkeypatch.setattr(stmf, "stmf_fit", fake_fit)
+    cache = autotune.Cache(str(tmp_path / "t.json"))
+    got = autotune.tune_fit(_Shape(), None, 20, visits=40, cache=cache)
+    assert got == {"batch_first": 64, "batch_max": 0}
+    assert [v for _, _, v in seen] == [40] * len(autotune.CANDIDATES)
+    assert cache.get("fit:512x4096r32")["batch_first"] == 64
+    seen.clear()
+    assert autotune.tune_fit(_Shape(), None, 20, cache=cache) == got and not seen
+    autotune.tune_fit(_Shape(), None, 20, passes=2)
+    assert {v for _, _, v in seen} == {600}
