@@ -53,6 +53,18 @@ class Stats(C.Structure):
     ]
 
 
+class LockReport(C.Structure):
+    _fields_ = [
+        ("row_visits", C.c_int64), ("trials", C.c_int64), ("agree", C.c_int64),
+        ("flips", C.c_int64), ("flips_f32_accepts", C.c_int64), ("mismatches", C.c_int64),
+        ("order_pairs", C.c_int64),
+        ("order_flips", C.c_int64), ("order_mismatches", C.c_int64), ("k_checked", C.c_int64),
+        ("k_flips", C.c_int64), ("k_mismatches", C.c_int64), ("iters_done", C.c_int32),
+        ("first_bad_iter", C.c_int32), ("first_bad_row", C.c_int32), ("pad", C.c_int32),
+        ("max_rel_traj", C.c_double), ("max_flip_margin", C.c_double),
+    ]
+
+
 LOG_DTYPE = np.dtype([("iter", "<i4"), ("row", "<i4"), ("trials", "<i4"),
                       ("noops", "<i4"), ("j", "<i4"), ("k", "<i4"),
                       ("op", "<i4"), ("pad", "<i4"), ("e", "<f8")])
@@ -85,6 +97,11 @@ def lib():
             f.argtypes = [P, P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, P, P, P, P, P,
                           C.c_int, P, P, C.c_int]
             f.restype = C.c_int
+        L.oracle_lockstep.argtypes = [P, P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, P,
+                                      C.c_double, P, P, P, C.c_int, P, P]
+        L.oracle_lockstep.restype = C.c_int
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_get_threads.restype = C.c_int
         L.oracle_splitmix64.argtypes = [C.c_uint64, C.c_int, P]
         L.oracle_draw_init.argtypes = [P, P, C.c_int, C.c_int, C.c_int, C.c_uint64, P, P, P]
         L.oracle_draw_init.restype = C.c_int
@@ -182,8 +199,10 @@ def make_opts(init_mode=0, init_lo=0.0, init_hi=100.0, acol_p=5, U0=None, perm=N
     return o, keep
 
 
-def fit(R, M, rank, iters, seed=0, prec="f32", log_cap=None, row_limit=0, **opts) -> FitResult:
-    """Algorithm 3 on the oracle.  prec='f64' is the FP64 oracle."""
+def fit(R, M, rank, iters, seed=0, prec="f32", log_cap=None, row_limit=0, no_traj=False,
+        **opts) -> FitResult:
+    """Algorithm 3 on the oracle.  prec='f64' is the FP64 oracle.  no_traj:
+    pass no trajectory buffer (the returned traj stays zero)."""
     R = _c(R, np.float32); M = _c(M, np.uint8)
     m, n = R.shape
     o, keep = make_opts(**opts)
@@ -196,10 +215,47 @@ def fit(R, M, rank, iters, seed=0, prec="f32", log_cap=None, row_limit=0, **opts
     st = Stats()
     fn = getattr(lib(), f"oracle_fit_{prec}")
     s = fn(_p(R), _p(M), m, n, rank, iters, C.c_uint64(seed), C.byref(o), _p(U), _p(V),
-           _p(traj), _p(log), cap, C.byref(nlog), C.byref(st), row_limit)
+           None if no_traj else _p(traj), _p(log), cap, C.byref(nlog), C.byref(st), row_limit)
     del keep
     stats = {f: getattr(st, f) for f, _ in Stats._fields_}
     return FitResult(s, U, V, traj, log[: min(nlog.value, cap)], stats)
+
+
+@dataclass
+class LockResult:
+    status: int
+    traj_f32: np.ndarray
+    traj_f64: np.ndarray
+    log: np.ndarray
+    report: dict
+
+
+def lockstep(R, M, rank, iters, seed=0, band=1e-6, log_cap=None, **opts) -> LockResult:
+    """The FP32-value fit (FastSTMF: ByRow, TD_A) with every decision replayed
+    in FP64 from the same state (see oracle_lockstep in stmf_oracle.cpp)."""
+    R = _c(R, np.float32); M = _c(M, np.uint8)
+    m, n = R.shape
+    o, keep = make_opts(**opts)
+    tf = np.zeros(iters + 1, np.float64); td = np.zeros(iters + 1, np.float64)
+    mw = min(m, n)
+    cap = log_cap if log_cap is not None else mw * max(iters, 1)
+    log = np.zeros(max(cap, 1), LOG_DTYPE)
+    nlog = C.c_int(0)
+    rep = LockReport()
+    s = lib().oracle_lockstep(_p(R), _p(M), m, n, rank, iters, C.c_uint64(seed), C.byref(o),
+                              band, _p(tf), _p(td), _p(log), cap, C.byref(nlog), C.byref(rep))
+    del keep
+    report = {f: getattr(rep, f) for f, _ in LockReport._fields_ if f != "pad"}
+    return LockResult(s, tf, td, log[: min(nlog.value, cap)], report)
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's row loops (OpenMP); results do not depend on it."""
+    lib().oracle_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().oracle_get_threads())
 
 
 def splitmix64(seed: int, count: int) -> np.ndarray:

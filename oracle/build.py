@@ -8,7 +8,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "stmf_oracle.cpp")
 OUT = os.path.join(_HERE, "liboracle.so")
 FLAGS = ["-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
-         "-fno-fast-math", "-msse2", "-mfpmath=sse", "-Wall"]
+         "-fno-fast-math", "-msse2", "-mfpmath=sse", "-fopenmp", "-Wall"]
 
 
 def build(force: bool = True) -> str:

@@ -28,8 +28,12 @@
 // oracle": all value arithmetic in double on exactly promoted FP32 inputs.
 // T = float takes every value operation as one correctly rounded FP32
 // operation (the precision in which the GPU library decides accept/reject,
-// argmax and ordering), with error sums widened to double.  Sums of |d| run
-// in plain row-major order.  Built with -ffp-contract=off and no fast-math.
+// argmax and ordering), with error sums widened to double.  The b-norm is
+// summed row by row: each row's |d| in column order, then the row sums in row
+// order; td_col(j) adds its rows in row order.  The row loops of the
+// residuals and of the evaluation may run on several threads (OpenMP): every
+// sum keeps that order, so the results do not depend on the thread count.
+// Built with -ffp-contract=off and no fast-math.
 //
 // Readings of points the paper leaves open (each is listed in the design
 // notes of the repository):
@@ -91,6 +95,7 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#include <omp.h>
 
 namespace {
 
@@ -116,6 +121,9 @@ uint64_t draw_below(SplitMix64& g, uint64_t bound) {
   }
 }
 
+// Loops over fewer cells than this stay on the calling thread.
+constexpr int64_t PAR_CELLS = 16384;
+
 // ---------------------------------------------------------------- primitives
 // (U (x) V)_ij = max_l U_il + V_lj; A gets the lowest l reaching the maximum.
 template <class T>
@@ -138,6 +146,7 @@ void maxplus(const T* U, const T* V, int m, int r, int n, T* P, int32_t* A) {
 template <class T>
 void col_res(const T* R, const uint8_t* M, int m, int n, int r, int k,
              const T* U, T* V) {
+#pragma omp parallel for schedule(static) if ((int64_t)m * n >= PAR_CELLS)
   for (int j = 0; j < n; ++j) {
     bool seen = false;
     T best = 0;
@@ -155,6 +164,7 @@ void col_res(const T* R, const uint8_t* M, int m, int n, int r, int k,
 template <class T>
 void row_res(const T* R, const uint8_t* M, int m, int n, int r, int k,
              const T* V, T* U) {
+#pragma omp parallel for schedule(static) if ((int64_t)m * n >= PAR_CELLS)
   for (int t = 0; t < m; ++t) {
     bool seen = false;
     T best = 0;
@@ -167,17 +177,24 @@ void row_res(const T* R, const uint8_t* M, int m, int n, int r, int k,
   }
 }
 
-// b-norm of R - U (x) V over the observed cells, summed in double in row-major
-// order.  The per-cell difference is taken in T and then widened.  td_col[j]
-// (nullable) gets the sum over the observed rows of column j; A (nullable) the
-// argmax of every cell (observed or not).
+// b-norm of R - U (x) V over the observed cells (Sec. 3.6), in double: each
+// row's |d| summed in column order, then the row sums in row order.  The
+// per-cell difference is taken in T and then widened.  td_col[j] (nullable)
+// gets the sum over the observed rows of column j, in row order; A (nullable)
+// the argmax of every cell (observed or not).
 template <class T>
 double masked_error(const T* R, const uint8_t* M, const T* U, const T* V,
                     int m, int n, int r, double* td_col, int32_t* A) {
-  double e = 0.0;
-  if (td_col)
-    for (int j = 0; j < n; ++j) td_col[j] = 0.0;
-  for (int t = 0; t < m; ++t)
+  // |d| of every cell (0 where unobserved) and the row sums
+  static thread_local std::vector<double> ad, rows;
+  if (td_col && ad.size() < (size_t)m * n) ad.resize((size_t)m * n);
+  if (rows.size() < (size_t)m) rows.resize((size_t)m);
+  const bool par = (int64_t)m * n >= PAR_CELLS;
+  double* adp = td_col ? ad.data() : nullptr;
+  double* rowp = rows.data();
+#pragma omp parallel for schedule(static) if (par)
+  for (int t = 0; t < m; ++t) {
+    double rs = 0.0;
     for (int j = 0; j < n; ++j) {
       T best = U[(size_t)t * r + 0] + V[j];
       int arg = 0;
@@ -186,12 +203,26 @@ double masked_error(const T* R, const uint8_t* M, const T* U, const T* V,
         if (x > best) { best = x; arg = l; }
       }
       if (A) A[(size_t)t * n + j] = arg;
-      if (!M[(size_t)t * n + j]) continue;
-      T d = R[(size_t)t * n + j] - best;
-      double ad = std::fabs((double)d);
-      e += ad;
-      if (td_col) td_col[j] += ad;
+      double a = 0.0;
+      if (M[(size_t)t * n + j]) {
+        T d = R[(size_t)t * n + j] - best;
+        a = std::fabs((double)d);
+      }
+      if (adp) adp[(size_t)t * n + j] = a;
+      rs += a;
     }
+    rowp[t] = rs;
+  }
+  double e = 0.0;
+  for (int t = 0; t < m; ++t) e += rowp[t];
+  if (td_col) {
+#pragma omp parallel for schedule(static) if (par)
+    for (int j = 0; j < n; ++j) {
+      double c = 0.0;
+      for (int t = 0; t < m; ++t) c += adp[(size_t)t * n + j];
+      td_col[j] = c;
+    }
+  }
   return e;
 }
 
@@ -465,8 +496,8 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
   const uint8_t* M = w.M.data();
   for (int k = 0; k < r; ++k) col_res(R.data(), M, m, n, r, k, U.data(), V.data());
 
-  std::vector<double> td((size_t)n), td_try((size_t)n);
-  std::vector<int32_t> A((size_t)m * n), A_try((size_t)m * n);
+  std::vector<double> td((size_t)n);
+  std::vector<int32_t> A((size_t)m * n);
   std::vector<T> Ubak((size_t)m), Vbak((size_t)n);
   std::vector<char> closed((size_t)r, 0);
   int64_t omega = 0;
@@ -499,6 +530,7 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
     std::vector<double> tdr((size_t)m), tdc((size_t)n), tij((size_t)m * n), key((size_t)m * n);
     std::vector<int32_t> fk((size_t)m * n);
     std::vector<int64_t> order;
+    double e_prev_it = e;
     for (int it = 1; it <= iters && !stop; ++it) {
       if (rows_left == 0) break;
       if (rows_left > 0) --rows_left;
@@ -539,16 +571,15 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
         }
         const double e2 = op == 0
             ? f_ulf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k,
-                    Ubak.data(), Vbak.data(), td_try.data(), A_try.data())
+                    Ubak.data(), Vbak.data(), nullptr, nullptr)
             : f_urf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k,
-                    Ubak.data(), Vbak.data(), td_try.data(), A_try.data());
+                    Ubak.data(), Vbak.data(), nullptr, nullptr);
         rec.trials++;
         S.trials++;
         S.evaluated_cells += omega;
         if (e2 < e) {
           e = e2;
-          td.swap(td_try);
-          A.swap(A_try);
+          masked_error(R.data(), M, U.data(), V.data(), m, n, r, td.data(), A.data());
           closed[k] = 1;
           accepted = true;
           rec.row = i; rec.j = j; rec.k = k; rec.op = op; rec.e = e;
@@ -562,13 +593,17 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
       nlog++;
       it_done = it;
       if (traj) traj[it] = e;
-      if (!accepted) {
+      // a fixed point, or (Sec. 3.3) a decrease below eps, ends the fit
+      const bool small_step = eps > 0.0 && (e_prev_it - e < eps);
+      e_prev_it = e;
+      if (!accepted || small_step) {
         if (traj)
           for (int qq = it + 1; qq <= iters; ++qq) traj[qq] = e;
         stop = true;
       }
     }
   } else {
+    double e_prev_pass = e;  // error at the end of the previous pass
     for (int it = 1; it <= iters && !stop; ++it) {
       int64_t acc_this_pass = 0;
       for (int i = 0; i < m; ++i) {
@@ -588,9 +623,9 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
           }
           e2 = op == 0
               ? f_ulf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k,
-                      Ubak.data(), Vbak.data(), td_try.data(), A_try.data())
+                      Ubak.data(), Vbak.data(), nullptr, nullptr)
               : f_urf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k,
-                      Ubak.data(), Vbak.data(), td_try.data(), A_try.data());
+                      Ubak.data(), Vbak.data(), nullptr, nullptr);
           rec.trials++;
           S.trials++;
           S.evaluated_cells += omega;
@@ -602,8 +637,7 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
         };
         auto accept = [&](int j, int k, int op, double e2) {
           e = e2;
-          td.swap(td_try);
-          A.swap(A_try);
+          masked_error(R.data(), M, U.data(), V.data(), m, n, r, td.data(), A.data());
           closed[k] = 1;
           accepted = true;
           rec.j = j; rec.k = k; rec.op = op; rec.e = e;
@@ -671,9 +705,9 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
             // apply the chosen update again (the same arithmetic, the same result)
             double e2 = bop == 0
                 ? f_ulf(R.data(), M, U.data(), V.data(), m, n, r, i, bj, bk,
-                        Ubak.data(), Vbak.data(), td_try.data(), A_try.data())
+                        Ubak.data(), Vbak.data(), nullptr, nullptr)
                 : f_urf(R.data(), M, U.data(), V.data(), m, n, r, i, bj, bk,
-                        Ubak.data(), Vbak.data(), td_try.data(), A_try.data());
+                        Ubak.data(), Vbak.data(), nullptr, nullptr);
             accept(bj, bk, bop, e2);
           }
         } else {
@@ -737,8 +771,10 @@ int fit(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r,
       if (stop && rows_left == 0) break;
       it_done = it;
       if (traj) traj[it] = e;
+      // Sec. 3.3: stop once a pass lowers the error by less than eps
       bool fixed_point = acc_this_pass == 0;
-      bool small_step = eps > 0.0 && traj && (traj[it - 1] - traj[it] < eps);
+      bool small_step = eps > 0.0 && (e_prev_pass - e < eps);
+      e_prev_pass = e;
       if (fixed_point || small_step) {
         if (traj)
           for (int q = it + 1; q <= iters; ++q) traj[q] = e;
@@ -810,6 +846,279 @@ int oracle_draw_init(const float* R, const uint8_t* M, int m, int n, int rank,
   if (s) return s;
   if (perm_out) std::memcpy(perm_out, w.perm.data(), sizeof(int32_t) * w.perm.size());
   if (U0_out) std::memcpy(U0_out, U0.data(), sizeof(float) * U0.size());
+  return OK;
+}
+
+}  // extern "C"
+
+// ============================================================ lockstep
+// The FP32-value oracle (the precision in which the GPU library takes its
+// decisions) checked decision by decision against FP64 arithmetic, for the
+// FastSTMF method (ByRow, TD_A).  The FP32 run goes its own way; before every
+// row visit its state is promoted exactly to double (the FP64 side is
+// re-synchronised to it), and every decision of the visit is recomputed in
+// FP64 from that state:
+//   - the candidate order: each pair of consecutive candidates, up to the
+//     accepted one, must also be in order by the FP64 td_col;
+//   - the component of each tried candidate: the TD_A count argmax from the
+//     FP64 argmax of every counted cell;
+//   - every trial (a no-op skip counting as a rejection): the same operation
+//     applied in FP64 to the promoted state, accepted iff its FP64 error is
+//     below the FP64 error of the promoted state.
+// A decision the FP64 side takes the other way is a rounding flip when the
+// quantity deciding it is within `band` (relative) of the tie on either side
+// (|e' - e| / e, the gap between two td_col keys, the gap between the two
+// max-plus terms of a counted cell), and a mismatch otherwise.  The
+// trajectory of the FP64 side is the FP64 error of the synchronised state
+// at the end of each pass.
+namespace {
+
+int validate_input(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r, int iters,
+                   bool int_exact) {
+  if (m_in < 1 || n_in < 1 || r < 1 || r > 64 || iters < 0) return EINVAL_;
+  for (int i = 0; i < m_in; ++i) {
+    int c = 0;
+    for (int j = 0; j < n_in; ++j) c += Min[(size_t)i * n_in + j] ? 1 : 0;
+    if (!c) return EEMPTY;
+  }
+  for (int j = 0; j < n_in; ++j) {
+    int c = 0;
+    for (int i = 0; i < m_in; ++i) c += Min[(size_t)i * n_in + j] ? 1 : 0;
+    if (!c) return EEMPTY;
+  }
+  if (int_exact)
+    for (size_t q = 0; q < (size_t)m_in * n_in; ++q)
+      if (Min[q] && !(std::fabs(Rin[q]) < 16777216.0f)) return ERANGE_;
+  return OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+struct oracle_lock_report {
+  int64_t row_visits;
+  int64_t trials;            // operations the FP32 run decided (evaluated or skipped)
+  int64_t agree;             // decisions the FP64 replay takes the same way
+  int64_t flips;             // taken the other way, within the band of a tie
+  int64_t flips_f32_accepts; // of those: the FP32 run accepts, FP64 rejects
+  int64_t mismatches;        // taken the other way beyond it
+  int64_t order_pairs;       // candidate pairs checked
+  int64_t order_flips, order_mismatches;
+  int64_t k_checked;         // components checked
+  int64_t k_flips, k_mismatches;
+  int32_t iters_done;
+  int32_t first_bad_iter;    // first mismatch of any kind (-1: none)
+  int32_t first_bad_row;
+  int32_t pad;
+  double max_rel_traj;       // max over passes of |traj_f32 - traj_f64| / traj_f64
+  double max_flip_margin;    // largest relative margin among the flips
+};
+
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oracle_get_threads(void) { return omp_get_max_threads(); }
+
+int oracle_lockstep(const float* Rin, const uint8_t* Min, int m_in, int n_in, int r, int iters,
+                    uint64_t seed, const oracle_opts* o, double band, double* traj_f,
+                    double* traj_d, oracle_log* log, int log_cap, int* log_len,
+                    oracle_lock_report* rep) {
+  if (o && (o->selection != 0 || o->strategy != 0)) return EINVAL_;
+  const bool int_exact = o && o->integer_exact;
+  int s = validate_input(Rin, Min, m_in, n_in, r, iters, int_exact);
+  if (s) return s;
+  SplitMix64 g{seed};
+  Working w;
+  s = build_working(Rin, Min, m_in, n_in, o, seed, w, g);
+  if (s) return s;
+  std::vector<float> U0;
+  s = init_U0(w, r, o, g, U0);
+  if (s) return s;
+  const int m = w.m, n = w.n;
+  const uint8_t* M = w.M.data();
+  const int scope_all = o && o->count_scope == 1;
+  const int noop_rule = o ? o->noop_rule : 1;
+  const double eps = o ? o->eps : 0.0;
+
+  // the FP32 run's state, and the FP64 side's arrays
+  std::vector<float> R = w.R, U = U0, V((size_t)r * n);
+  std::vector<double> Rd((size_t)m * n), Ud((size_t)m * r), Vd((size_t)r * n);
+  for (size_t q = 0; q < R.size(); ++q) Rd[q] = (double)R[q];
+  for (int k = 0; k < r; ++k) col_res(R.data(), M, m, n, r, k, U.data(), V.data());
+  std::vector<double> td((size_t)n), tdd((size_t)n);
+  std::vector<int32_t> A((size_t)m * n), Ad((size_t)m * n);
+  std::vector<float> Ubak((size_t)m), Vbak((size_t)n);
+  std::vector<double> Udb((size_t)m), Vdb((size_t)n);
+  std::vector<char> closed((size_t)r, 0);
+  oracle_lock_report Q{};
+  Q.first_bad_iter = Q.first_bad_row = -1;
+  auto bad = [&](int it, int i) {
+    if (Q.first_bad_iter < 0) { Q.first_bad_iter = it; Q.first_bad_row = i; }
+  };
+  auto promote = [&]() {
+    for (size_t q = 0; q < U.size(); ++q) Ud[q] = (double)U[q];
+    for (size_t q = 0; q < V.size(); ++q) Vd[q] = (double)V[q];
+    return masked_error(Rd.data(), M, Ud.data(), Vd.data(), m, n, r, tdd.data(), Ad.data());
+  };
+  auto rel = [](double a, double b) {
+    const double s = std::max(std::fabs(a), std::fabs(b));
+    return s > 0.0 ? std::fabs(a - b) / s : 0.0;
+  };
+
+  double e = masked_error(R.data(), M, U.data(), V.data(), m, n, r, td.data(), A.data());
+  double ed = promote();
+  if (traj_f) traj_f[0] = e;
+  if (traj_d) traj_d[0] = ed;
+  Q.max_rel_traj = rel(e, ed);
+  int nlog = 0;
+  double e_prev_pass = e;
+  bool stop = false;
+  for (int it = 1; it <= iters && !stop; ++it) {
+    int64_t acc_pass = 0;
+    for (int i = 0; i < m; ++i) {
+      ed = promote();
+      oracle_log rec{it, i, 0, 0, -1, -1, -1, 0, e};
+      std::vector<int> cand;
+      for (int j = 0; j < n; ++j)
+        if (M[(size_t)i * n + j]) cand.push_back(j);
+      std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) { return td[a] > td[b]; });
+      // TD_A counts of row i, in both precisions
+      std::vector<int> crow((size_t)r, 0), crowd((size_t)r, 0);
+      for (int t = 0; t < n; ++t)
+        if (scope_all || M[(size_t)i * n + t]) {
+          crow[A[(size_t)i * n + t]]++;
+          crowd[Ad[(size_t)i * n + t]]++;
+        }
+      // a counted cell whose argmax differs between the two precisions: a
+      // near-tie of two max-plus terms in FP64?
+      auto cell_near_tie = [&](int t, int c) {
+        const int a = A[(size_t)t * n + c], b = Ad[(size_t)t * n + c];
+        if (a == b) return true;
+        const double pa = Ud[(size_t)t * r + a] + Vd[(size_t)a * n + c];
+        const double pb = Ud[(size_t)t * r + b] + Vd[(size_t)b * n + c];
+        return rel(pa, pb) <= band;
+      };
+      bool accepted = false;
+      size_t pos = 0;
+      for (; pos < cand.size() && !accepted; ++pos) {
+        const int j = cand[pos];
+        std::vector<int> cnt(crow), cntd(crowd);
+        for (int t = 0; t < m; ++t)
+          if (scope_all || M[(size_t)t * n + j]) {
+            cnt[A[(size_t)t * n + j]]++;
+            cntd[Ad[(size_t)t * n + j]]++;
+          }
+        int k = 0, kd = 0;
+        for (int l = 1; l < r; ++l) {
+          if (cnt[l] > cnt[k]) k = l;
+          if (cntd[l] > cntd[kd]) kd = l;
+        }
+        Q.k_checked++;
+        if (k != kd) {
+          bool ties = true;
+          for (int t = 0; t < n && ties; ++t)
+            if (scope_all || M[(size_t)i * n + t]) ties = cell_near_tie(i, t);
+          for (int t = 0; t < m && ties; ++t)
+            if (scope_all || M[(size_t)t * n + j]) ties = cell_near_tie(t, j);
+          if (ties) Q.k_flips++;
+          else { Q.k_mismatches++; bad(it, i); }
+        }
+        for (int op = 0; op < 2 && !accepted; ++op) {
+          // FP32 run
+          const float Rij = R[(size_t)i * n + j];
+          bool skip_f = false;
+          double e2 = e;
+          if (noop_rule && closed[k]) {
+            const float Uik = U[(size_t)i * r + k], Vkj = V[(size_t)k * n + j];
+            skip_f = op == 0 ? (float)(Rij - Vkj) == Uik : (float)(Rij - Uik) == Vkj;
+          }
+          if (skip_f) {
+            rec.noops++;
+          } else {
+            e2 = op == 0 ? f_ulf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k, Ubak.data(),
+                                 Vbak.data(), nullptr, nullptr)
+                         : f_urf(R.data(), M, U.data(), V.data(), m, n, r, i, j, k, Ubak.data(),
+                                 Vbak.data(), nullptr, nullptr);
+            rec.trials++;
+          }
+          const bool acc_f = !skip_f && e2 < e;
+          // FP64 replay of the same operation from the promoted state
+          const double Rijd = Rd[(size_t)i * n + j];
+          bool skip_d = false;
+          double e2d = ed;
+          if (noop_rule && closed[k]) {
+            const double Uik = Ud[(size_t)i * r + k], Vkj = Vd[(size_t)k * n + j];
+            skip_d = op == 0 ? (Rijd - Vkj) == Uik : (Rijd - Uik) == Vkj;
+          }
+          if (!skip_d) {
+            e2d = op == 0 ? f_ulf(Rd.data(), M, Ud.data(), Vd.data(), m, n, r, i, j, k, Udb.data(),
+                                  Vdb.data(), nullptr, nullptr)
+                          : f_urf(Rd.data(), M, Ud.data(), Vd.data(), m, n, r, i, j, k, Udb.data(),
+                                  Vdb.data(), nullptr, nullptr);
+            for (int t = 0; t < m; ++t) Ud[(size_t)t * r + k] = Udb[t];
+            for (int c = 0; c < n; ++c) Vd[(size_t)k * n + c] = Vdb[c];
+          }
+          const bool acc_d = !skip_d && e2d < ed;
+          Q.trials++;
+          if (acc_f == acc_d) {
+            Q.agree++;
+          } else {
+            const double mf = rel(e2, e), md = rel(e2d, ed);
+            if (std::min(mf, md) <= band) {
+              Q.flips++;
+              if (acc_f) Q.flips_f32_accepts++;
+              Q.max_flip_margin = std::max(Q.max_flip_margin, std::min(mf, md));
+            } else {
+              Q.mismatches++;
+              bad(it, i);
+            }
+          }
+          if (acc_f) {
+            e = e2;
+            masked_error(R.data(), M, U.data(), V.data(), m, n, r, td.data(), A.data());
+            closed[k] = 1;
+            accepted = true;
+            rec.j = j; rec.k = k; rec.op = op; rec.e = e;
+            acc_pass++;
+          } else if (!skip_f) {
+            for (int t = 0; t < m; ++t) U[(size_t)t * r + k] = Ubak[t];
+            for (int c = 0; c < n; ++c) V[(size_t)k * n + c] = Vbak[c];
+          }
+        }
+      }
+      // candidate order up to (and including the pair after) the last tried
+      // candidate, by the FP64 td_col of the visit's starting state
+      const size_t last = std::min(pos, cand.size() - 1);
+      for (size_t p = 0; p < last; ++p) {
+        const int a = cand[p], b = cand[p + 1];
+        Q.order_pairs++;
+        const bool ok = tdd[a] > tdd[b] || (tdd[a] == tdd[b] && a < b);
+        if (!ok) {
+          if (rel(tdd[a], tdd[b]) <= band) Q.order_flips++;
+          else { Q.order_mismatches++; bad(it, i); }
+        }
+      }
+      Q.row_visits++;
+      if (log && nlog < log_cap) log[nlog] = rec;
+      nlog++;
+    }
+    ed = promote();
+    if (traj_f) traj_f[it] = e;
+    if (traj_d) traj_d[it] = ed;
+    Q.max_rel_traj = std::max(Q.max_rel_traj, rel(e, ed));
+    Q.iters_done = it;
+    const bool fixed_point = acc_pass == 0;
+    const bool small_step = eps > 0.0 && (e_prev_pass - e < eps);
+    e_prev_pass = e;
+    if (fixed_point || small_step) {
+      for (int q = it + 1; q <= iters; ++q) {
+        if (traj_f) traj_f[q] = e;
+        if (traj_d) traj_d[q] = ed;
+      }
+      stop = true;
+    }
+  }
+  if (log_len) *log_len = nlog;
+  if (rep) *rep = Q;
   return OK;
 }
 

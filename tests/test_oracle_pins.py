@@ -712,6 +712,53 @@ def test_fixed_point_padding():
     assert np.all(a.traj[d:] == a.traj[d])
 
 
+def _eps_between(traj, done):
+    """A threshold between two distinct decreases of an eps-free run, so that
+    the stop falls strictly inside the run; None if the run has no room."""
+    dec = traj[:done] - traj[1:done + 1]
+    vals = np.unique(dec[dec > 0])
+    if len(vals) < 2:
+        return None
+    mid = len(vals) // 2
+    return float((vals[mid - 1] + vals[mid]) / 2)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("strategy,iters", [(0, 12), (1, 12), (2, 80)])
+def test_eps_stop_truncates_the_eps_free_run(prec, strategy, iters):
+    # Sec. 3.3: iterating stops once a pass (ByMatrix: an iteration) lowers
+    # the error by less than eps.  Derived from the eps-free run alone: the
+    # run with eps repeats its passes up to the first one whose decrease is
+    # below eps, stops there and pads the trajectory with that error.
+    found = False
+    for seed in range(20):
+        R, M = synth.int_planted(24, 40, 3, 0.3, seed=100 + seed, hi=40)
+        kw = dict(seed=seed, prec=prec, init_hi=40, strategy=strategy,
+                  perm_mode=2 if strategy == 2 else 0)
+        free = oracle.fit(R, M, 3, iters, **kw)
+        done = free.stats["iters_done"]
+        eps = _eps_between(free.traj, done)
+        if eps is None:
+            continue
+        found = True
+        dec = free.traj[:-1] - free.traj[1:]
+        p = 1 + int(np.argmax(dec[:done] < eps))  # first pass decreasing by < eps
+        assert dec[p - 1] < eps and np.all(dec[:p - 1] >= eps)
+        got = oracle.fit(R, M, 3, iters, eps=eps, **kw)
+        assert got.stats["iters_done"] == p
+        np.testing.assert_array_equal(got.traj[:p + 1], free.traj[:p + 1])
+        np.testing.assert_array_equal(got.traj[p + 1:], free.traj[p])
+        nrec = sum(1 for r in free.log if r["iter"] <= p)
+        np.testing.assert_array_equal(got.log, free.log[:nrec])
+        # the stop does not depend on the caller asking for the trajectory
+        quiet = oracle.fit(R, M, 3, iters, eps=eps, no_traj=True, **kw)
+        assert quiet.stats["iters_done"] == p
+        np.testing.assert_array_equal(quiet.U, got.U)
+        np.testing.assert_array_equal(quiet.V, got.V)
+        break
+    assert found
+
+
 # ------------------------------------------------------------------ ByMatrix
 BYMATRIX_OP_STREAM = 0xA0761D6478BD642F  # seed XOR this: the operation draws
 
@@ -830,3 +877,57 @@ def test_bymatrix_one_update_per_iteration_and_seed_drives_operations():
     ops_c = [int(x["op"]) for x in c.log]; ops_d = [int(x["op"]) for x in d.log]
     assert ops_c != ops_d or not np.array_equal(c.traj, d.traj)
 
+
+
+# ------------------------------------------------------------------ FP64 lockstep
+def test_lockstep_float_side_is_the_f32_oracle_and_integers_agree_exactly():
+    # on integer data every operation is exact in both precisions: the FP64
+    # replay takes every decision the same way and the trajectories are equal
+    R, M = synth.int_planted(30, 70, 3, 0.3, seed=7, hi=50)
+    L = oracle.lockstep(R, M, 3, 8, seed=7, init_hi=50, integer_exact=1)
+    o = oracle.fit(R, M, 3, 8, seed=7, prec="f32", init_hi=50, integer_exact=1)
+    assert L.status == 0
+    np.testing.assert_array_equal(L.log, o.log)
+    np.testing.assert_array_equal(L.traj_f32, o.traj)
+    np.testing.assert_array_equal(L.traj_f32, L.traj_f64)
+    rep = L.report
+    assert rep["flips"] == rep["mismatches"] == 0
+    assert rep["order_flips"] == rep["order_mismatches"] == 0
+    assert rep["k_flips"] == rep["k_mismatches"] == 0
+    assert rep["agree"] == rep["trials"] > 0
+
+
+def test_lockstep_real_data_disagrees_only_at_rounding_level():
+    # real data: the FP32 run is the f32 oracle, decision for decision; every
+    # decision the FP64 replay takes the other way is within 1e-6 of a tie
+    R, M = synth.gene_expr(40, 90, 3, 0.5, seed=2)
+    L = oracle.lockstep(R, M, 3, 10, seed=2, init_mode=1)
+    o = oracle.fit(R, M, 3, 10, seed=2, prec="f32", init_mode=1)
+    np.testing.assert_array_equal(L.log, o.log)
+    np.testing.assert_array_equal(L.traj_f32, o.traj)
+    rep = L.report
+    assert rep["mismatches"] == rep["order_mismatches"] == rep["k_mismatches"] == 0
+    assert rep["agree"] + rep["flips"] == rep["trials"]
+    assert rep["max_flip_margin"] < 1e-7
+    np.testing.assert_allclose(L.traj_f32, L.traj_f64, rtol=1e-5)
+    # with no band every disagreement is a mismatch: the classification only
+    # sorts the same disagreements
+    L0 = oracle.lockstep(R, M, 3, 10, seed=2, init_mode=1, band=0.0)
+    assert L0.report["flips"] + L0.report["mismatches"] == rep["flips"]
+
+
+def test_oracle_results_do_not_depend_on_thread_count():
+    # the row loops run on several threads with every sum in a fixed order
+    R, M = synth.gene_expr(150, 260, 4, 0.5, seed=9)   # above the parallel threshold
+    before = oracle.get_threads()
+    try:
+        oracle.set_threads(1)
+        a = oracle.fit(R, M, 4, 2, seed=9, prec="f32", init_mode=1)
+        oracle.set_threads(4)
+        b = oracle.fit(R, M, 4, 2, seed=9, prec="f32", init_mode=1)
+    finally:
+        oracle.set_threads(before)
+    np.testing.assert_array_equal(a.traj, b.traj)
+    np.testing.assert_array_equal(a.U, b.U)
+    np.testing.assert_array_equal(a.V, b.V)
+    np.testing.assert_array_equal(a.log, b.log)
