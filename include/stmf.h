@@ -47,7 +47,7 @@ typedef enum {
   STMF_ENOMEM = 4,      /* workspace too small or misaligned                         */
   STMF_EHIP = 5,        /* a HIP runtime call failed                                 */
   STMF_EBUSY = 6,       /* serving engine: no slot or not enough memory free         */
-  STMF_ETIMEOUT = 7     /* a cooperative fit stopped: a group barrier waited > 4 s   */
+  STMF_ETIMEOUT = 7     /* a fit stopped: a group barrier waited > 4 s             */
 } stmf_status;
 
 /* Short English description of a status code (static string). */
@@ -78,6 +78,7 @@ int stmf_masked_error(const float* R, const uint8_t* M, const float* U,
                       const float* V, int m, int n, int r, double* err,
                       double* td_col, void* ws, size_t ws_bytes, void* stream);
 
+
 /* Workspace bytes of stmf_update_U / stmf_update_V. */
 size_t stmf_update_workspace(int m, int n, int r);
 
@@ -90,7 +91,10 @@ size_t stmf_update_workspace(int m, int n, int r);
  * The call never accepts or restores: the caller compares err with the
  * previous error and copies the backups back to reject.  Requires M[i,j]
  * observed (checked, synchronously: STMF_EINVAL otherwise) and 0 <= k < r.
- * A line of M with no observed cell makes the matching residual +inf.
+ * Every row and column of M must hold an observed cell (a residual over an
+ * empty line is undefined): otherwise STMF_EEMPTY_LINE, returned before any
+ * launch (M is copied back and checked on the host, synchronously on the
+ * stream), so U and V are untouched.
  * U_col_prev (m floats), V_row_prev (n floats), err (1 double): device. */
 int stmf_update_U(const float* R, const uint8_t* M, float* U, float* V, int m,
                   int n, int r, int i, int j, int k, float* U_col_prev,

@@ -24,8 +24,10 @@
 //   The new product is P' = max(P without k, U''_tk + V'_kc), bit-identical
 //   to a full max over components (max is exact and order-free).
 // Every value operation is one correctly rounded FP32 operation; |R - P'| is
-// widened to FP64 and summed in a fixed order (lane, tile, workgroup, chunk),
-// so a trial's error depends only on the state and the trial.
+// widened to FP64 and summed in a fixed order (lane, row, tile, chunks of
+// tiles, a tree over the chunks) that depends on the working shape alone, so
+// a trial's error depends only on the state and the trial, never on how many
+// workgroups share the fit.
 //
 // Per row visit: batches (residual pass, group barrier, error pass, group
 // barrier with the decision taken by the last workgroup to arrive); after an
@@ -152,8 +154,7 @@ struct CombineScratch {
   double dpart[2048];        // staged td_col partials
 };
 struct ReduceScratch {
-  double v[4096];            // staged per-workgroup partial errors
-  double chunk[TMAX];        // chunk sums of the trials being reduced
+  double v[4096];            // chunk sums of the trials being reduced
 };
 struct Smem {
   union {
@@ -166,7 +167,6 @@ struct Smem {
   float Ut[RMAX][TS];        // U of the tile rows, every component
   float Vt[RMAX][TS];        // V of the tile columns, every component
   float uk[TS], vk[TS];      // new component values of the tile (refresh)
-  double wsum[TMAX];         // per trial: this workgroup's partial error
   Trial trials[TMAX];
   int trow[TMAX];            // ByMatrix: each trial's row (a batch mixes rows)
   int noops_before[TMAX];    // no-op skips preceding each trial in the batch
@@ -671,12 +671,12 @@ DEV void chunk_stage(Grp& gp, Smem& S, const WaveTrials& w, const Chunk& c, int 
 }
 
 // Per trial of an evaluated chunk: the eight row sums (half 0 first) in a
-// fixed order, added to this workgroup's partial error of the trial.
-DEV void chunk_reduce(Grp& gp, Smem& S, const Chunk& c) {
+// fixed order, the tile's partial error of the trial (epart[trial][tile]).
+DEV void chunk_reduce(Grp& gp, Smem& S, const Chunk& c, GA double* epart, int ntile, int tile) {
   if (gp.tid < c.cn) {
     const double* p = &S.u.b.epl[gp.tid][0][0];
     const double s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
-    S.wsum[list_at(S, c.cs + gp.tid, c.a0, c.n0, c.a1)] += s;
+    st_coh(&epart[(size_t)list_at(S, c.cs + gp.tid, c.a0, c.n0, c.a1) * ntile + tile], s);
   }
 }
 
@@ -685,11 +685,9 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
   const FitDev& d = *gp.d;
   const auto Rw = d.Rw;
   const auto epart = d.epart;
-  const size_t ldn = d.ldn, gs = d.gsize;
+  const size_t ldn = d.ldn;
   const int dr = d.r, nct = d.nct;
-  const int nt = S.nt;
   constexpr int NE = TCH / NWAVE;
-  for (int q = gp.tid; q < nt; q += NTHR) S.wsum[q] = 0.0;
   const int ntile = d.nrt * d.nct;
   const int half = gp.wave & 1, h0 = half * (TS / 2);
   for (int tile = gp.g; tile < ntile; tile += gp.G) {
@@ -748,7 +746,7 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
       }
       __syncthreads();
       chunk_stage<NE, MR>(gp, S, wcur, cur, cur.k - kb0, r0, c0, rawA, rawB);
-      chunk_reduce(gp, S, prev);
+      chunk_reduce(gp, S, prev, epart, ntile, tile);
       const Chunk next = chunk_at(S, dr, cur.k, cur.cs + TCH);
       const WaveTrials wnext =
           wave_trials<NE, MR>(gp, S, next.cs, next.cn, next.a0, next.n0, next.a1);
@@ -780,46 +778,53 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
       wcur = wnext;
     }
     __syncthreads();
-    chunk_reduce(gp, S, prev);
+    chunk_reduce(gp, S, prev, epart, ntile, tile);
   }
-  __syncthreads();
-  for (int q = gp.tid; q < nt; q += NTHR) st_coh(&epart[q * gs + gp.g], S.wsum[q]);
 }
 
-// Errors of this workgroup's slice of trials from the per-workgroup partials:
-// eight fixed chunks of consecutive workgroups, each summed in order, then a
-// fixed tree over the chunks.  The result depends only on the partials.
+// Errors of this workgroup's slice of trials from the per-tile partials, in
+// an order fixed by the tile count alone: chunks of consecutive tiles (RCH,
+// or more when there are over 4096 chunks), each summed in tile order, then
+// a pairwise tree over the chunk sums.  How the tiles were spread over the
+// group's workgroups does not enter, so a fit's errors (and with them its
+// decisions) are the same on any group size.
+static constexpr int RCH = 32;
+
 DEV void reduce_errors(Grp& gp, Smem& S, int nt) {
   const FitDev& d = *gp.d;
   const auto epart = d.epart;
   const auto eprime = d.eprime;
-  const size_t gs = d.gsize;
+  const int ntile = d.nrt * d.nct;
+  const int per = ntile <= 4096 * RCH ? RCH : (ntile + 4095) / 4096;
+  const int nch = (ntile + per - 1) / per;
   int lo, hi;
   slice(nt, gp.g, gp.G, lo, hi);
-  const int per = (gp.G + 7) / 8;
-  // trials staged at a time: G partials each (<= 4096 doubles), 8 chunk sums
-  // each (<= TMAX doubles)
-  const int qb = 4096 / gp.G < TMAX / 8 ? 4096 / gp.G : TMAX / 8;
+  // trials staged at a time: their chunk sums (<= 4096 doubles)
+  const int qb = 4096 / nch;
   for (int q0 = lo; q0 < hi; q0 += qb) {
     const int qn = hi - q0 < qb ? hi - q0 : qb;
     __syncthreads();
-    for (int e = gp.tid; e < qn * gp.G; e += NTHR) {
-      const int qq = e / gp.G, g = e % gp.G;
-      S.u.r.v[e] = ld_atomic(&epart[(q0 + qq) * gs + g]);
-    }
-    __syncthreads();
-    for (int e = gp.tid; e < qn * 8; e += NTHR) {
-      const int qq = e >> 3, part = e & 7;
-      const int glo = part * per < gp.G ? part * per : gp.G;
-      const int ghi = glo + per < gp.G ? glo + per : gp.G;
-      double s = 0.0;
-      for (int g = glo; g < ghi; ++g) s += S.u.r.v[qq * gp.G + g];
-      S.u.r.chunk[e] = s;
+    for (int e = gp.tid; e < qn * nch; e += NTHR) {
+      const int qq = e / nch, c = e % nch;
+      const GA double* p = epart + (size_t)(q0 + qq) * ntile + (size_t)c * per;
+      const int len = ntile - c * per < per ? ntile - c * per : per;
+      double sum = 0.0;
+      for (int t0 = 0; t0 < len; t0 += RCH) {
+        double v[RCH];
+#pragma unroll
+        for (int t = 0; t < RCH; ++t) v[t] = t0 + t < len ? ld_atomic(&p[t0 + t]) : 0.0;
+#pragma unroll
+        for (int t = 0; t < RCH; ++t)
+          if (t0 + t < len) sum += v[t];
+      }
+      S.u.r.v[e] = sum;
     }
     __syncthreads();
     for (int qq = gp.tid; qq < qn; qq += NTHR) {
-      const double* p = S.u.r.chunk + qq * 8;
-      st_coh(&eprime[q0 + qq], ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7])));
+      double* v = S.u.r.v + qq * nch;
+      for (int w = 1; w < nch; w *= 2)
+        for (int c = 0; c + w < nch; c += 2 * w) v[c] += v[c + w];
+      st_coh(&eprime[q0 + qq], v[0]);
     }
   }
 }

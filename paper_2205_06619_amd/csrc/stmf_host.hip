@@ -199,7 +199,7 @@ static void make_layout(int m, int n, int r, int iters, int G, int acol_p, int b
   L.rord = take((size_t)L.ldn * 4);
   L.tdrow = take((size_t)L.ldn * 8);
   L.tvec = take((size_t)2 * L.tmax * L.ldmax * 4);
-  L.epart = take((size_t)L.tmax * G * 8);
+  L.epart = take((size_t)L.tmax * L.nrt * L.nct * 8);
   L.eprime = take((size_t)L.tmax * 8);
   L.closed = take((size_t)r * 4);
   L.rowt = take((size_t)L.mw * 4);
@@ -457,20 +457,21 @@ static int launch_output(const Layout& L, char* base, float* U_out, float* V_out
 // compiled for it alone, in its own build for launches with a fit wider than
 // SORT_MAX columns: `wide`).  queue: batched launches (one workgroup per fit,
 // fits taken from the queue); null: the fits own consecutive ranges of
-// gsize workgroups.  A cooperative launch has the runtime check that the
-// whole grid is resident at once; other launches with group barriers keep
-// the grid within the co-resident count.
+// gsize workgroups.  Every launch is a plain one whose grid stays within the
+// co-resident count (one fit-kernel workgroup per CU: its LDS takes most of
+// a CU's), so on an otherwise idle device every group is resident at once;
+// the group barrier's bounded wait turns anything else into STMF_ETIMEOUT.
+// (No cooperative launch: it adds nothing the bounded wait does not cover,
+// and a process that made one ended with a segmentation fault at exit under
+// the profiler.)
 static int launch_fit_kernel(const FitDev* dev_fits, int nfits, int grid, int max_rows,
-                             unsigned* queue, int sel, bool wide, bool cooperative, hipStream_t s) {
+                             unsigned* queue, int sel, bool wide, hipStream_t s) {
   const size_t smem = fit_smem_bytes();
   const void* k = sel == SEL_TD_A     ? (wide ? (const void*)fit_kernel_wide : (const void*)fit_kernel)
                   : sel == SEL_MATRIX ? (const void*)fit_kernel_matrix
                                       : (const void*)fit_kernel_sel;
   void* args[] = {(void*)&dev_fits, (void*)&nfits, (void*)&max_rows, (void*)&queue};
-  if (cooperative)
-    HIPCHK(hipLaunchCooperativeKernel(k, dim3(grid), dim3(NTHR), args, (unsigned)smem, s));
-  else
-    HIPCHK(hipLaunchKernel(k, dim3(grid), dim3(NTHR), args, smem, s));
+  HIPCHK(hipLaunchKernel(k, dim3(grid), dim3(NTHR), args, smem, s));
   return STMF_OK;
 }
 
@@ -516,7 +517,7 @@ const char* stmf_status_str(int s) {
     case STMF_ENOMEM: return "workspace too small or misaligned";
     case STMF_EHIP: return "HIP runtime error";
     case STMF_EBUSY: return "no free slot or memory";
-    case STMF_ETIMEOUT: return "cooperative fit timed out at a group barrier";
+    case STMF_ETIMEOUT: return "fit timed out at a group barrier";
     default: return "unknown status";
   }
 }
@@ -559,9 +560,21 @@ static int update_common(int op, const float* R, const uint8_t* M, float* U, flo
   if (i < 0 || i >= m || j < 0 || j >= n || k < 0 || k >= r) return STMF_EINVAL;
   if (!ws || ((uintptr_t)ws & 255) || ws_bytes < masked_error_ws(m, n)) return STMF_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
-  uint8_t obs = 0;
-  HIPCHK(hipMemcpyAsync(&obs, M + (size_t)i * n + j, 1, hipMemcpyDeviceToHost, s));
+  // a residual over a row or column with no observed cell is undefined: the
+  // mask is read back and every line checked before anything is launched
+  std::vector<uint8_t> hm((size_t)m * n);
+  HIPCHK(hipMemcpyAsync(hm.data(), M, hm.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  std::vector<char> col_seen(n, 0);
+  for (int t = 0; t < m; ++t) {
+    bool row_seen = false;
+    for (int c = 0; c < n; ++c)
+      if (hm[(size_t)t * n + c]) { row_seen = true; col_seen[c] = 1; }
+    if (!row_seen) return STMF_EEMPTY_LINE;
+  }
+  for (int c = 0; c < n; ++c)
+    if (!col_seen[c]) return STMF_EEMPTY_LINE;
+  const uint8_t obs = hm[(size_t)i * n + j];
   if (!obs) return STMF_EINVAL;
   HIPCHK(launch_update(op, R, M, U, V, m, n, r, i, j, k, Ub, Vb, err, ws, s));
   return STMF_OK;
@@ -655,7 +668,7 @@ int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters
   HIPCHK(hipEventCreate(&ev1));
   HIPCHK(hipEventRecord(ev0, s));
   st = launch_fit_kernel((const FitDev*)(base + L.dev), 1, G, o.max_row_visits, nullptr,
-                         kernel_sel(o), L.nw > SORT_MAX, G > 1, s);
+                         kernel_sel(o), L.nw > SORT_MAX, s);
   if (st) { (void)hipEventDestroy(ev0); (void)hipEventDestroy(ev1); return st; }
   HIPCHK(hipEventRecord(ev1, s));
   FitCtl c;
@@ -754,7 +767,7 @@ static int run_grouped(std::vector<FitDev> active, int coresident, char* table_d
     for (int f = 0; f <= n; ++f) {
       if (f == n || grid + active[f].gsize > coresident) {
         int st = launch_fit_kernel(t + first, f - first, grid, BATCH_ROUND_ROWS, nullptr, sel,
-                                   any_wide(active.data() + first, f - first), false, s);
+                                   any_wide(active.data() + first, f - first), s);
         if (st) return st;
         first = f;
         grid = 0;
@@ -852,7 +865,7 @@ int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts, const stmf_op
     const int grid = std::min<int>((int)table.size(), P.coresident);
     st = launch_fit_kernel((const FitDev*)(base + B.table), (int)table.size(), grid, 0,
                            (unsigned*)(base + B.queue), kernel_sel(o),
-                           any_wide(table.data(), (int)table.size()), false, s);
+                           any_wide(table.data(), (int)table.size()), s);
     if (st) return st;
   }
   HIPCHK(hipStreamSynchronize(s));  // host staging vectors go out of scope after this
@@ -1063,10 +1076,10 @@ static int tick_work(stmf_engine* e, const std::vector<int>& plan, int max_rows,
       st = fill_u32(e->arena + e->queue_off, 1, 0, s);
       if (!st)
         st = launch_fit_kernel(table + first, count, std::min(count, e->coresident), max_rows,
-                               (unsigned*)(e->arena + e->queue_off), sel, wide, false, s);
+                               (unsigned*)(e->arena + e->queue_off), sel, wide, s);
     } else {
       // every group of the launch is resident at once: grid <= coresident
-      st = launch_fit_kernel(table + first, count, grid, max_rows, nullptr, sel, wide, false, s);
+      st = launch_fit_kernel(table + first, count, grid, max_rows, nullptr, sel, wide, s);
     }
     if (st) return st;
   }

@@ -143,7 +143,7 @@ struct FitDev {
   STMF_G(int) mlist_q;       // tmax: candidates in order (cell position)
   STMF_G(int) mlist_k;       // tmax: their component f(i, j)
   STMF_G(unsigned) tvec;     // 2 x TMAX x ldmax: atomic-min targets (order-mapped floats)
-  STMF_G(double) epart;      // TMAX x gsize: per-workgroup partial errors
+  STMF_G(double) epart;      // tmax x tiles: per-tile partial errors of every trial
   STMF_G(double) eprime;     // TMAX: error of every trial of the batch
   STMF_G(int) closed;        // r
   STMF_G(int) rowt;          // m': trials the last visit of each row evaluated (0: none yet)

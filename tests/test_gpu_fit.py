@@ -137,6 +137,45 @@ def test_fit_gene_expression_prefix(S):
     assert g.traj[0] == pytest.approx(o.traj[0], rel=1e-12)
 
 
+def test_fit_gene_expression_first_pass(S):
+    # the gene-expression-shaped workload at full size: the whole first pass
+    # (500 row visits), decision by decision against the FP32-value oracle
+    print("fit real 500x2000 first pass", flush=True)
+    R, M = synth.gene_expr()
+    o = oracle.fit(R, M, 5, 50, seed=2, prec="f32", init_mode=1, row_limit=500)
+    assert o.status == 0 and len(o.log) == 500
+    g = S.stmf_fit(_t(R), _t(M), 5, 50, seed=2, init_mode=1, max_row_visits=500, log_cap=512)
+    print(g.info["trials"], o.stats["trials"], flush=True)
+    assert _log_rows(g.log) == _log_rows(o.log)
+    np.testing.assert_allclose(g.log["e"], o.log["e"], rtol=1e-9)
+    assert g.info["trials"] == o.stats["trials"]
+    assert g.info["noops"] == o.stats["noops"]
+
+
+@pytest.mark.timeout(900)
+def test_fit_real_lockstep_fp64_all_passes(S):
+    # a multi-tile real fit (80 x 200: 2 x 4 tiles, both ragged), rank 4, 50
+    # passes, against the FP64 oracle in lockstep: the FP32-value oracle runs
+    # the fit while every one of its decisions (candidate order, component,
+    # accept or reject) is recomputed in FP64 from the same state.  The GPU
+    # must take the FP32 oracle's decisions row visit by row visit, no FP64
+    # decision may differ beyond a 1e-6 relative band around a tie, and every
+    # trajectory entry must be within 1e-5 of the FP64 error of the same state.
+    print("fit real 80x200 lockstep fp64, 50 passes", flush=True)
+    R, M = synth.gene_expr(80, 200, 4, 0.5, seed=12)
+    g = S.stmf_fit(_t(R), _t(M), 4, 50, seed=12, init_mode=1, log_cap=80 * 50 + 8)
+    L = oracle.lockstep(R, M, 4, 50, seed=12, init_mode=1)
+    assert L.status == 0
+    rep = L.report
+    print(rep, flush=True)
+    assert _log_rows(g.log) == _log_rows(L.log)
+    np.testing.assert_allclose(g.traj, L.traj_f32, rtol=1e-9, atol=0)
+    np.testing.assert_allclose(g.traj, L.traj_f64, rtol=1e-5, atol=0)
+    assert rep["mismatches"] == rep["order_mismatches"] == rep["k_mismatches"] == 0
+    assert rep["flips"] <= 0.05 * rep["trials"]
+    assert rep["max_flip_margin"] < 1e-7
+
+
 def test_fit_large_prefix(S):
     # the large single factorization at full size (2000 x 20000, planted rank
     # 20, 70% missing with row-dependent rates, rank 20, Random Acol): the
@@ -151,6 +190,30 @@ def test_fit_large_prefix(S):
     assert _log_rows(g.log) == _log_rows(o.log)
     np.testing.assert_allclose(g.log["e"], o.log["e"], rtol=1e-9)
     assert g.traj[0] == pytest.approx(o.traj[0], rel=1e-12)
+
+
+@pytest.mark.parametrize("strategy,iters", [(0, 12), (1, 12), (2, 80)])
+def test_fit_eps_stop_integer_exact(S, strategy, iters):
+    # Sec. 3.3 convergence threshold: eps chosen between two decreases of the
+    # oracle's eps-free run, so the stop falls inside the run; the GPU fit
+    # with that eps must equal the oracle's bit for bit (integer data)
+    for seed in range(20):
+        R, M = synth.int_planted(24, 40, 3, 0.3, seed=100 + seed, hi=40)
+        kw = dict(init_hi=40, strategy=strategy, perm_mode=2 if strategy == 2 else 0)
+        free = oracle.fit(R, M, 3, iters, seed=seed, prec="f32", **kw)
+        done = free.stats["iters_done"]
+        dec = np.unique((free.traj[:done] - free.traj[1:done + 1]))
+        dec = dec[dec > 0]
+        if len(dec) >= 2:
+            break
+    eps = float((dec[len(dec) // 2 - 1] + dec[len(dec) // 2]) / 2)
+    print(f"fit eps={eps} strategy={strategy} seed={seed}", flush=True)
+    o = oracle.fit(R, M, 3, iters, seed=seed, prec="f32", eps=eps, **kw)
+    assert o.stats["iters_done"] < done
+    g = S.stmf_fit(_t(R), _t(M), 3, iters, seed=seed, eps=eps, init_hi=40.0,
+                   log_cap=len(o.log) + 8, **{k: v for k, v in kw.items() if k != "init_hi"})
+    assert g.info["iters_done"] == o.stats["iters_done"]
+    _compare(g, o)
 
 
 def test_fit_nan_in_unobserved_cells(S):

@@ -134,3 +134,22 @@ def test_update_rejects_unobserved_cell(S):
     with pytest.raises(S.StmfError) as ex:
         S.stmf_update_U(_t(Rn), _t(M), _t(U), _t(V), 2, 3, 0)
     assert ex.value.status == S.STMF_EINVAL
+
+
+@pytest.mark.parametrize("line", ["row", "col"])
+@pytest.mark.parametrize("op", ["U", "V"])
+def test_update_rejects_empty_line_before_writing(S, line, op):
+    # a residual over a line with no observed cell is undefined: the update
+    # calls refuse such a mask before launching anything (U, V untouched)
+    U, V, R, Rn, M = _case(8, 9, 2, 5, True)
+    if line == "row":
+        M[4, :] = 0
+    else:
+        M[:, 6] = 0
+    Ud, Vd = _t(U), _t(V)
+    fn = S.stmf_update_U if op == "U" else S.stmf_update_V
+    with pytest.raises(S.StmfError) as ex:
+        fn(_t(Rn), _t(M), Ud, Vd, 0, 0, 1)
+    assert ex.value.status == S.STMF_EEMPTY_LINE
+    np.testing.assert_array_equal(Ud.cpu().numpy(), U)
+    np.testing.assert_array_equal(Vd.cpu().numpy(), V)
