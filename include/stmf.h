@@ -78,6 +78,21 @@ int stmf_masked_error(const float* R, const uint8_t* M, const float* U,
                       const float* V, int m, int n, int r, double* err,
                       double* td_col, void* ws, size_t ws_bytes, void* stream);
 
+/* stmf_masked_error without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation).  Same arguments (minus ws, ws_bytes), kernels and
+ * result bits as stmf_masked_error.  Its scratch is a static device array
+ * of 8 MiB per device, held from the library's load until the process ends:
+ * shapes whose partials need more (ceil(m/64) * ceil(n/64) * 64 doubles
+ * above 2^20, e.g. m = n = 8192 fits, m = 8192, n = 8256 does not) return
+ * STMF_ENOMEM before any work is queued.  No call allocates: the first call
+ * on a device only looks up the array's device address.  Every call on a
+ * device shares that device's array, so calls that overlap on one device
+ * (on different streams, or from several threads) race and must be
+ * serialised by the caller. */
+int stmf_masked_error_noalloc(const float* R, const uint8_t* M, const float* U,
+                              const float* V, int m, int n, int r, double* err,
+                              double* td_col, void* stream);
 
 /* Workspace bytes of stmf_update_U / stmf_update_V. */
 size_t stmf_update_workspace(int m, int n, int r);

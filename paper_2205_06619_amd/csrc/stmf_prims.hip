@@ -9,6 +9,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
+#include "stmf.h"
 #include "stmf_internal.h"
 
 namespace stmf {
@@ -191,4 +194,45 @@ hipError_t launch_update(int op, const float* R, const uint8_t* M, float* U, flo
   return launch_masked_error(R, M, U, V, m, n, r, err, nullptr, ws, s);
 }
 
+// ---------------------------------------------------------------- no allocation
+// Scratch of stmf_masked_error_noalloc: the per (row tile, column) partials,
+// up to NOALLOC_PARTIALS doubles (8 MiB; every device the library runs on
+// holds its own copy until the process ends).  Its device address is looked
+// up once per device, with that device current; the host-side name is never
+// passed to a kernel or a copy.
+static constexpr size_t NOALLOC_PARTIALS = (size_t)1 << 20;
+static __device__ __align__(256) double scratch[NOALLOC_PARTIALS];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];
+
+static int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return STMF_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return STMF_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return STMF_OK;
+}
+
 }  // namespace stmf
+
+extern "C" int stmf_masked_error_noalloc(const float* R, const uint8_t* M, const float* U,
+                                         const float* V, int m, int n, int r, double* err,
+                                         double* td_col, void* stream) {
+  using namespace stmf;
+  if (!R || !M || !U || !V || !err || m < 1 || n < 1 || r < 1 || r > RMAX) return STMF_EINVAL;
+  // the partials of this shape must fit the static scratch
+  if (masked_error_ws(m, n) > sizeof(scratch)) return STMF_ENOMEM;
+  void* ws = nullptr;
+  const int st = scratch_address(&ws);
+  if (st) return st;
+  // every partial the final reduction reads is written first: nothing to clear
+  if (launch_masked_error(R, M, U, V, m, n, r, err, td_col, ws, (hipStream_t)stream) != hipSuccess)
+    return STMF_EHIP;
+  return STMF_OK;
+}

@@ -29,6 +29,7 @@ EXPORTS = (
     "stmf_job_footprint", "stmf_engine_admit", "stmf_batch_tick", "stmf_engine_poll",
     "stmf_engine_retire", "stmf_engine_set_graph", "stmf_dcor_workspace", "stmf_distance_correlation",
     "stmf_completion_metrics_workspace", "stmf_completion_metrics", "stmf_engine_job_footprint",
+    "stmf_masked_error_noalloc",
 )
 
 
@@ -92,6 +93,7 @@ def _load():
         "stmf_maxplus_product": ([P, P, I, I, I, P, P, P], I),
         "stmf_masked_error_workspace": ([I, I, I], Z),
         "stmf_masked_error": ([P, P, P, P, I, I, I, P, P, P, Z, P], I),
+        "stmf_masked_error_noalloc": ([P, P, P, P, I, I, I, P, P, P], I),
         "stmf_update_workspace": ([I, I, I], Z),
         "stmf_update_U": ([P, P, P, P, I, I, I, I, I, I, P, P, P, P, Z, P], I),
         "stmf_update_V": ([P, P, P, P, I, I, I, I, I, I, P, P, P, P, Z, P], I),
@@ -209,6 +211,24 @@ def stmf_masked_error(R, M, U, V, td_col=None, ws=None, stream=None):
         td_col = torch.empty(n, dtype=torch.float64, device=R.device)
     _chk(lib.stmf_masked_error(_ptr(R), _ptr(M), _ptr(U), _ptr(V), m, n, r, _ptr(err), _ptr(td_col),
                                _ptr(ws), ws.numel(), _stream(stream)), "stmf_masked_error")
+    return err, td_col
+
+
+def stmf_masked_error_noalloc(R, M, U, V, err=None, td_col=None, stream=None):
+    """Masked b-norm through the entry point that allocates nothing (its
+    scratch is the library's static device array); err and td_col are
+    allocated here when None.  Returns (err tensor (1,), td_col (n,))."""
+    torch = _torch()
+    m, n = R.shape
+    r = U.shape[1]
+    _check(R, torch.float32, (m, n), "R"); _check(M, torch.uint8, (m, n), "M")
+    _check(U, torch.float32, (m, r), "U"); _check(V, torch.float32, (r, n), "V")
+    if err is None:
+        err = torch.empty(1, dtype=torch.float64, device=R.device)
+    if td_col is None:
+        td_col = torch.empty(n, dtype=torch.float64, device=R.device)
+    _chk(lib.stmf_masked_error_noalloc(_ptr(R), _ptr(M), _ptr(U), _ptr(V), m, n, r, _ptr(err),
+                                       _ptr(td_col), _stream(stream)), "stmf_masked_error_noalloc")
     return err, td_col
 
 
