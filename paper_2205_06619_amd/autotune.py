@@ -3,12 +3,16 @@
 The fit kernel's tiles are 64 x 64; what changes its speed on a given shape
 is the speculative batch: how many trials the first batch of a row visit
 evaluates (``batch_first``) and the largest batch (``batch_max``, which also
-sizes the trial buffers).  Neither changes a result (every fit is identical
-for any batch shape), so the tuner only times: for a shape bucket it runs a
-short prefix of a fit (a few passes' worth of row visits) with each
-candidate and keeps the fastest; for a batched workload it times the batched
-launch on a sample of the problems.  Choices are cached in a JSON file keyed
-by bucket, so a shape is tuned once.
+sizes the trial buffers), and for batched fits the number of workgroups
+each fit runs on (``group_size``: the persistent launch is cut into groups
+of that many workgroups, each taking fits from a queue).  None of them
+changes a result (every fit is identical for any batch shape and group
+size), so the tuner only times: for a shape bucket it runs a short prefix of
+a fit (a few passes' worth of row visits) with each candidate and keeps the
+fastest; for a batched workload it times the batched launch on a sample of
+the problems, first over group sizes, then over batch shapes at the best
+group size.  Choices are cached in a JSON file keyed by bucket, so a shape
+is tuned once.
 
 Buckets: the working shape (m' = min(m, n), n' = max(m, n)) and the rank,
 each rounded up to a power of two.
@@ -25,6 +29,7 @@ CANDIDATES: Tuple[Tuple[int, int], ...] = (
     (0, 256), (16, 256), (64, 256),
     (0, 1024), (64, 1024), (256, 1024),
 )
+GROUP_SIZES: Tuple[int, ...] = (1, 2, 4, 8, 16)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "stmf_autotune.json")
 
 
@@ -108,29 +113,45 @@ def tune_fit(R, M, rank: int, passes: int = 2, seed: int = 0, cache: Optional[Ca
     return {"batch_first": bf, "batch_max": bm}
 
 
+def sample_problems(problems: List[dict], sample: int) -> List[dict]:
+    """`sample` problems spread over the population ordered by size (the
+    largest, the smallest and evenly between), in that order."""
+    order = sorted(problems, key=lambda p: -p["R"].numel())
+    if sample >= len(order):
+        return order
+    step = (len(order) - 1) / max(sample - 1, 1)
+    return [order[round(q * step)] for q in range(sample)]
+
+
 def tune_batched(problems: List[dict], restarts: int = 1, sample: int = 16, iters: int = 2,
                  cache: Optional[Cache] = None, key: Optional[str] = None,
-                 candidates: Sequence[Tuple[int, int]] = CANDIDATES, **opts) -> dict:
-    """Launch shape for a batched workload: each candidate runs the batched
-    launch on the `sample` largest problems for `iters` passes; the wall time
-    of the call decides.  Returns {batch_first, batch_max}."""
+                 candidates: Sequence[Tuple[int, int]] = CANDIDATES,
+                 group_sizes: Sequence[int] = GROUP_SIZES, **opts) -> dict:
+    """Launch shape for a batched workload: the batched launch on `sample`
+    problems spread over the population's sizes, with its restarts, for
+    `iters` passes; the wall time of the call decides, first among the group
+    sizes (default batches), then among the batch shapes at the best group
+    size.  Returns {group_size, batch_first, batch_max}."""
     import torch
     from . import stmf
+    fields = ("group_size", "batch_first", "batch_max")
     if cache is not None and key and cache.get(key):
         c = cache.get(key)
-        return {"batch_first": c["batch_first"], "batch_max": c["batch_max"]}
-    big = sorted(problems, key=lambda p: -p["R"].numel())[:sample]
-    probe = [dict(p, iters=iters) for p in big]
+        return {f: c[f] for f in fields}
+    probe = [dict(p, iters=iters) for p in sample_problems(problems, sample)]
 
-    def timer(bf, bm):
+    def run(gs, bf, bm):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        stmf.stmf_fit_batched(probe, restarts=1, batch_first=bf, batch_max=bm, **opts)
+        stmf.stmf_fit_batched(probe, restarts=restarts, group_size=gs, batch_first=bf,
+                              batch_max=bm, **opts)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3
 
-    timer(0, 0)  # first call pays the workspace allocation
-    (bf, bm), times = choose(candidates, timer)
+    run(group_sizes[0], 0, 0)  # first call pays the workspace allocation
+    (gs, _), gtimes = choose([(g, 0) for g in group_sizes], lambda g, _: run(g, 0, 0))
+    (bf, bm), times = choose(candidates, lambda bf, bm: run(gs, bf, bm))
     if cache is not None and key:
-        cache.put(key, {"batch_first": bf, "batch_max": bm, "times_ms": times})
-    return {"batch_first": bf, "batch_max": bm}
+        cache.put(key, {"group_size": gs, "batch_first": bf, "batch_max": bm,
+                        "group_times_ms": gtimes, "times_ms": times})
+    return {"group_size": gs, "batch_first": bf, "batch_max": bm}

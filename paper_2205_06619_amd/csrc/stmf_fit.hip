@@ -2213,6 +2213,7 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
     tmark = now;
   };
   int seg_t = d.t0;  // ByElement, ByMatrix: first batch of the next segment or round
+  int last_trials = 0;  // ByRow: trials the last row visit needed (0: none yet)
   while (MODE == 2 && phase == 1) {
     // one ByMatrix iteration per step (counted as a row visit)
     if (max_rows > 0 && rows_done >= max_rows) break;
@@ -2247,9 +2248,11 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
       lap(0);
       // SEQ evaluates every trial of the row: full batches, the best one kept
       const bool seq = sel == SEL_SEQ;
-      // first batch: sized from the trials this row's previous visit needed
-      // (batch sizes change which trials are evaluated speculatively, never
-      // the outcome)
+      // first batch: sized from the trials this row's previous visit needed,
+      // or on a row's first visit from the trials the last row visit needed
+      // (at least t0, the batch whose evaluation costs about what a batch's
+      // fixed steps do); batch sizes change which trials are evaluated
+      // speculatively, never the outcome
       const int prev_trials = ld_atomic(&d.rowt[i]);
       int T = d.t0;
       if (seq) {
@@ -2257,6 +2260,8 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
       } else if (prev_trials > 0) {
         T = 16;
         while (T < prev_trials) T *= 2;
+      } else {
+        while (T < last_trials) T *= 2;
       }
       if (T > d.tmax) T = d.tmax;  // the trial buffers hold tmax trials
       long long row_trials = 0, row_noops = 0, row_spec = 0;
@@ -2325,7 +2330,8 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
         par ^= 1;
       }
       if (acc_j >= 0) ++acc_pass;
-      if (gp.g == 0 && gp.tid == 0) st_coh(&d.rowt[i], (int)(row_trials > 0 ? row_trials : 1));
+      last_trials = (int)(row_trials > 0 ? row_trials : 1);
+      if (gp.g == 0 && gp.tid == 0) st_coh(&d.rowt[i], last_trials);
       book(gp, it, i, row_trials, row_noops, row_spec, acc_j, acc_k, acc_op, e_cur);
     }
     if (gp.g == 0 && gp.tid == 0) ctl->row_visits += 1;
@@ -2356,32 +2362,42 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
   group_sync(gp, S);
 }
 
-// Which fit each workgroup works on.  With a queue (batched fits), every
-// workgroup takes fits from it one after another, one workgroup per fit.
-// Without one, the fits own consecutive ranges of the grid, fits[f].gsize
-// workgroups each in table order (one fit over the whole grid, or several
-// fits side by side), and a workgroup beyond the last range has nothing to do.
-// fit_run has one call site, so it is expanded once per kernel.
+// Which fit each workgroup works on.  With a queue (batched fits) the grid
+// is cut into groups of qgroup workgroups; each group takes fits from the
+// queue one after another (its first workgroup takes the next index and
+// publishes it through the group's control block gctl[group], behind a
+// group barrier) and runs each on its qgroup workgroups; a group leaves once
+// the queue is exhausted.  Without a queue the fits own consecutive ranges
+// of the grid, fits[f].gsize workgroups each in table order (one fit over
+// the whole grid, or several side by side), and a workgroup beyond the last
+// range has nothing to do.  fit_run has one call site, so it is expanded
+// once per kernel.
 template <int MODE>
 DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int max_rows,
-                         unsigned* __restrict__ queue) {
+                         unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl) {
   extern __shared__ __align__(16) char smem_raw[];
   Smem& S = *reinterpret_cast<Smem*>(smem_raw);
   Grp gp;
   gp.tid = threadIdx.x;
   gp.lane = threadIdx.x & 63;
   gp.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  __shared__ int fid_s;
   int b = (int)blockIdx.x;
   while (true) {
     int fid;
     if (queue) {
-      if (gp.tid == 0) fid_s = (int)atomicAdd(queue, 1u);
-      __syncthreads();
-      fid = fid_s;
-      __syncthreads();
-      gp.g = 0;
-      gp.G = 1;
+      // the group's own barrier, on its control block
+      Grp gq = gp;
+      gq.g = b % qgroup;
+      gq.G = qgroup;
+      gq.d = nullptr;
+      gq.ctl = (GA FitCtl*)(gctl + b / qgroup);
+      if (gq.g == 0 && gq.tid == 0) st_coh(&gq.ctl->decision, (int)atomicAdd(queue, 1u));
+      if (!group_sync(gq, S)) break;
+      fid = ld_atomic(&gq.ctl->decision);
+      // every workgroup has read the index before the next one is taken
+      if (!group_sync(gq, S)) break;
+      gp.g = gq.g;
+      gp.G = qgroup;
     } else {
       if (b < 0) break;
       fid = 0;
@@ -2400,30 +2416,30 @@ DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int max_row
 // FastSTMF (TD_A) fits.
 __global__ void __launch_bounds__(NTHR) fit_kernel(const FitDev* __restrict__ fits, int nfits,
                                                    int max_rows,
-                                                   unsigned* __restrict__ queue) {
-  fit_kernel_body<0>(fits, nfits, max_rows, queue);
+                                                   unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl) {
+  fit_kernel_body<0>(fits, nfits, max_rows, queue, qgroup, gctl);
 }
 
 // Fits with any ByRow selection (all fits of one launch share it).
 __global__ void __launch_bounds__(NTHR) fit_kernel_sel(const FitDev* __restrict__ fits, int nfits,
                                                        int max_rows,
-                                                       unsigned* __restrict__ queue) {
-  fit_kernel_body<1>(fits, nfits, max_rows, queue);
+                                                       unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl) {
+  fit_kernel_body<1>(fits, nfits, max_rows, queue, qgroup, gctl);
 }
 
 // FastSTMF (TD_A) fits on matrices wider than SORT_MAX columns (the same
 // fit; the column order ranked with every thread counting).
 __global__ void __launch_bounds__(NTHR) fit_kernel_wide(const FitDev* __restrict__ fits, int nfits,
                                                         int max_rows,
-                                                        unsigned* __restrict__ queue) {
-  fit_kernel_body<3>(fits, nfits, max_rows, queue);
+                                                        unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl) {
+  fit_kernel_body<3>(fits, nfits, max_rows, queue, qgroup, gctl);
 }
 
 // ByMatrix fits.
 __global__ void __launch_bounds__(NTHR) fit_kernel_matrix(const FitDev* __restrict__ fits,
                                                           int nfits, int max_rows,
-                                                          unsigned* __restrict__ queue) {
-  fit_kernel_body<2>(fits, nfits, max_rows, queue);
+                                                          unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl) {
+  fit_kernel_body<2>(fits, nfits, max_rows, queue, qgroup, gctl);
 }
 
 size_t fit_smem_bytes() { return sizeof(Smem); }

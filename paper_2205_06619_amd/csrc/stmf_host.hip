@@ -15,10 +15,14 @@
 namespace stmf {
 
 // kernels (stmf_fit.hip, stmf_prims.hip, stmf_setup.hip)
-__global__ void fit_kernel(const FitDev* fits, int nfits, int max_rows, unsigned* queue);
-__global__ void fit_kernel_sel(const FitDev* fits, int nfits, int max_rows, unsigned* queue);
-__global__ void fit_kernel_matrix(const FitDev* fits, int nfits, int max_rows, unsigned* queue);
-__global__ void fit_kernel_wide(const FitDev* fits, int nfits, int max_rows, unsigned* queue);
+__global__ void fit_kernel(const FitDev* fits, int nfits, int max_rows, unsigned* queue, int qgroup,
+                           FitCtl* gctl);
+__global__ void fit_kernel_sel(const FitDev* fits, int nfits, int max_rows, unsigned* queue,
+                               int qgroup, FitCtl* gctl);
+__global__ void fit_kernel_matrix(const FitDev* fits, int nfits, int max_rows, unsigned* queue,
+                                  int qgroup, FitCtl* gctl);
+__global__ void fit_kernel_wide(const FitDev* fits, int nfits, int max_rows, unsigned* queue,
+                                int qgroup, FitCtl* gctl);
 size_t fit_smem_bytes();
 size_t masked_error_ws(int m, int n);
 hipError_t launch_maxplus(const float*, const float*, int, int, int, float*, int32_t*, hipStream_t);
@@ -43,7 +47,6 @@ __global__ void output_kernel(const float*, const float*, int, int, int, int, in
                               const int*,
                               float*, float*);
 __global__ void copy_f64_kernel(const double*, double*, int);
-__global__ void fit_done_kernel(const FitDev*, int, int*);
 
 // ---------------------------------------------------------------- randomness
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): a Weyl sequence with step
@@ -228,21 +231,20 @@ static void make_layout(int m, int n, int r, int iters, int G, int acol_p, int b
   L.total = o;
 }
 
-// First batch of a row visit when the caller leaves it to the library.  A
-// batch costs its synchronisation and, for every tile a workgroup sweeps,
-// the tile's staging plus the trials' evaluation; trials after the accepted
-// one are wasted.  The first batch shrinks as each workgroup's share of
-// tiles grows: 512 / tiles per workgroup, a power of two, at least 4.  A
-// group also pays three group barriers per batch, which fewer than 64 trials
-// do not amortise: its first batch is at least 64.  Never above the largest
-// batch.  (On the 2000 x 20000 rank-20 fit, 40 tiles per workgroup, a first
-// batch of 64 rather than 8 took a pass from 5.2-5.4 s to 4.7-4.9 s.)
+// Smallest first batch of a row visit when the caller leaves it to the
+// library.  A batch costs its synchronisation and, for every tile a
+// workgroup sweeps, the tile's staging plus the trials' evaluation; trials
+// after the accepted one are wasted.  The floor shrinks as each workgroup's
+// share of tiles grows: 512 / tiles per workgroup, a power of two, at least
+// 4, never above the largest batch.  A row's first visit starts at the
+// power of two at or above the trials the last row visit needed, if that is
+// more (the first pass of a fit that accepts early, on groups that sweep many
+// tiles, wastes little); later visits from the row's own previous visit.
 static int auto_batch_first(const Layout& L) {
   const int tiles = L.nrt * L.nct;
   const int per = (tiles + L.G - 1) / L.G;
   int t = 4;
   while (t * 2 <= 512 / per && t * 2 <= L.tmax) t *= 2;
-  if (L.G > 1 && t < 64) t = 64;
   return std::min(t, L.tmax);
 }
 
@@ -455,22 +457,26 @@ static int launch_output(const Layout& L, char* base, float* U_out, float* V_out
 
 // sel: the ByRow selection of every fit of the launch (TD_A runs the kernel
 // compiled for it alone, in its own build for launches with a fit wider than
-// SORT_MAX columns: `wide`).  queue: batched launches (one workgroup per fit,
-// fits taken from the queue); null: the fits own consecutive ranges of
-// gsize workgroups.  Every launch is a plain one whose grid stays within the
-// co-resident count (one fit-kernel workgroup per CU: its LDS takes most of
-// a CU's), so on an otherwise idle device every group is resident at once;
-// the group barrier's bounded wait turns anything else into STMF_ETIMEOUT.
-// (No cooperative launch: it adds nothing the bounded wait does not cover,
-// and a process that made one ended with a segmentation fault at exit under
-// the profiler.)
+// SORT_MAX columns: `wide`).  queue: the grid is cut into groups of qgroup
+// workgroups that take fits from the queue one after another, each group
+// publishing its fit through its control block in gctl (zeroed before the
+// launch); null: the fits own consecutive ranges of gsize workgroups.  Every
+// launch is a plain one whose grid stays within the co-resident count (one
+// fit-kernel workgroup per CU: its LDS takes most of a CU's), so on an
+// otherwise idle device every group is resident at once; the group
+// barrier's bounded wait turns anything else into STMF_ETIMEOUT.  (No
+// cooperative launch: it adds nothing the bounded wait does not cover, and
+// a process that made one ended with a segmentation fault at exit under the
+// profiler.)
 static int launch_fit_kernel(const FitDev* dev_fits, int nfits, int grid, int max_rows,
-                             unsigned* queue, int sel, bool wide, hipStream_t s) {
+                             unsigned* queue, int qgroup, FitCtl* gctl, int sel, bool wide,
+                             hipStream_t s) {
   const size_t smem = fit_smem_bytes();
   const void* k = sel == SEL_TD_A     ? (wide ? (const void*)fit_kernel_wide : (const void*)fit_kernel)
                   : sel == SEL_MATRIX ? (const void*)fit_kernel_matrix
                                       : (const void*)fit_kernel_sel;
-  void* args[] = {(void*)&dev_fits, (void*)&nfits, (void*)&max_rows, (void*)&queue};
+  void* args[] = {(void*)&dev_fits, (void*)&nfits, (void*)&max_rows, (void*)&queue,
+                  (void*)&qgroup,   (void*)&gctl};
   HIPCHK(hipLaunchKernel(k, dim3(grid), dim3(NTHR), args, smem, s));
   return STMF_OK;
 }
@@ -667,8 +673,8 @@ int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters
   HIPCHK(hipEventCreate(&ev0));
   HIPCHK(hipEventCreate(&ev1));
   HIPCHK(hipEventRecord(ev0, s));
-  st = launch_fit_kernel((const FitDev*)(base + L.dev), 1, G, o.max_row_visits, nullptr,
-                         kernel_sel(o), L.nw > SORT_MAX, s);
+  st = launch_fit_kernel((const FitDev*)(base + L.dev), 1, G, o.max_row_visits, nullptr, 1,
+                         nullptr, kernel_sel(o), L.nw > SORT_MAX, s);
   if (st) { (void)hipEventDestroy(ev0); (void)hipEventDestroy(ev1); return st; }
   HIPCHK(hipEventRecord(ev1, s));
   FitCtl c;
@@ -699,27 +705,58 @@ struct BatchPlan {
   std::vector<size_t> off;     // workspace offset of each fit
   std::vector<int> prob;       // problem of each fit
   std::vector<uint64_t> seed;  // seed of each fit
-  bool grouped = false;        // some fit runs on more than one workgroup
-  size_t table, queue, done, total;
+  int qgroup = 1;              // workgroups per group of the persistent launch
+  int ngroups = 1;             // groups in the launch
+  size_t table, queue, gctl, total;
 };
 
-// A fit's group: the smaller of group_size (0: the co-resident count) and
-// its tile count, as stmf_fit chooses it.
+// Estimated work of a fit, for ordering the queue (largest first) and
+// sizing groups: rows visited per pass x tiles swept per trial x rank.
+static double fit_work(const Layout& L) {
+  return (double)L.mw * (double)(L.nrt * L.nct) * (double)L.r;
+}
+
+// Workgroups per fit when the caller leaves it to the library.  A fit's time
+// scales with its group (measured: the same CU-time on groups of 4 to 64),
+// so with fits handed out largest first the launch ends no sooner than
+// W / (co-resident count) or w_max / G (W the total, w_max the largest
+// fit's work).  G is the power of two at or above 4 co-resident w_max / W
+// (a margin for the work estimate), between 1 and 64 and at most the largest
+// fit's tiles.
+static int auto_qgroup(double w_total, double w_max, int max_tiles, int coresident) {
+  const double want = 4.0 * coresident * w_max / std::max(w_total, 1.0);
+  int g = 1;
+  while (g < want && g * 2 <= 64 && g * 2 <= max_tiles) g *= 2;
+  return g;
+}
+
 static void plan_batched(const stmf_problem* probs, int nprob, int restarts, const stmf_options& o,
                          int coresident, BatchPlan& B) {
-  const int gcap = o.group_size > 0 ? std::min(o.group_size, coresident) : coresident;
+  const int F = nprob * restarts;
+  int max_tiles = 1;
+  double w_total = 0.0, w_max = 0.0;
+  for (int p = 0; p < nprob; ++p) {
+    Layout L;
+    make_layout(probs[p].m, probs[p].n, probs[p].rank, probs[p].iters, 1, o.acol_p, o.batch_max, L);
+    max_tiles = std::max(max_tiles, L.nrt * L.nct);
+    w_total += restarts * fit_work(L);
+    w_max = std::max(w_max, fit_work(L));
+  }
+  B.qgroup = o.group_size > 0 ? std::min(o.group_size, coresident)
+                              : auto_qgroup(w_total, w_max, max_tiles, coresident);
+  B.ngroups = std::max(1, std::min(coresident / B.qgroup, F));
   size_t o_ = 0;
   for (int p = 0; p < nprob; ++p) {
     Rng g{probs[p].seed};
     for (int q = 0; q < restarts; ++q) {
+      // a fit's layout takes its group (the batch sizes depend on it; its
+      // results do not)
       Layout L;
       make_layout(probs[p].m, probs[p].n, probs[p].rank, probs[p].iters, 1, o.acol_p, o.batch_max, L);
-      const int G = std::min(gcap, L.nrt * L.nct);
-      if (G > 1) {
+      const int G = std::min(B.qgroup, L.nrt * L.nct);
+      if (G > 1)
         make_layout(probs[p].m, probs[p].n, probs[p].rank, probs[p].iters, G, o.acol_p,
                     o.batch_max, L);
-        B.grouped = true;
-      }
       B.L.push_back(L);
       B.off.push_back(o_);
       B.prob.push_back(p);
@@ -731,8 +768,8 @@ static void plan_batched(const stmf_problem* probs, int nprob, int restarts, con
   o_ += al256(B.L.size() * sizeof(FitDev));
   B.queue = o_;
   o_ += 256;
-  B.done = o_;
-  o_ += al256(B.L.size() * sizeof(int));
+  B.gctl = o_;
+  o_ += al256((size_t)B.ngroups * sizeof(FitCtl));
   B.total = o_;
 }
 
@@ -743,50 +780,36 @@ static bool any_wide(const FitDev* fits, int n) {
   return false;
 }
 
-// Grouped fits to completion in rounds: each round packs the unfinished fits
-// (longest first) side by side into launches of at most the co-resident
-// workgroups, advances each by at most BATCH_ROUND_ROWS row visits, and
-// drops the fits that finished.  A fit's result does not depend on the
-// rounds (its state is kept between launches).  The device table holds the
-// unfinished fits, rewritten when that set changes.
-static constexpr int BATCH_ROUND_ROWS = 64;
-
-static int run_grouped(std::vector<FitDev> active, int coresident, char* table_dev, int* done_dev,
-                       int sel, hipStream_t s) {
-  std::vector<int> done;
-  bool upload = true;
-  while (!active.empty()) {
-    const int n = (int)active.size();
-    if (upload) {
-      HIPCHK(hipMemcpyAsync(table_dev, active.data(), (size_t)n * sizeof(FitDev),
-                            hipMemcpyHostToDevice, s));
-      upload = false;
-    }
-    const FitDev* t = (const FitDev*)table_dev;
-    int first = 0, grid = 0;
-    for (int f = 0; f <= n; ++f) {
-      if (f == n || grid + active[f].gsize > coresident) {
-        int st = launch_fit_kernel(t + first, f - first, grid, BATCH_ROUND_ROWS, nullptr, sel,
-                                   any_wide(active.data() + first, f - first), s);
-        if (st) return st;
-        first = f;
-        grid = 0;
-      }
-      if (f < n) grid += active[f].gsize;
-    }
-    hipLaunchKernelGGL(fit_done_kernel, dim3((n + 255) / 256), dim3(256), 0, s, t, n, done_dev);
-    HIPCHK(hipGetLastError());
-    done.assign(n, 0);
-    HIPCHK(hipMemcpyAsync(done.data(), done_dev, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    std::vector<FitDev> left;
-    for (int f = 0; f < n; ++f)
-      if (!done[f]) left.push_back(active[f]);
-    if ((int)left.size() != n) {
-      active.swap(left);
-      upload = true;
-    }
+// The device side of a batched call, recorded on stream c: queue and group
+// control blocks cleared by fill kernels, the persistent fit launch, then the
+// output (un-permuted, un-transposed factors) and trajectory of every fit.
+static int record_batched(const BatchPlan& B, const std::vector<int>& fit_ids,
+                          const std::vector<FitDev>& table, stmf_problem* probs, int restarts,
+                          char* base, int sel, hipStream_t c) {
+  int st = fill_u32(base + B.queue, 1, 0, c);
+  if (!st) st = fill_u32(base + B.gctl, (size_t)B.ngroups * sizeof(FitCtl) / 4, 0, c);
+  if (st) return st;
+  const int n = (int)table.size();
+  const int ngroups = std::min(B.ngroups, n);
+  st = launch_fit_kernel((const FitDev*)(base + B.table), n, ngroups * B.qgroup, 0,
+                         (unsigned*)(base + B.queue), B.qgroup, (FitCtl*)(base + B.gctl), sel,
+                         any_wide(table.data(), n), c);
+  if (st) return st;
+  for (int f : fit_ids) {
+    const Layout& L = B.L[f];
+    char* fb = base + B.off[f];
+    const int p = B.prob[f];
+    const int q = f - p * restarts;
+    float* Uo = probs[p].U_out + (size_t)q * L.m * L.r;
+    float* Vo = probs[p].V_out + (size_t)q * L.r * L.n;
+    st = launch_output(L, fb, Uo, Vo, c);
+    if (st) return st;
+    if (probs[p].err_traj)
+      hipLaunchKernelGGL(copy_f64_kernel, dim3((L.iters + 1 + 255) / 256), dim3(256), 0, c,
+                         (const double*)(fb + L.traj), probs[p].err_traj + (size_t)q * (L.iters + 1),
+                         L.iters + 1);
   }
+  HIPCHK(hipGetLastError());
   return STMF_OK;
 }
 
@@ -847,50 +870,56 @@ int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts, const stmf_op
     if (s2) { probs[p].status = s2; continue; }
     fit_ids.push_back(f);
   }
-  // longest fits first
-  std::stable_sort(fit_ids.begin(), fit_ids.end(), [&](int a, int b) {
-    const Layout& A = B.L[a];
-    const Layout& C = B.L[b];
-    return (double)A.mw * A.nw * A.r > (double)C.mw * C.nw * C.r;
-  });
+  // largest fits first (the queue hands them out in table order)
+  std::stable_sort(fit_ids.begin(), fit_ids.end(),
+                   [&](int a, int b) { return fit_work(B.L[a]) > fit_work(B.L[b]); });
   for (int f : fit_ids) table.push_back(make_dev(B.L[f], base + B.off[f], o, observed[B.prob[f]]));
-  if (!table.empty() && B.grouped) {
-    st = run_grouped(table, P.coresident, base + B.table, (int*)(base + B.done), kernel_sel(o), s);
-    if (st) return st;
-  } else if (!table.empty()) {
+  if (!table.empty()) {
     HIPCHK(hipMemcpyAsync(base + B.table, table.data(), table.size() * sizeof(FitDev),
                           hipMemcpyHostToDevice, s));
-    st = fill_u32(base + B.queue, 1, 0, s);
-    if (st) return st;
-    const int grid = std::min<int>((int)table.size(), P.coresident);
-    st = launch_fit_kernel((const FitDev*)(base + B.table), (int)table.size(), grid, 0,
-                           (unsigned*)(base + B.queue), kernel_sel(o),
-                           any_wide(table.data(), (int)table.size()), s);
-    if (st) return st;
+    // the whole device side (one persistent launch and the outputs) as one
+    // captured graph, launched on the caller's stream
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    auto cleanup = [&]() {
+      if (gexec) (void)hipGraphExecDestroy(gexec);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (cap) (void)hipStreamDestroy(cap);
+    };
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) { cleanup(); return STMF_EHIP; }
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      cleanup();
+      return STMF_EHIP;
+    }
+    st = record_batched(B, fit_ids, table, probs, restarts, base, kernel_sel(o), cap);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(cap, &g);
+    graph = g;
+    if (st || ce != hipSuccess) { cleanup(); return st ? st : STMF_EHIP; }
+    if (hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess ||
+        hipGraphLaunch(gexec, s) != hipSuccess) {
+      cleanup();
+      return STMF_EHIP;
+    }
+    const hipError_t se = hipStreamSynchronize(s);  // host staging vectors go out of scope after this
+    cleanup();
+    if (se != hipSuccess) return STMF_EHIP;
+  } else {
+    HIPCHK(hipStreamSynchronize(s));
   }
-  HIPCHK(hipStreamSynchronize(s));  // host staging vectors go out of scope after this
   if (info) std::memset(info, 0, sizeof(*info));
   for (int f : fit_ids) {
     const Layout& L = B.L[f];
     char* fb = base + B.off[f];
     const int p = B.prob[f];
-    const int q = f - p * restarts;
     FitCtl c;
     HIPCHK(hipMemcpyAsync(&c, fb + L.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (c.status) { probs[p].status = c.status == STMF_ETIMEOUT ? STMF_ETIMEOUT : STMF_EHIP; continue; }
-    float* Uo = probs[p].U_out + (size_t)q * L.m * L.r;
-    float* Vo = probs[p].V_out + (size_t)q * L.r * L.n;
-    st = launch_output(L, fb, Uo, Vo, s);
-    if (st) return st;
-    if (probs[p].err_traj)
-      hipLaunchKernelGGL(copy_f64_kernel, dim3((L.iters + 1 + 255) / 256), dim3(256), 0, s,
-                         (const double*)(fb + L.traj), probs[p].err_traj + (size_t)q * (L.iters + 1),
-                         L.iters + 1);
     fill_info(info, c, L);
   }
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(s));
+  if (info) info->group_size = B.qgroup;
   return STMF_OK;
 }
 
@@ -915,7 +944,7 @@ struct stmf_engine {
   int gcap = 1;        // workgroups per job, at most
   int coresident = 0;  // fit-kernel workgroups resident at once
   stmf_options opt;
-  size_t table_off = 0, queue_off = 0, heap_off = 0;
+  size_t table_off = 0, queue_off = 0, gctl_off = 0, heap_off = 0;
   struct Slot {
     bool used = false;
     size_t off = 0, len = 0;
@@ -1003,11 +1032,13 @@ int stmf_engine_create(void* ws, size_t ws_bytes, int max_slots, const stmf_opti
   if (o.decision_log || o.perm || o.init_mode == 2 || o.max_row_visits) return STMF_EINVAL;
   if (o.strategy == 2) return STMF_EINVAL;  // ByMatrix runs through stmf_fit only
   if (!ws || ((uintptr_t)ws & 255)) return STMF_ENOMEM;
-  const size_t table = al256((size_t)max_slots * sizeof(FitDev));
-  if (ws_bytes < table + 256 + 256) return STMF_ENOMEM;
   DevProps P;
   st = device_props(P);
   if (st) return st;
+  const size_t table = al256((size_t)max_slots * sizeof(FitDev));
+  // control blocks of the one-workgroup groups of a queue launch
+  const size_t gctl = al256((size_t)P.coresident * sizeof(FitCtl));
+  if (ws_bytes < table + 256 + gctl + 256) return STMF_ENOMEM;
   stmf_engine* e = new (std::nothrow) stmf_engine();
   if (!e) return STMF_ENOMEM;
   e->arena = (char*)ws;
@@ -1019,7 +1050,8 @@ int stmf_engine_create(void* ws, size_t ws_bytes, int max_slots, const stmf_opti
   e->opt = o;
   e->table_off = 0;
   e->queue_off = table;
-  e->heap_off = table + 256;
+  e->gctl_off = table + 256;
+  e->heap_off = table + 256 + gctl;
   e->slots.resize(max_slots);
   e->free_list.push_back({e->heap_off, (ws_bytes - e->heap_off) / 256 * 256});
   *out = e;
@@ -1073,13 +1105,17 @@ static int tick_work(stmf_engine* e, const std::vector<int>& plan, int max_rows,
     const bool wide = plan[q + 3] != 0;
     int st;
     if (grid < 0) {
+      const int groups = std::min(count, e->coresident);
       st = fill_u32(e->arena + e->queue_off, 1, 0, s);
+      if (!st) st = fill_u32(e->arena + e->gctl_off, (size_t)groups * sizeof(FitCtl) / 4, 0, s);
       if (!st)
-        st = launch_fit_kernel(table + first, count, std::min(count, e->coresident), max_rows,
-                               (unsigned*)(e->arena + e->queue_off), sel, wide, s);
+        st = launch_fit_kernel(table + first, count, groups, max_rows,
+                               (unsigned*)(e->arena + e->queue_off), 1,
+                               (FitCtl*)(e->arena + e->gctl_off), sel, wide, s);
     } else {
       // every group of the launch is resident at once: grid <= coresident
-      st = launch_fit_kernel(table + first, count, grid, max_rows, nullptr, sel, wide, s);
+      st = launch_fit_kernel(table + first, count, grid, max_rows, nullptr, 1, nullptr, sel, wide,
+                             s);
     }
     if (st) return st;
   }

@@ -202,14 +202,5 @@ __global__ void copy_f64_kernel(const double* __restrict__ src, double* __restri
   if (x < n) dst[x] = src[x];
 }
 
-// done[k] = 1 when fit k of a launch table has finished or failed (read
-// between launches, so plain loads see the fit kernel's final stores).
-__global__ void fit_done_kernel(const FitDev* __restrict__ fits, int n, int* __restrict__ done) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) {
-    const FitCtl* c = fits[k].ctl;
-    done[k] = (c->phase == 2 || c->status != 0) ? 1 : 0;
-  }
-}
 
 }  // namespace stmf

@@ -70,3 +70,18 @@ def test_tune_fit_prefix_and_cache(tmp_path, monkeypatch):
     assert autotune.tune_fit(_Shape(), None, 20, cache=cache) == got and not seen
     autotune.tune_fit(_Shape(), None, 20, passes=2)
     assert {v for _, _, v in seen} == {600}
+
+
+def test_sample_spreads_over_the_sizes():
+    class P:
+        def __init__(self, n):
+            self.n = n
+
+        def numel(self):
+            return self.n
+
+    probs = [dict(R=P(n), pid=n) for n in (5, 50, 20, 80, 10, 40, 70, 30)]
+    got = [p["pid"] for p in autotune.sample_problems(probs, 3)]
+    assert got == [80, 30, 5]           # largest, middle, smallest
+    assert len(autotune.sample_problems(probs, 20)) == 8
+    assert all(g in (1, 2, 4, 8, 16) for g in autotune.GROUP_SIZES)

@@ -46,7 +46,8 @@ def test_tuned_batched_equals_default(S):
     probs = synth.batched_problems(10, seed=80, integer=True, m_range=(20, 120), n_range=(20, 200),
                                    r_range=(2, 6), miss_range=(0.2, 0.6))
     dev = [dict(R=_t(p.R), M=_t(p.M), rank=p.rank, iters=3, seed=500 + p.pid) for p in probs]
-    opts = autotune.tune_batched(dev, sample=4, iters=1)
+    opts = autotune.tune_batched(dev, restarts=2, sample=4, iters=1)
+    assert opts["group_size"] in autotune.GROUP_SIZES
     a, sa, _ = S.stmf_fit_batched(dev, restarts=2)
     b, sb, _ = S.stmf_fit_batched(dev, restarts=2, **opts)
     assert sa == sb == [0] * len(probs)

@@ -1,9 +1,9 @@
 """GPU tests of the batched path (stmf_fit_batched): many fits of uneven shape
-and several restarts, in one persistent launch (one workgroup per fit) or in
-rounds of launches (fits on groups of workgroups side by side).  Batching
-changes where a fit runs, never its arithmetic: every fit equals stmf_fit
-alone with the fit's group size and the restart's seed, bit for bit
-(integer and real data), and on integer data equals the oracle."""
+and several restarts in one persistent launch (captured in a HIP graph),
+whose groups of workgroups take fits from a device queue.  Batching changes
+where a fit runs, never its arithmetic: every fit equals stmf_fit alone with
+the restart's seed, bit for bit (integer and real data; a fit's result does
+not depend on its group size), and on integer data equals the oracle."""
 import numpy as np
 import pytest
 
@@ -125,10 +125,11 @@ def test_batched_rejects_bad_arguments(S):
         S.stmf_fit_batched(dev, restarts=1, max_row_visits=3)
 
 
-def test_batched_groups_over_several_launches(S):
-    # three fits of 4 x 66 tiles, each on as many workgroups as the device
-    # holds at once (or its tile count): every round runs one launch per fit
-    print("batched groups over launches", flush=True)
+@pytest.mark.parametrize("gcap", [64, 0])
+def test_batched_wide_fits_on_large_groups(S, gcap):
+    # three fits of 4 x 66 tiles on groups of 64 workgroups (or the
+    # library's choice), wider than one workgroup's column sort
+    print(f"batched wide fits group={gcap}", flush=True)
     rng = np.random.default_rng(51)
     dev = []
     for q in range(3):
@@ -137,8 +138,10 @@ def test_batched_groups_over_several_launches(S):
         M[:, 0] = 1
         M[0, :] = 1
         dev.append(dict(R=_t(R), M=_t(M), rank=2, iters=1, seed=60 + q))
-    outs, statuses, info = S.stmf_fit_batched(dev, restarts=1)
+    outs, statuses, info = S.stmf_fit_batched(dev, restarts=1, group_size=gcap)
     assert statuses == [0, 0, 0]
+    if gcap:
+        assert info["group_size"] == gcap
     for d, (U, V, T) in zip(dev, outs):
         g = S.stmf_fit(d["R"], d["M"], 2, 1, seed=d["seed"])
         assert g.info["group_size"] >= 64
@@ -165,6 +168,25 @@ def test_batched_zero_passes_and_tiny_problems(S, gcap):
         for q, sd in enumerate(_restart_seeds(d["seed"], 2)):
             g = S.stmf_fit(d["R"], d["M"], d["rank"], d["iters"], seed=sd,
                            group_size=_group(gcap, m, n))
+            np.testing.assert_array_equal(U[q].cpu().numpy(), g.U.cpu().numpy())
+            np.testing.assert_array_equal(V[q].cpu().numpy(), g.V.cpu().numpy())
+            np.testing.assert_array_equal(T[q].cpu().numpy(), g.traj)
+
+
+@pytest.mark.parametrize("gcap", [8, 32])
+def test_batched_more_fits_than_groups(S, gcap):
+    # 20 problems x 4 restarts = 80 fits on groups of 8 (32 groups) or 32
+    # (8 groups) workgroups: groups take several fits each from the queue
+    print(f"batched 80 fits group={gcap}", flush=True)
+    probs = synth.batched_problems(20, seed=55, integer=False, m_range=(40, 200),
+                                   n_range=(60, 400), r_range=(2, 6), miss_range=(0.2, 0.7))
+    dev = _dev(probs, 2)
+    outs, statuses, info = S.stmf_fit_batched(dev, restarts=4, group_size=gcap, init_mode=1)
+    assert statuses == [0] * len(probs)
+    assert info["group_size"] == gcap
+    for p, d, (U, V, T) in zip(probs, dev, outs):
+        for q, sd in enumerate(_restart_seeds(d["seed"], 4)):
+            g = S.stmf_fit(d["R"], d["M"], p.rank, 2, seed=sd, init_mode=1)
             np.testing.assert_array_equal(U[q].cpu().numpy(), g.U.cpu().numpy())
             np.testing.assert_array_equal(V[q].cpu().numpy(), g.V.cpu().numpy())
             np.testing.assert_array_equal(T[q].cpu().numpy(), g.traj)
