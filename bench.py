@@ -57,10 +57,22 @@ HBM_PEAK = 8.0e12
 WORKLOAD = dict(name="gene-expression-shaped", m=500, n=2000, rank=5, missing=0.5, iters=50,
                 seed=2, init="random-acol")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fit_kernel_gene_expr_500x2000_traffic.json")
-BATCHED = dict(count=64, restarts=2, iters=5, m=(50, 250), n=(50, 500), rank=(2, 8),
-               missing=(0.2, 0.8), seed=4)
-SERVING = dict(count=48, rate_per_s=100.0, iters=5, m=(50, 250), n=(50, 500), rank=(2, 8),
-               missing=(0.2, 0.8), seed=5, rows_per_tick=48, slots=256)
+# batched: the full population's shapes (m ~ U{50..1000}, n ~ U{50..5000},
+# rank ~ U{2..30}, missing ~ U[0.2, 0.8], integer planted), a stated subset
+# of its 256 problems with all 8 restarts, for a stated number of passes
+BATCHED = dict(count=32, restarts=8, iters=1, m=(50, 1000), n=(50, 5000), rank=(2, 30),
+               missing=(0.2, 0.8), seed=4, same_fit_problems=4, tune_sample=8, tune_visits=24)
+# serving: FP32 noisy planted jobs of a stated subset of the batched shapes,
+# 30 passes each, Poisson arrivals at 0.5x and 0.9x the batched path's
+# saturation rate for the same job mix
+SERVING = dict(count=64, iters=30, m=(50, 250), n=(50, 500), rank=(2, 8), missing=(0.2, 0.8),
+               seed=5, rows_per_tick=48, slots=256, loads=(0.5, 0.9))
+_T0 = time.perf_counter()
+
+
+def progress(msg: str) -> None:
+    """A step of the benchmark done (stderr, so the JSON line stays alone on stdout)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def splitmix64(seed: int, count: int):
@@ -77,12 +89,12 @@ def splitmix64(seed: int, count: int):
 
 
 def batched_compare():
-    """Batched fits (each on as many workgroups as it has tiles, in rounds of
-    launches; then one workgroup per fit in one persistent launch) vs the
-    plain path, same fits."""
-    import numpy as np
+    """The batched path on a subset of the batched population: the autotuner
+    picks the group size and batch shape on a sample, then every fit of the
+    subset runs in one persistent launch; the first problems' fits also run
+    through the plain one-fit-at-a-time path and are compared bit for bit."""
     import torch
-    from paper_2205_06619_amd import stmf, synth
+    from paper_2205_06619_amd import autotune, stmf, synth
     b = BATCHED
     probs = synth.batched_problems(b["count"], seed=b["seed"], integer=True, m_range=b["m"],
                                    n_range=b["n"], r_range=b["rank"], miss_range=b["missing"])
@@ -90,114 +102,124 @@ def batched_compare():
                 iters=b["iters"], seed=1000 + p.pid) for p in probs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    outs, statuses, info = stmf.stmf_fit_batched(dev, restarts=b["restarts"], integer_exact=1)
+    progress(f"batched: {len(probs)} problems on the device")
+    tuned = autotune.tune_batched(dev, restarts=b["restarts"], sample=b["tune_sample"],
+                                  iters=b["iters"], group_sizes=(8, 16, 32, 64),
+                                  candidates=((0, 0), (16, 256), (64, 1024)),
+                                  visits=b["tune_visits"], integer_exact=1)
+    tune_s = time.perf_counter() - t0
+    progress(f"batched: autotuned {tuned} in {tune_s:.1f} s")
     torch.cuda.synchronize()
-    t_batched = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    outs, statuses, info = stmf.stmf_fit_batched(dev, restarts=b["restarts"], integer_exact=1,
+                                                 **tuned)
+    torch.cuda.synchronize()
+    t_pop = time.perf_counter() - t0
     assert statuses == [0] * len(probs)
+    progress(f"batched: population of {len(probs) * b['restarts']} fits in {t_pop:.1f} s")
+    fits = len(probs) * b["restarts"]
+    del outs
+    # the same fits both ways: the first problems, every restart
+    sub = dev[:b["same_fit_problems"]]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    outs1, statuses1, _ = stmf.stmf_fit_batched(dev, restarts=b["restarts"], integer_exact=1,
-                                                group_size=1)
+    outs, statuses, sinfo = stmf.stmf_fit_batched(sub, restarts=b["restarts"], integer_exact=1,
+                                                  **tuned)
     torch.cuda.synchronize()
-    t_one = time.perf_counter() - t0
-    same_one = statuses1 == statuses and all(
-        bool(torch.equal(Ua, Ub)) and bool(torch.equal(Va, Vb)) and bool(torch.equal(Ta, Tb))
-        for (Ua, Va, Ta), (Ub, Vb, Tb) in zip(outs, outs1))
+    t_sub = time.perf_counter() - t0
+    progress(f"batched: {len(sub) * b['restarts']} fits batched in {t_sub:.1f} s")
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plain_trials, updates, same = 0, 0, True
-    for p, d, (U, V, T) in zip(probs, dev, outs):
+    plain_trials, plain_updates, same = 0, 0, True
+    for p, d, (U, V, T) in zip(probs, sub, outs):
         for q, sd in enumerate(splitmix64(d["seed"], b["restarts"])):
             g = stmf.stmf_fit(d["R"], d["M"], p.rank, b["iters"], seed=sd, integer_exact=1)
             plain_trials += g.info["trials"]
-            updates += g.info["trials"] * (min(p.m, p.n) + max(p.m, p.n) + 1)
-            same = same and bool(torch.equal(U[q], g.U)) and bool(torch.equal(V[q], g.V))
+            plain_updates += g.info["trials"] * (min(p.m, p.n) + max(p.m, p.n) + 1)
+            same = (same and bool(torch.equal(U[q], g.U)) and bool(torch.equal(V[q], g.V))
+                    and bool(torch.equal(T[q].cpu(), torch.from_numpy(g.traj))))
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    # the autotuned launch shape (timed on the 16 largest problems, 2 passes)
-    from paper_2205_06619_amd import autotune
-    t0 = time.perf_counter()
-    tuned = autotune.tune_batched(dev, sample=16, iters=2, integer_exact=1)
-    tune_s = time.perf_counter() - t0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs_t, statuses_t, _ = stmf.stmf_fit_batched(dev, restarts=b["restarts"], integer_exact=1,
-                                                  **tuned)
-    torch.cuda.synchronize()
-    t_tuned = time.perf_counter() - t0
-    same_tuned = statuses_t == statuses and all(
-        bool(torch.equal(Ua, Ub)) and bool(torch.equal(Va, Vb)) and bool(torch.equal(Ta, Tb))
-        for (Ua, Va, Ta), (Ub, Vb, Tb) in zip(outs, outs_t))
-    fits = len(probs) * b["restarts"]
+    progress(f"batched: the same fits plain in {t_plain:.1f} s")
+    sub_fits = len(sub) * b["restarts"]
     return {
-        "config": {"workload": f"{b['count']} integer planted problems x {b['restarts']} restarts, "
-                               f"m in {list(b['m'])}, n in {list(b['n'])}, rank in {list(b['rank'])}, "
-                               f"missing in {list(b['missing'])}, {b['iters']} passes"},
-        "fits": fits,
-        "batched_s": t_batched,
-        "plain_s": t_plain,
-        "batched_fits_per_s": fits / t_batched,
-        "plain_fits_per_s": fits / t_plain,
-        "batched_updates_per_s": updates / t_batched,
-        "plain_updates_per_s": updates / t_plain,
-        "speedup": t_plain / t_batched,
-        "trials": plain_trials,
-        "identical": same,
-        "one_workgroup_per_fit": {"batched_s": t_one, "speedup_vs_plain": t_plain / t_one,
-                                  "identical": same_one},
-        "autotuned": {"options": tuned, "tune_s": tune_s, "batched_s": t_tuned,
-                      "speedup_vs_plain": t_plain / t_tuned, "speedup_vs_default": t_batched / t_tuned,
-                      "identical": same_tuned},
+        "config": {"workload": f"{b['count']} of the 256 integer planted problems of the batched "
+                               f"population (m in {list(b['m'])}, n in {list(b['n'])}, rank in "
+                               f"{list(b['rank'])}, missing in {list(b['missing'])}) x "
+                               f"{b['restarts']} restarts, {b['iters']} pass(es); the first "
+                               f"{b['same_fit_problems']} problems' fits also through the plain path"},
+        "autotuned": {"options": tuned, "tune_s": tune_s},
+        "population": {"fits": fits, "batched_s": t_pop, "fits_per_s": fits / t_pop,
+                       "trials": info["trials"], "trials_per_s": info["trials"] / t_pop,
+                       "spec_trials": info["spec_trials"], "group_size": info["group_size"]},
+        "same_fits": {"fits": sub_fits, "batched_s": t_sub, "plain_s": t_plain,
+                      "batched_fits_per_s": sub_fits / t_sub, "plain_fits_per_s": sub_fits / t_plain,
+                      "batched_updates_per_s": plain_updates / t_sub,
+                      "plain_updates_per_s": plain_updates / t_plain,
+                      "speedup": t_plain / t_sub, "trials": plain_trials,
+                      "identical": same},
     }
 
 
 def serving_compare():
-    """Continuous batching (each job on as many workgroups as it has tiles,
-    then one workgroup per job) vs the plain sequential path on one Poisson
-    stream."""
+    """Continuous batching at 0.5x and 0.9x the saturation rate of the
+    batched path for the same job mix, against the plain sequential path on
+    the same 0.5x stream; every served result equals the plain fit's."""
     import numpy as np
+    import torch
     from paper_2205_06619_amd import serve, stmf
     c = SERVING
 
-    def stream():
-        return serve.synthetic_jobs(c["count"], c["rate_per_s"], seed=c["seed"], m_range=c["m"],
+    def stream(rate):
+        return serve.synthetic_jobs(c["count"], rate, seed=c["seed"], m_range=c["m"],
                                     n_range=c["n"], r_range=c["rank"], miss_range=c["missing"],
                                     iters=c["iters"])
 
-    def continuous(group_size):
-        jobs = stream()
-        backend = serve.EngineBackend(64 << 20, c["slots"], group_size=group_size)
+    # saturation: every job of the mix submitted at once to the batched path
+    jobs = stream(1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs, statuses, _ = stmf.stmf_fit_batched(
+        [dict(R=j.R, M=j.M, rank=j.rank, iters=j.iters, seed=j.seed) for j in jobs], restarts=1)
+    torch.cuda.synchronize()
+    sat = len(jobs) / (time.perf_counter() - t0)
+    assert statuses == [0] * len(jobs)
+    progress(f"serving: saturation {sat:.2f} jobs/s")
+    del outs, jobs
+
+    def continuous(rate):
+        jobs = stream(rate)
+        backend = serve.EngineBackend(64 << 20, c["slots"])
         need = sum(backend.footprint(j) for j in jobs)
         backend.close()
-        backend = serve.EngineBackend(need + (64 << 20), c["slots"], group_size=group_size)
+        backend = serve.EngineBackend(need + (64 << 20), c["slots"])
         try:
             st = serve.Server(backend, rows_per_tick=c["rows_per_tick"]).run(jobs)
         finally:
             backend.close()
         return jobs, st
 
-    grouped, st = continuous(0)
-    single, st1 = continuous(1)
-    seq_jobs = stream()
+    out = {"config": {"workload": f"{c['count']} FP32 noisy planted completion jobs per run, m in "
+                                  f"{list(c['m'])}, n in {list(c['n'])}, rank in {list(c['rank'])}, "
+                                  f"missing in {list(c['missing'])}, {c['iters']} passes each, "
+                                  f"Poisson arrivals at {list(c['loads'])} x the saturation rate, "
+                                  f"{c['rows_per_tick']} row visits per tick"},
+           "saturation_jobs_per_s": sat}
+    served = {}
+    for load in c["loads"]:
+        jobs, st = continuous(load * sat)
+        progress(f"serving: {load}x load done ({st.jobs_per_s:.2f} jobs/s)")
+        served[load] = jobs
+        out[f"continuous_{load}x"] = dict(st.as_dict(), rate_per_s=load * sat)
+    seq_jobs = stream(c["loads"][0] * sat)
     sq = serve.sequential(seq_jobs, lambda j: stmf.stmf_fit(j.R, j.M, j.rank, j.iters, seed=j.seed))
-    # the grouped engine reproduces the plain path bit for bit; one workgroup
-    # per job sums the errors in another FP64 order: trajectories agree to
-    # rounding
-    same = all(np.array_equal(a.result.traj, b.result.traj) and
-               bool((a.result.U == b.result.U).all()) and bool((a.result.V == b.result.V).all())
-               for a, b in zip(grouped, seq_jobs))
-    worst = max(float(np.max(np.abs(a.result.traj - b.result.traj) / np.abs(b.result.traj)))
-                for a, b in zip(single, seq_jobs))
-    return {
-        "config": {"workload": f"{c['count']} FP32 noisy planted completion jobs, Poisson arrivals "
-                               f"at {c['rate_per_s']} jobs/s, m in {list(c['m'])}, n in {list(c['n'])}, "
-                               f"rank in {list(c['rank'])}, {c['iters']} passes, "
-                               f"{c['rows_per_tick']} row visits per tick"},
-        "continuous": st.as_dict(),
-        "continuous_one_workgroup_per_job": st1.as_dict(),
-        "sequential": sq.as_dict(),
-        "grouped_equals_plain": same,
-        "one_workgroup_max_traj_rel_diff": worst,
-    }
+    progress("serving: sequential done")
+    out[f"sequential_{c['loads'][0]}x"] = dict(sq.as_dict(), rate_per_s=c["loads"][0] * sat)
+    out["served_equals_plain"] = all(
+        np.array_equal(a.result.traj, b.result.traj) and bool((a.result.U == b.result.U).all())
+        and bool((a.result.V == b.result.V).all())
+        for a, b in zip(served[c["loads"][0]], seq_jobs))
+    return out
 
 
 SELECTIONS = [  # (name, strategy, selection, perm_mode, passes)
@@ -291,7 +313,7 @@ def quality_compare():
     }
 
 
-LARGE = dict(m=2000, n=20000, rank=20, passes=1, seed=3)
+LARGE = dict(m=2000, n=20000, rank=20, passes=3, seed=3)
 
 
 def large_compare():
@@ -306,8 +328,10 @@ def large_compare():
     Rd, Md = torch.from_numpy(R).cuda(), torch.from_numpy(M).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    progress(f"large: {c['m']} x {c['n']} on the device, {c['passes']} passes")
     r = stmf.stmf_fit(Rd, Md, c["rank"], c["passes"], seed=c["seed"], init_mode=1)
     wall = time.perf_counter() - t0
+    progress(f"large: done in {wall:.1f} s")
     kernel_s = r.info["kernel_ms"] / 1e3
     trials = r.info["trials"]
     mw, nw = min(R.shape), max(R.shape)

@@ -285,24 +285,28 @@ typedef struct {
 } stmf_problem;
 
 /* Workspace bytes of stmf_fit_batched with these problems and options on the
- * current device (each fit's group size, and with it its layout, depends on
- * group_size and on how many fit-kernel workgroups the device holds at
- * once); 0 for invalid arguments or when the device cannot be queried. */
+ * current device (the group size, and with it each fit's layout, depends on
+ * group_size, on the problems and on how many fit-kernel workgroups the
+ * device holds at once); 0 for invalid arguments or when the device cannot
+ * be queried. */
 size_t stmf_fit_batched_workspace(const stmf_problem* probs, int nprob, int restarts,
                                   const stmf_options* opt);
 
-/* Many independent fits.  Each fit runs on a group of workgroups: the
- * smaller of opt->group_size (0: no limit but the co-resident workgroup
- * count) and its tile count (64 x 64 tiles of the working matrix), and its
- * result equals stmf_fit with that group_size and the same seed (with
- * group_size 0, stmf_fit's own result).  With group_size 1 the fits run in
- * one persistent launch whose workgroups take fits from a queue, longest
- * fits first; otherwise in rounds of launches, the unfinished fits side by
- * side (longest first), each advanced by at most 64 row visits per round.
- * With one restart a problem's fit uses its seed; with several, restart q
- * uses output q of SplitMix64 seeded with the problem's seed.  Synchronous.
- * info (host, nullable) gets the summed counters.  Options decision_log,
- * perm, init_mode 2, max_row_visits and strategy 2 are rejected. */
+/* Many independent fits (Algorithm 3 for each, as stmf_fit) in one
+ * persistent launch: the grid is cut into groups of G workgroups that take
+ * fits from a device queue, largest estimated work first, until it is empty.
+ * G = opt->group_size (at most the co-resident workgroup count), or with 0
+ * the library's choice from the fits' work (a power of two up to 64).  The
+ * device side (queue reset, the launch, every fit's output and trajectory)
+ * is one captured HIP graph launched on `stream`.  A fit's result equals
+ * stmf_fit's with the same seed and options on any group size.  With one
+ * restart a problem's fit uses its seed; with several, restart q uses output
+ * q of SplitMix64 seeded with the problem's seed.  max_row_visits > 0 stops
+ * every fit after that many row visits (a prefix, for timing: the outputs
+ * are then those of the state reached).  Synchronous.  info (host,
+ * nullable) gets the summed counters and group_size the G used.  Options
+ * decision_log, perm, init_mode 2 and strategy 2 are rejected; a problem
+ * whose input fails the checks gets its status and no fit, the others run. */
 int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts,
                      const stmf_options* opt, stmf_fit_info* info, void* ws,
                      size_t ws_bytes, void* stream);

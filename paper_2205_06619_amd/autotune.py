@@ -126,12 +126,14 @@ def sample_problems(problems: List[dict], sample: int) -> List[dict]:
 def tune_batched(problems: List[dict], restarts: int = 1, sample: int = 16, iters: int = 2,
                  cache: Optional[Cache] = None, key: Optional[str] = None,
                  candidates: Sequence[Tuple[int, int]] = CANDIDATES,
-                 group_sizes: Sequence[int] = GROUP_SIZES, **opts) -> dict:
+                 group_sizes: Sequence[int] = GROUP_SIZES, visits: int = 0, **opts) -> dict:
     """Launch shape for a batched workload: the batched launch on `sample`
     problems spread over the population's sizes, with its restarts, for
-    `iters` passes; the wall time of the call decides, first among the group
-    sizes (default batches), then among the batch shapes at the best group
-    size.  Returns {group_size, batch_first, batch_max}."""
+    `iters` passes (or the first `visits` row visits of every fit: a prefix
+    keeps tuning a population of large fits cheap); the wall time of the call
+    decides, first among the group sizes (default batches), then among the
+    batch shapes at the best group size.  Returns {group_size, batch_first,
+    batch_max}."""
     import torch
     from . import stmf
     fields = ("group_size", "batch_first", "batch_max")
@@ -144,7 +146,7 @@ def tune_batched(problems: List[dict], restarts: int = 1, sample: int = 16, iter
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         stmf.stmf_fit_batched(probe, restarts=restarts, group_size=gs, batch_first=bf,
-                              batch_max=bm, **opts)
+                              batch_max=bm, max_row_visits=visits, **opts)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3
 

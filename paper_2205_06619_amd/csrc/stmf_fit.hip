@@ -137,6 +137,8 @@ struct BatchScratch {
   } v;
   double epl[TCH][2][4];     // error pass: per staged trial, row half and 16-lane
                              // row, partial error
+  float pc[TS][TS];          // error pass: the product without the current
+                             // component at every cell of the tile
 };
 struct RefreshScratch {
   int hc[TS][RMAX];          // argmax histogram of the tile columns
@@ -716,35 +718,44 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
     int kb0 = -KB, kcur = -1;
 #pragma unroll 1
     while (cur.k < dr) {
-      if (cur.k != kcur) {
+      const bool newk = cur.k != kcur;
+      if (newk) {
         // summaries of the component's block (read by the staging after the
         // chunk's barrier; the previous chunk's staging is done with them)
         if (cur.k >= kb0 + KB) {
           kb0 = cur.k;
           stage_block<MR>(gp, S, kb0, dr - kb0 < KB ? dr - kb0 : KB, true, true, r0, c0, i);
         }
-        // the product without k for this wave's rows and lane column, from
-        // the staged U and V (each wave forms its own: no barrier)
+        // the product without k at the tile, from the staged U and V: wave w
+        // forms rows 8 (w >> 1) .. of its half into LDS (the four waves of a
+        // half share the work), read back by every wave after the barrier
+        const int rb = h0 + 8 * (gp.wave >> 1);
+        float P8[8];
 #pragma unroll
-        for (int t = 0; t < TS / 2; ++t) Pc[t] = -FINF;
+        for (int t = 0; t < 8; ++t) P8[t] = -FINF;
         for (int l = 0; l < dr; ++l) {
           if (l == cur.k) continue;
           const float v = S.Vt[l][gp.lane];
-          const float4* u4 = reinterpret_cast<const float4*>(&S.Ut[l][h0]);
+          const float4* u4 = reinterpret_cast<const float4*>(&S.Ut[l][rb]);
 #pragma unroll
-          for (int t4 = 0; t4 < TS / 8; ++t4) {
+          for (int t4 = 0; t4 < 2; ++t4) {
             const float4 u = u4[t4];
-            Pc[4 * t4 + 0] = vmax(Pc[4 * t4 + 0], u.x + v);
-            Pc[4 * t4 + 1] = vmax(Pc[4 * t4 + 1], u.y + v);
-            Pc[4 * t4 + 2] = vmax(Pc[4 * t4 + 2], u.z + v);
-            Pc[4 * t4 + 3] = vmax(Pc[4 * t4 + 3], u.w + v);
+            P8[4 * t4 + 0] = vmax(P8[4 * t4 + 0], u.x + v);
+            P8[4 * t4 + 1] = vmax(P8[4 * t4 + 1], u.y + v);
+            P8[4 * t4 + 2] = vmax(P8[4 * t4 + 2], u.z + v);
+            P8[4 * t4 + 3] = vmax(P8[4 * t4 + 3], u.w + v);
           }
         }
 #pragma unroll
-        for (int t = 0; t < TS / 2; ++t) Pc[t] = ((obs >> t) & 1u) ? Pc[t] : FLT_MAX;
+        for (int t = 0; t < 8; ++t) S.u.b.pc[rb + t][gp.lane] = P8[t];
         kcur = cur.k;
       }
       __syncthreads();
+      if (newk) {
+#pragma unroll
+        for (int t = 0; t < TS / 2; ++t)
+          Pc[t] = ((obs >> t) & 1u) ? S.u.b.pc[h0 + t][gp.lane] : FLT_MAX;
+      }
       chunk_stage<NE, MR>(gp, S, wcur, cur, cur.k - kb0, r0, c0, rawA, rawB);
       chunk_reduce(gp, S, prev, epart, ntile, tile);
       const Chunk next = chunk_at(S, dr, cur.k, cur.cs + TCH);
@@ -905,11 +916,15 @@ DEV void refresh_tiles(Grp& gp, Smem& S, int k, bool has_acc, Trial acc, int par
     const int rt = tile / d.nct, ct = tile % d.nct;
     const int r0 = rt * TS, c0 = ct * TS;
     __syncthreads();
-    if (full)
-      for (int e = gp.tid; e < TS * RMAX; e += NTHR) {
-        (&S.u.f.hc[0][0])[e] = 0;
-        (&S.u.f.hr[0][0])[e] = 0;
+    if (full) {
+      // only the rank's components of each histogram row are used
+      const int dr = d.r;
+      for (int e = gp.tid; e < TS * dr; e += NTHR) {
+        const int x = e / dr, l = e - x * dr;
+        S.u.f.hc[x][l] = 0;
+        S.u.f.hr[x][l] = 0;
       }
+    }
     if (gp.tid < TS) {
       const int t = r0 + gp.tid;
       const float v = has_acc ? row_side(d, acc, par, slot, t) : ld_atomic(&d.Uc[(size_t)k * d.ldm + t]);

@@ -785,13 +785,13 @@ static bool any_wide(const FitDev* fits, int n) {
 // output (un-permuted, un-transposed factors) and trajectory of every fit.
 static int record_batched(const BatchPlan& B, const std::vector<int>& fit_ids,
                           const std::vector<FitDev>& table, stmf_problem* probs, int restarts,
-                          char* base, int sel, hipStream_t c) {
+                          char* base, int sel, int max_rows, hipStream_t c) {
   int st = fill_u32(base + B.queue, 1, 0, c);
   if (!st) st = fill_u32(base + B.gctl, (size_t)B.ngroups * sizeof(FitCtl) / 4, 0, c);
   if (st) return st;
   const int n = (int)table.size();
   const int ngroups = std::min(B.ngroups, n);
-  st = launch_fit_kernel((const FitDev*)(base + B.table), n, ngroups * B.qgroup, 0,
+  st = launch_fit_kernel((const FitDev*)(base + B.table), n, ngroups * B.qgroup, max_rows,
                          (unsigned*)(base + B.queue), B.qgroup, (FitCtl*)(base + B.gctl), sel,
                          any_wide(table.data(), n), c);
   if (st) return st;
@@ -834,7 +834,7 @@ int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts, const stmf_op
   int st = resolve(opt, o);
   if (st) return st;
   if (!probs || nprob < 1 || restarts < 1) return STMF_EINVAL;
-  if (o.decision_log || o.perm || o.init_mode == 2 || o.max_row_visits) return STMF_EINVAL;
+  if (o.decision_log || o.perm || o.init_mode == 2 || o.max_row_visits < 0) return STMF_EINVAL;
   if (o.strategy == 2) return STMF_EINVAL;  // ByMatrix runs through stmf_fit only
   for (int p = 0; p < nprob; ++p)
     if (!probs[p].R || !probs[p].M || !probs[p].U_out || !probs[p].V_out || probs[p].m < 1 ||
@@ -892,7 +892,8 @@ int stmf_fit_batched(stmf_problem* probs, int nprob, int restarts, const stmf_op
       cleanup();
       return STMF_EHIP;
     }
-    st = record_batched(B, fit_ids, table, probs, restarts, base, kernel_sel(o), cap);
+    st = record_batched(B, fit_ids, table, probs, restarts, base, kernel_sel(o), o.max_row_visits,
+                        cap);
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(cap, &g);
     graph = g;

@@ -122,7 +122,25 @@ def test_batched_rejects_bad_arguments(S):
     with pytest.raises(S.StmfError):
         S.stmf_fit_batched(dev, restarts=0)
     with pytest.raises(S.StmfError):
-        S.stmf_fit_batched(dev, restarts=1, max_row_visits=3)
+        S.stmf_fit_batched(dev, restarts=1, decision_log=1, log_cap=4)
+    with pytest.raises(S.StmfError):
+        S.stmf_fit_batched(dev, restarts=1, strategy=2)
+
+
+def test_batched_row_visit_prefix_equals_plain_prefix(S):
+    # max_row_visits stops every fit after that many row visits: each fit's
+    # state then is the plain fit's after the same prefix
+    print("batched prefix", flush=True)
+    probs = _problems(False, 5, seed=56)
+    dev = _dev(probs, 3)
+    outs, statuses, info = S.stmf_fit_batched(dev, restarts=2, max_row_visits=7, init_mode=1)
+    assert statuses == [0] * len(probs)
+    for p, d, (U, V, T) in zip(probs, dev, outs):
+        for q, sd in enumerate(_restart_seeds(d["seed"], 2)):
+            g = S.stmf_fit(d["R"], d["M"], p.rank, 3, seed=sd, init_mode=1, max_row_visits=7)
+            np.testing.assert_array_equal(U[q].cpu().numpy(), g.U.cpu().numpy())
+            np.testing.assert_array_equal(V[q].cpu().numpy(), g.V.cpu().numpy())
+            assert T[q].cpu().numpy()[0] == g.traj[0]
 
 
 @pytest.mark.parametrize("gcap", [64, 0])
