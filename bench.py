@@ -396,23 +396,38 @@ def host_cpu():
 
 
 def cpu_baseline(R, M, rows: int):
-    """The oracle (FP32 values, FP64 sums) on the first `rows` row visits."""
+    """The oracle (FP32 values, FP64 sums) on the first `rows` row visits of
+    the workload: once on one thread, once on every host core the process
+    may use (OpenMP over the rows of each trial's residuals and evaluation;
+    the results are identical, checked)."""
     import oracle
     w = WORKLOAD
-    t0 = time.perf_counter()
-    res = oracle.fit(R, M, w["rank"], w["iters"], seed=w["seed"], prec="f32", init_mode=1,
-                     row_limit=rows)
-    dt = time.perf_counter() - t0
-    assert res.status == 0
     mw, nw = min(R.shape), max(R.shape)
-    trials = res.stats["trials"]
+    cores = host_cpu()["nproc"]
+
+    def timed(threads):
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        res = oracle.fit(R, M, w["rank"], w["iters"], seed=w["seed"], prec="f32", init_mode=1,
+                         row_limit=rows)
+        dt = time.perf_counter() - t0
+        assert res.status == 0
+        return res, dt
+
+    one, dt1 = timed(1)
+    progress(f"cpu baseline: one thread {dt1:.1f} s")
+    many, dtn = timed(cores)
+    progress(f"cpu baseline: {cores} threads {dtn:.1f} s")
+    assert (many.log == one.log).all() and (many.traj == one.traj).all()
+    trials = one.stats["trials"]
     return {
-        "value": trials * (mw + nw + 1) / dt,
+        "value": trials * (mw + nw + 1) / dtn,
         "unit": UNIT,
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
-        "sample": f"first {rows} row visits of pass 1 of the same workload "
-                  f"({trials} trials, {dt:.1f} s single-threaded)",
+        "sample": f"first {rows} row visits of pass 1 of the same workload ({trials} trials): "
+                  f"{dtn:.2f} s on {cores} threads, {dt1:.2f} s on one (identical results)",
+        "single_thread_value": trials * (mw + nw + 1) / dt1,
         **host_cpu(),
     }
 
@@ -434,7 +449,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--cpu-rows", type=int, default=16,
+    ap.add_argument("--cpu-rows", type=int, default=32,
                     help="row visits of the oracle's CPU-baseline sample (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--selections-only", action="store_true",

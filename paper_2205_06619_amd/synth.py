@@ -161,11 +161,12 @@ class BatchProblem:
 
 def batched_problems(count: int = 256, seed: int = 4, integer: bool = True,
                      m_range=(50, 1000), n_range=(50, 5000), r_range=(2, 30),
-                     miss_range=(0.2, 0.8)) -> List[BatchProblem]:
+                     miss_range=(0.2, 0.8), only=None) -> List[BatchProblem]:
     """Problems of uneven shape: m, n, rank uniform ints, missing ~ U[lo, hi].
 
     ``integer`` selects planted uniform-int data (exact arithmetic); otherwise
-    planted U[0,10] factors with N(0, 0.5) noise.
+    planted U[0,10] factors with N(0, 0.5) noise.  ``only`` (problem ids)
+    builds just those problems of the population, the same as in the whole.
     """
     rng = np.random.default_rng(seed)
     out = []
@@ -174,6 +175,8 @@ def batched_problems(count: int = 256, seed: int = 4, integer: bool = True,
         n = int(rng.integers(n_range[0], n_range[1] + 1))
         r = int(rng.integers(r_range[0], r_range[1] + 1))
         miss = float(rng.uniform(miss_range[0], miss_range[1]))
+        if only is not None and pid not in only:
+            continue
         sub = np.random.default_rng([seed, pid])
         if integer:
             U = sub.integers(0, 101, size=(m, r)).astype(np.float32)

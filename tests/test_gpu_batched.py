@@ -208,3 +208,24 @@ def test_batched_more_fits_than_groups(S, gcap):
             np.testing.assert_array_equal(U[q].cpu().numpy(), g.U.cpu().numpy())
             np.testing.assert_array_equal(V[q].cpu().numpy(), g.V.cpu().numpy())
             np.testing.assert_array_equal(T[q].cpu().numpy(), g.traj)
+
+
+@pytest.mark.timeout(600)
+def test_batched_population_subset_matches_oracle(S):
+    # the two smallest problems of the 256-problem batched population (integer
+    # planted, seed 4): 68 x 247 rank 6 and 57 x 379 rank 11, each with its 8
+    # restarts, one pass, batched: every one of the 16 fits equals the oracle
+    # bit for bit
+    print("batched population subset vs oracle", flush=True)
+    probs = synth.batched_problems(256, seed=4, integer=True, only=(62, 73))
+    assert sorted((p.m, p.n, p.rank) for p in probs) == [(57, 379, 11), (68, 247, 6)]
+    dev = _dev(probs, 1)
+    outs, statuses, _ = S.stmf_fit_batched(dev, restarts=8, integer_exact=1)
+    assert statuses == [0, 0]
+    for p, d, (U, V, T) in zip(probs, dev, outs):
+        for q, sd in enumerate(_restart_seeds(d["seed"], 8)):
+            o = oracle.fit(p.R, p.M, p.rank, 1, seed=sd, prec="f32", integer_exact=1)
+            assert o.status == 0
+            np.testing.assert_array_equal(U[q].cpu().numpy(), o.U)
+            np.testing.assert_array_equal(V[q].cpu().numpy(), o.V)
+            np.testing.assert_array_equal(T[q].cpu().numpy(), o.traj)
