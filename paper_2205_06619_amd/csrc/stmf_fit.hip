@@ -194,6 +194,7 @@ struct Smem {
   int cur_op;
   int exhausted;
   int is_last;
+  unsigned bar_e;            // group barrier: the episode being released
   int status;
   int dec;
   int wcount[NWAVE];
@@ -227,56 +228,75 @@ static_assert(KB * TS == NTHR, "one thread per staged summary");
 struct Grp {
   const FitDev* d;
   GA FitCtl* ctl;
+  GA BarTree* bar;   // the group barrier's counters (unused by a group of one)
   int g, G;
   int lane, wave, tid;
 };
 
 // ------------------------------------------------------------ group barrier
-// Sense-reversing barrier over the group's workgroups with a bounded wait: a
-// wait longer than BARRIER_TIMEOUT (or any other workgroup's abort) sets the
-// fit's status and every workgroup leaves the fit.  If `last_work` is set, the
-// last workgroup to arrive runs it before releasing the others.  Returns false
-// when the fit has been aborted.
+// Two-level barrier over the group's workgroups with a bounded wait.  A
+// workgroup arrives on its subgroup's counter; the last member of each
+// subgroup to arrive goes on to the top counter, and the last arrival there
+// runs `last_work` (if any) and releases the episode to every subgroup.  The
+// others wait on their subgroup's release word, so at most BAR_SUB
+// workgroups contend for any one counter or word (with one counter for the
+// whole group, its 256 serialised atomics made each barrier about 10 us;
+// two levels about 2 us).  The counters only grow: an arrival's episode is
+// its count divided by the arrivals per episode, which also holds for a fit
+// resumed by a later launch.  A wait longer than BARRIER_TIMEOUT (or another
+// workgroup's abort) sets the fit's status and leaves.  Returns false when
+// this workgroup left on an abort.
 template <typename F>
 DEV bool group_sync_last(Grp& gp, Smem& S, F last_work) {
   GA FitCtl* ctl = gp.ctl;
+  GA BarTree* bar = gp.bar;
   // every wave's stores (all device-coherent) are complete before arriving
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (gp.G == 1) {
-    S.is_last = 1;
-  } else if (gp.tid == 0) {
-    unsigned gen = ld_atomic(&ctl->bar_gen);
-    unsigned old = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-    S.is_last = (old == (unsigned)gp.G - 1) ? 1 : 0;
-    if (!S.is_last) {
-      unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
-      while (ld_atomic(&ctl->bar_gen) == gen) {
-        if (ld_atomic(&ctl->status) != 0) break;
-        if (__builtin_amdgcn_s_memrealtime() - t0 > BARRIER_TIMEOUT) {
-          int zero = 0;
-          __hip_atomic_compare_exchange_strong(&ctl->status, &zero, ST_TIMEOUT, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
+  const int G = gp.G, q = gp.g / BAR_SUB, nq = (G + BAR_SUB - 1) / BAR_SUB;
+  if (gp.tid == 0) {
+    int st = 0, last = 1;
+    unsigned e = 0;
+    if (G > 1) {
+      const unsigned members = (unsigned)(q == nq - 1 ? G - BAR_SUB * q : BAR_SUB);
+      const unsigned old = __hip_atomic_fetch_add(&bar->sub[q][0], 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+      e = old / members + 1;
+      last = old % members == members - 1;
+      if (last && nq > 1) {
+        const unsigned o2 = __hip_atomic_fetch_add(&bar->top[0], 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        last = o2 % (unsigned)nq == (unsigned)nq - 1;
+      }
+      if (!last) {
+        unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+        while ((int)(ld_atomic(&bar->rel[q][0]) - e) < 0) {
+          st = ld_atomic(&ctl->status);
+          if (st != 0) break;
+          if (__builtin_amdgcn_s_memrealtime() - t0 > BARRIER_TIMEOUT) {
+            int zero = 0;
+            __hip_atomic_compare_exchange_strong(&ctl->status, &zero, ST_TIMEOUT, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st = ST_TIMEOUT;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
         }
-        __builtin_amdgcn_s_sleep(1);
       }
     }
+    S.is_last = last;
+    S.bar_e = e;
+    S.status = st;
   }
   __syncthreads();
   if (S.is_last) {
     last_work();
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (gp.G > 1 && gp.tid == 0) {
-      st_coh(&ctl->bar_count, 0u);
-      __builtin_amdgcn_s_waitcnt(0);
-      const unsigned gen = ld_atomic(&ctl->bar_gen);
-      st_coh(&ctl->bar_gen, gen + 1);
+    if (G > 1 && gp.tid == 0) {
+      for (int r = 0; r < nq; ++r) st_coh(&bar->rel[r][0], S.bar_e);
     }
   }
-  if (gp.tid == 0) S.status = ld_atomic(&ctl->status);
   __syncthreads();
   return S.status == 0;
 }
@@ -525,22 +545,49 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
             }
           }
           __syncthreads();
+          // Each trial's 16 broadcast LDS reads are kept AHEAD deep in
+          // flight, and the next trial's first AHEAD are issued before this
+          // trial's reduction and atomic: the scheduling fences stop the
+          // compiler from issuing each read just before its use (by itself
+          // it keeps two in flight, and with two waves per SIMD the reads'
+          // latency shows).  A read past the chunk's last trial stays inside
+          // the staging array and its value is never used.
+          constexpr int NQ = TS / 4, AHEAD = 4;
+          float4 qn[AHEAD];
+#pragma unroll
+          for (int c4 = 0; c4 < AHEAD; ++c4)
+            qn[c4] = reinterpret_cast<const float4*>(S.u.b.v.sX[gp.wave])[c4];
 #pragma unroll 1
           for (int sl = gp.wave; sl < cn; sl += NWAVE) {
             const float4* sx = reinterpret_cast<const float4*>(S.u.b.v.sX[sl]);
+            const int q = S.byk[cs + sl];
+            float4 sq[NQ];
+#pragma unroll
+            for (int c4 = 0; c4 < AHEAD; ++c4) sq[c4] = qn[c4];
+            __builtin_amdgcn_sched_barrier(0);
             float x0 = FINF, x1 = FINF, x2 = FINF, x3 = FINF;
 #pragma unroll
-            for (int c4 = 0; c4 < TS / 4; c4 += 2) {
-              const float4 s = sx[c4], s2 = sx[c4 + 1];
+            for (int c4 = 0; c4 < NQ; ++c4) {
+              const float4 s = sq[c4];
               const int c = 4 * c4;
-              x0 = vmin(vmin(x0, Rv[c + 0] - s.x), Rv[c + 1] - s.y);
-              x1 = vmin(vmin(x1, Rv[c + 2] - s.z), Rv[c + 3] - s.w);
-              x2 = vmin(vmin(x2, Rv[c + 4] - s2.x), Rv[c + 5] - s2.y);
-              x3 = vmin(vmin(x3, Rv[c + 6] - s2.z), Rv[c + 7] - s2.w);
+              if (c4 & 1) {
+                x2 = vmin(vmin(x2, Rv[c + 0] - s.x), Rv[c + 1] - s.y);
+                x3 = vmin(vmin(x3, Rv[c + 2] - s.z), Rv[c + 3] - s.w);
+              } else {
+                x0 = vmin(vmin(x0, Rv[c + 0] - s.x), Rv[c + 1] - s.y);
+                x1 = vmin(vmin(x1, Rv[c + 2] - s.z), Rv[c + 3] - s.w);
+              }
+              if (c4 + AHEAD < NQ) sq[c4 + AHEAD] = sx[c4 + AHEAD];
+              __builtin_amdgcn_sched_barrier(0);
             }
+            const int nx = sl + NWAVE < 2 * TCH ? sl + NWAVE : sl;
+#pragma unroll
+            for (int c4 = 0; c4 < AHEAD; ++c4)
+              qn[c4] = reinterpret_cast<const float4*>(S.u.b.v.sX[nx])[c4];
+            __builtin_amdgcn_sched_barrier(0);
             const float xm = vmin(vmin(x0, x1), vmin(x2, x3));
             // +inf: no observed cell of this row (column) in the tile
-            if (xm != FINF) atomic_min_g(&tv[S.byk[cs + sl] * ldx + own], fmap(xm));
+            if (xm != FINF) atomic_min_g(&tv[q * ldx + own], fmap(xm));
           }
         }
       }
@@ -763,14 +810,28 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
           wave_trials<NE, MR>(gp, S, next.cs, next.cn, next.a0, next.n0, next.a1);
       chunk_loads<NE, MR>(gp, wnext, next, par, r0, c0, rawA, rawB);
       __syncthreads();
+      // The trial's first LDS reads are issued while the previous trial's
+      // lane sums are reduced, the rest AHEAD deep (see the residual pass);
+      // a read past the chunk's last trial stays inside the staging arrays
+      // and its value is never used.
+      constexpr int NQ = TS / 8, AHEAD = 3;
+      float vn = S.u.b.v.e.sB[gp.wave >> 1][gp.lane];
+      float4 qn[AHEAD];
+#pragma unroll
+      for (int t4 = 0; t4 < AHEAD; ++t4)
+        qn[t4] = reinterpret_cast<const float4*>(&S.u.b.v.e.sA[gp.wave >> 1][h0])[t4];
 #pragma unroll 1
       for (int sl = gp.wave >> 1; sl < cur.cn; sl += NWAVE / 2) {
-        const float vs = S.u.b.v.e.sB[sl][gp.lane];
+        const float vs = vn;
         const float4* sa = reinterpret_cast<const float4*>(&S.u.b.v.e.sA[sl][h0]);
+        float4 sq[NQ];
+#pragma unroll
+        for (int t4 = 0; t4 < AHEAD; ++t4) sq[t4] = qn[t4];
+        __builtin_amdgcn_sched_barrier(0);
         double e0 = 0.0, e1 = 0.0, e2 = 0.0, e3 = 0.0;
 #pragma unroll
-        for (int t4 = 0; t4 < TS / 8; ++t4) {
-          const float4 s = sa[t4];
+        for (int t4 = 0; t4 < NQ; ++t4) {
+          const float4 s = sq[t4];
           const int t = 4 * t4;
           const float d0 = Rev[t + 0] - vmax(Pc[t + 0], s.x + vs);
           const float d1 = Rev[t + 1] - vmax(Pc[t + 1], s.y + vs);
@@ -780,7 +841,15 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
           e1 += fabs((double)d1);
           e2 += fabs((double)d2);
           e3 += fabs((double)d3);
+          if (t4 + AHEAD < NQ) sq[t4 + AHEAD] = sa[t4 + AHEAD];
+          __builtin_amdgcn_sched_barrier(0);
         }
+        const int nx = sl + NWAVE / 2 < TCH ? sl + NWAVE / 2 : sl;
+        vn = S.u.b.v.e.sB[nx][gp.lane];
+#pragma unroll
+        for (int t4 = 0; t4 < AHEAD; ++t4)
+          qn[t4] = reinterpret_cast<const float4*>(&S.u.b.v.e.sA[nx][h0])[t4];
+        __builtin_amdgcn_sched_barrier(0);
         const double v = row_sum((e0 + e1) + (e2 + e3));
         if ((gp.lane & 15) == 0) S.u.b.epl[sl][half][gp.lane >> 4] = v;
       }
@@ -878,7 +947,8 @@ DEV void decide(Grp& gp, Smem& S, int nt, double thr, bool best) {
     const int dec = S.dec == 0x7fffffff ? -1 : S.dec;
     st_coh(&gp.ctl->decision, dec);
     st_coh(&gp.ctl->e_new, dec >= 0 ? ld_atomic(&eprime[dec]) : 0.0);
-    gp.ctl->batches += 1;
+    // the deciding workgroup changes from batch to batch: device-coherent
+    st_coh(&gp.ctl->batches, ld_atomic(&gp.ctl->batches) + 1);
   }
 }
 
@@ -2389,7 +2459,8 @@ DEV void fit_run(Grp& gp, Smem& S, int max_rows) {
 // once per kernel.
 template <int MODE>
 DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int max_rows,
-                         unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl) {
+                         unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl,
+                         BarTree* __restrict__ gbar) {
   extern __shared__ __align__(16) char smem_raw[];
   Smem& S = *reinterpret_cast<Smem*>(smem_raw);
   Grp gp;
@@ -2406,6 +2477,7 @@ DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int max_row
       gq.G = qgroup;
       gq.d = nullptr;
       gq.ctl = (GA FitCtl*)(gctl + b / qgroup);
+      gq.bar = gbar ? (GA BarTree*)(gbar + b / qgroup) : nullptr;
       if (gq.g == 0 && gq.tid == 0) st_coh(&gq.ctl->decision, (int)atomicAdd(queue, 1u));
       if (!group_sync(gq, S)) break;
       fid = ld_atomic(&gq.ctl->decision);
@@ -2424,6 +2496,7 @@ DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int max_row
     if (fid >= nfits) break;
     gp.d = &fits[fid];
     gp.ctl = fits[fid].ctl;
+    gp.bar = fits[fid].bar;
     if (ld_atomic(&gp.ctl->phase) != 2) fit_run<MODE>(gp, S, max_rows);
   }
 }
@@ -2431,30 +2504,34 @@ DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int max_row
 // FastSTMF (TD_A) fits.
 __global__ void __launch_bounds__(NTHR) fit_kernel(const FitDev* __restrict__ fits, int nfits,
                                                    int max_rows,
-                                                   unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl) {
-  fit_kernel_body<0>(fits, nfits, max_rows, queue, qgroup, gctl);
+                                                   unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl,
+    BarTree* __restrict__ gbar) {
+  fit_kernel_body<0>(fits, nfits, max_rows, queue, qgroup, gctl, gbar);
 }
 
 // Fits with any ByRow selection (all fits of one launch share it).
 __global__ void __launch_bounds__(NTHR) fit_kernel_sel(const FitDev* __restrict__ fits, int nfits,
                                                        int max_rows,
-                                                       unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl) {
-  fit_kernel_body<1>(fits, nfits, max_rows, queue, qgroup, gctl);
+                                                       unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl,
+    BarTree* __restrict__ gbar) {
+  fit_kernel_body<1>(fits, nfits, max_rows, queue, qgroup, gctl, gbar);
 }
 
 // FastSTMF (TD_A) fits on matrices wider than SORT_MAX columns (the same
 // fit; the column order ranked with every thread counting).
 __global__ void __launch_bounds__(NTHR) fit_kernel_wide(const FitDev* __restrict__ fits, int nfits,
                                                         int max_rows,
-                                                        unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl) {
-  fit_kernel_body<3>(fits, nfits, max_rows, queue, qgroup, gctl);
+                                                        unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl,
+    BarTree* __restrict__ gbar) {
+  fit_kernel_body<3>(fits, nfits, max_rows, queue, qgroup, gctl, gbar);
 }
 
 // ByMatrix fits.
 __global__ void __launch_bounds__(NTHR) fit_kernel_matrix(const FitDev* __restrict__ fits,
                                                           int nfits, int max_rows,
-                                                          unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl) {
-  fit_kernel_body<2>(fits, nfits, max_rows, queue, qgroup, gctl);
+                                                          unsigned* __restrict__ queue, int qgroup, FitCtl* __restrict__ gctl,
+    BarTree* __restrict__ gbar) {
+  fit_kernel_body<2>(fits, nfits, max_rows, queue, qgroup, gctl, gbar);
 }
 
 size_t fit_smem_bytes() { return sizeof(Smem); }

@@ -16,13 +16,13 @@ namespace stmf {
 
 // kernels (stmf_fit.hip, stmf_prims.hip, stmf_setup.hip)
 __global__ void fit_kernel(const FitDev* fits, int nfits, int max_rows, unsigned* queue, int qgroup,
-                           FitCtl* gctl);
+                           FitCtl* gctl, BarTree* gbar);
 __global__ void fit_kernel_sel(const FitDev* fits, int nfits, int max_rows, unsigned* queue,
-                               int qgroup, FitCtl* gctl);
+                               int qgroup, FitCtl* gctl, BarTree* gbar);
 __global__ void fit_kernel_matrix(const FitDev* fits, int nfits, int max_rows, unsigned* queue,
-                                  int qgroup, FitCtl* gctl);
+                                  int qgroup, FitCtl* gctl, BarTree* gbar);
 __global__ void fit_kernel_wide(const FitDev* fits, int nfits, int max_rows, unsigned* queue,
-                                int qgroup, FitCtl* gctl);
+                                int qgroup, FitCtl* gctl, BarTree* gbar);
 size_t fit_smem_bytes();
 size_t masked_error_ws(int m, int n);
 hipError_t launch_maxplus(const float*, const float*, int, int, int, float*, int32_t*, hipStream_t);
@@ -118,6 +118,8 @@ static int device_props(DevProps& out) {
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_wide, (const void*)fit_kernel_wide,
                                                         NTHR, smem));
     p.coresident = std::min(std::min(per, per_sel), std::min(per_mat, per_wide)) * p.cus;
+    // a group barrier holds up to GROUP_MAX workgroups
+    p.coresident = std::min(p.coresident, GROUP_MAX);
     p.ok = true;
   }
   out = p;
@@ -155,7 +157,7 @@ struct Layout {
   int mw, nw, ldm, ldn, nrt, nct, ldmax, G, acol_p, tmax;
   int transposed;
   size_t Rw, RwT, Uc, V, td, tdpart, crow, ccol, colst, rowst, colpart, rowpart, order, rowt,
-      rord, tdrow, tvec, epart, eprime, closed, traj, ctl, dev, perm, cperm, stage, check, rowc,
+      rord, tdrow, tvec, epart, eprime, closed, traj, ctl, bar, dev, perm, cperm, stage, check, rowc,
       colc, mtd, mfk, mkey, mtdr, mtdc, mhist, mcnt, mgat_u, mgat_q, mlist_q, mlist_k;
   bool matrix;
   size_t total;
@@ -208,6 +210,7 @@ static void make_layout(int m, int n, int r, int iters, int G, int acol_p, int b
   L.rowt = take((size_t)L.mw * 4);
   L.traj = take((size_t)(iters + 1) * 8);
   L.ctl = take(sizeof(FitCtl));
+  L.bar = take(sizeof(BarTree));
   L.dev = take(sizeof(FitDev));
   L.perm = take((size_t)L.mw * 4);
   L.cperm = take((size_t)L.nw * 4);
@@ -289,6 +292,7 @@ static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int o
   d.traj = (double*)(base + L.traj);
   d.log = (LogRec*)o.decision_log;
   d.ctl = (FitCtl*)(base + L.ctl);
+  d.bar = (BarTree*)(base + L.bar);
   d.ldmax = L.ldmax;
   d.gsize = L.G;
   if (L.matrix) {
@@ -440,6 +444,7 @@ static int prepare_fit(const float* R, const uint8_t* M, const Layout& L, char* 
                      L.ldn, L.r, (float*)(base + L.V));
   HIPCHK(hipGetLastError());
   int st = fill_u32(base + L.ctl, sizeof(FitCtl) / 4, 0, s);
+  if (!st) st = fill_u32(base + L.bar, sizeof(BarTree) / 4, 0, s);
   if (!st) st = fill_u32(base + L.closed, (size_t)L.r, 0, s);
   if (!st) st = fill_u32(base + L.rowt, (size_t)L.mw, 0, s);
   if (!st) st = fill_u32(base + L.traj, (size_t)(L.iters + 1) * 2, 0, s);
@@ -469,14 +474,14 @@ static int launch_output(const Layout& L, char* base, float* U_out, float* V_out
 // a process that made one ended with a segmentation fault at exit under the
 // profiler.)
 static int launch_fit_kernel(const FitDev* dev_fits, int nfits, int grid, int max_rows,
-                             unsigned* queue, int qgroup, FitCtl* gctl, int sel, bool wide,
-                             hipStream_t s) {
+                             unsigned* queue, int qgroup, FitCtl* gctl, BarTree* gbar, int sel,
+                             bool wide, hipStream_t s) {
   const size_t smem = fit_smem_bytes();
   const void* k = sel == SEL_TD_A     ? (wide ? (const void*)fit_kernel_wide : (const void*)fit_kernel)
                   : sel == SEL_MATRIX ? (const void*)fit_kernel_matrix
                                       : (const void*)fit_kernel_sel;
   void* args[] = {(void*)&dev_fits, (void*)&nfits, (void*)&max_rows, (void*)&queue,
-                  (void*)&qgroup,   (void*)&gctl};
+                  (void*)&qgroup,   (void*)&gctl,  (void*)&gbar};
   HIPCHK(hipLaunchKernel(k, dim3(grid), dim3(NTHR), args, smem, s));
   return STMF_OK;
 }
@@ -674,7 +679,7 @@ int stmf_fit(const float* R, const uint8_t* M, int m, int n, int rank, int iters
   HIPCHK(hipEventCreate(&ev1));
   HIPCHK(hipEventRecord(ev0, s));
   st = launch_fit_kernel((const FitDev*)(base + L.dev), 1, G, o.max_row_visits, nullptr, 1,
-                         nullptr, kernel_sel(o), L.nw > SORT_MAX, s);
+                         nullptr, nullptr, kernel_sel(o), L.nw > SORT_MAX, s);
   if (st) { (void)hipEventDestroy(ev0); (void)hipEventDestroy(ev1); return st; }
   HIPCHK(hipEventRecord(ev1, s));
   FitCtl c;
@@ -707,7 +712,7 @@ struct BatchPlan {
   std::vector<uint64_t> seed;  // seed of each fit
   int qgroup = 1;              // workgroups per group of the persistent launch
   int ngroups = 1;             // groups in the launch
-  size_t table, queue, gctl, total;
+  size_t table, queue, gctl, gbar, total;
 };
 
 // Estimated work of a fit, for ordering the queue (largest first) and
@@ -770,6 +775,8 @@ static void plan_batched(const stmf_problem* probs, int nprob, int restarts, con
   o_ += 256;
   B.gctl = o_;
   o_ += al256((size_t)B.ngroups * sizeof(FitCtl));
+  B.gbar = o_;
+  o_ += al256((size_t)B.ngroups * sizeof(BarTree));
   B.total = o_;
 }
 
@@ -788,11 +795,13 @@ static int record_batched(const BatchPlan& B, const std::vector<int>& fit_ids,
                           char* base, int sel, int max_rows, hipStream_t c) {
   int st = fill_u32(base + B.queue, 1, 0, c);
   if (!st) st = fill_u32(base + B.gctl, (size_t)B.ngroups * sizeof(FitCtl) / 4, 0, c);
+  if (!st) st = fill_u32(base + B.gbar, (size_t)B.ngroups * sizeof(BarTree) / 4, 0, c);
   if (st) return st;
   const int n = (int)table.size();
   const int ngroups = std::min(B.ngroups, n);
   st = launch_fit_kernel((const FitDev*)(base + B.table), n, ngroups * B.qgroup, max_rows,
-                         (unsigned*)(base + B.queue), B.qgroup, (FitCtl*)(base + B.gctl), sel,
+                         (unsigned*)(base + B.queue), B.qgroup, (FitCtl*)(base + B.gctl),
+                         (BarTree*)(base + B.gbar), sel,
                          any_wide(table.data(), n), c);
   if (st) return st;
   for (int f : fit_ids) {
@@ -1112,11 +1121,11 @@ static int tick_work(stmf_engine* e, const std::vector<int>& plan, int max_rows,
       if (!st)
         st = launch_fit_kernel(table + first, count, groups, max_rows,
                                (unsigned*)(e->arena + e->queue_off), 1,
-                               (FitCtl*)(e->arena + e->gctl_off), sel, wide, s);
+                               (FitCtl*)(e->arena + e->gctl_off), nullptr, sel, wide, s);
     } else {
       // every group of the launch is resident at once: grid <= coresident
-      st = launch_fit_kernel(table + first, count, grid, max_rows, nullptr, 1, nullptr, sel, wide,
-                             s);
+      st = launch_fit_kernel(table + first, count, grid, max_rows, nullptr, 1, nullptr, nullptr,
+                             sel, wide, s);
     }
     if (st) return st;
   }

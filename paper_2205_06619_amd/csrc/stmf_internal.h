@@ -66,6 +66,18 @@ struct LogRec {
   double e;
 };
 
+// Two-level group barrier: workgroup g of a group belongs to subgroup
+// g / BAR_SUB; the counters only grow (from zero at the fit's preparation),
+// each on a 128-byte line of its own.
+constexpr int BAR_SUB = 16;                    // workgroups per subgroup
+constexpr int BAR_NSUB = 16;                   // subgroups
+constexpr int GROUP_MAX = BAR_SUB * BAR_NSUB;  // largest group
+struct alignas(128) BarTree {
+  unsigned top[32];             // [0]: arrivals of the subgroups' last members
+  unsigned sub[BAR_NSUB][32];   // [q][0]: arrivals of subgroup q's members
+  unsigned rel[BAR_NSUB][32];   // [q][0]: episodes released to subgroup q
+};
+
 // Control block of one fit (device memory).  Everything a resumed launch
 // needs to continue a fit lives here or in the arrays of FitDev.
 struct FitCtl {
@@ -79,8 +91,6 @@ struct FitCtl {
   int acc_in_pass;       // acceptances in the current pass
   int ncand;             // candidates of the current row
   int iters_done;
-  unsigned bar_count;    // group barrier
-  unsigned bar_gen;
   unsigned queue;        // batched launches: next fit to take (only in ctl[0])
   unsigned pad0;
   long long trials;      // trials the method evaluates (up to the accepted one)
@@ -150,6 +160,7 @@ struct FitDev {
   STMF_G(double) traj;       // iters + 1
   STMF_G(LogRec) log;        // nullable
   STMF_G(FitCtl) ctl;
+  STMF_G(BarTree) bar;       // the group barrier's counters
   int ldmax;
   int gsize;             // workgroups cooperating on this fit
 };
