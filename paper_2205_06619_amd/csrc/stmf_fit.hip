@@ -500,11 +500,13 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
           __syncthreads();
           const WaveTrials w = wave_trials_range<NE, MR>(gp, S, cs, cn);
           if (side == 0 && MR) {
+            // unconditional loads (element 0 past the chunk's end): the
+            // compiler keeps them all in flight
             float raw[NE];
 #pragma unroll
             for (int m = 0; m < NE; ++m) {
               const int sl = gp.wave + m * NWAVE;
-              if (sl < cn) raw[m] = Rw[lane_i(w.i, m) * ldn + c0 + x];
+              raw[m] = Rw[sl < cn ? (size_t)lane_i(w.i, m) * ldn + c0 + x : 0];
             }
 #pragma unroll
             for (int m = 0; m < NE; ++m) {
@@ -527,11 +529,13 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
               }
             }
           } else {
+            // unconditional loads (element 0 past the chunk's end): the
+            // compiler keeps them all in flight
             float raw[NE];
 #pragma unroll
             for (int m = 0; m < NE; ++m) {
               const int sl = gp.wave + m * NWAVE;
-              if (sl < cn) raw[m] = RwT[lane_i(w.j, m) * ldm + r0 + x];
+              raw[m] = RwT[sl < cn ? (size_t)lane_i(w.j, m) * ldm + r0 + x : 0];
             }
 #pragma unroll
             for (int m = 0; m < NE; ++m) {
@@ -659,17 +663,24 @@ DEV void chunk_loads(Grp& gp, const WaveTrials& w, const Chunk& c, int par, int 
   const auto RwT = d.RwT;
   const size_t ldx = d.ldmax, ldm = d.ldm;
   const int x = gp.lane;
+  // Every slot loads, unconditionally: a slot without a trial of either
+  // operation reads element 0 of the target array and of R's transpose
+  // (valid addresses, values unused).  With the loads under branches the
+  // compiler merged each into the register array right away and waited for
+  // it there, so the chunk's loads went one at a time.
 #pragma unroll
   for (int m = 0; m < NE; ++m) {
-    if (gp.wave + m * NWAVE < c.cn) {
-      const int q = lane_i(w.q, m), op = lane_i(w.op, m);
-      if (op == OP_ULF) {
-        rawB[m] = ld_atomic(&tv[q * ldx + r0 + x]);
-        if (MR) rawA[m] = d.Rw[(size_t)lane_i(w.i, m) * d.ldn + c0 + x];
-      } else if (op == OP_URF) {
-        rawA[m] = RwT[lane_i(w.j, m) * ldm + r0 + x];
-        rawB[m] = ld_atomic(&tv[q * ldx + c0 + x]);
-      }
+    const bool has = gp.wave + m * NWAVE < c.cn;
+    const int q = has ? lane_i(w.q, m) : 0, op = has ? lane_i(w.op, m) : OP_NULL;
+    const bool ulf = op == OP_ULF, urf = op == OP_URF;
+    const size_t ob = ulf ? (size_t)q * ldx + r0 + x : urf ? (size_t)q * ldx + c0 + x : 0;
+    rawB[m] = ld_atomic(&tv[ob]);
+    if (MR) {
+      const size_t oa = urf ? (size_t)lane_i(w.j, m) * ldm + r0 + x : 0;
+      const size_t oc = ulf ? (size_t)lane_i(w.i, m) * d.ldn + c0 + x : 0;
+      rawA[m] = ulf ? d.Rw[oc] : RwT[oa];
+    } else {
+      rawA[m] = RwT[urf ? (size_t)lane_i(w.j, m) * ldm + r0 + x : 0];
     }
   }
 }
