@@ -996,6 +996,18 @@ DEV void refresh_tiles(Grp& gp, Smem& S, int k, bool has_acc, Trial acc, int par
   for (int tile = gp.g; tile < ntile; tile += gp.G) {
     const int rt = tile / d.nct, ct = tile % d.nct;
     const int r0 = rt * TS, c0 = ct * TS;
+    // the tile's R values (lanes over columns, the wave's rows) and R's
+    // transpose (lanes over rows, the wave's columns), loaded first: they
+    // arrive while the component's vectors are staged
+    const int c = c0 + gp.lane;
+    const int tl0 = gp.wave * RPW;
+    const int tb = r0 + tl0;
+    const int cl0 = gp.wave * RPW;
+    float R[RPW], RT[RPW];
+#pragma unroll
+    for (int tt = 0; tt < RPW; ++tt) R[tt] = d.Rw[(size_t)(tb + tt) * d.ldn + c];
+#pragma unroll
+    for (int cc = 0; cc < RPW; ++cc) RT[cc] = d.RwT[(size_t)(c0 + cl0 + cc) * d.ldm + r0 + gp.lane];
     __syncthreads();
     if (full) {
       // only the rank's components of each histogram row are used
@@ -1019,12 +1031,6 @@ DEV void refresh_tiles(Grp& gp, Smem& S, int k, bool has_acc, Trial acc, int par
     }
     if (full) stage_uv(gp, S, r0, c0);
     __syncthreads();
-    const int c = c0 + gp.lane;
-    const int tl0 = gp.wave * RPW;
-    const int tb = r0 + tl0;
-    float R[RPW];
-#pragma unroll
-    for (int tt = 0; tt < RPW; ++tt) R[tt] = d.Rw[(size_t)(tb + tt) * d.ldn + c];
     if (full) {
       float P[RPW];
       int A[RPW];
@@ -1069,13 +1075,10 @@ DEV void refresh_tiles(Grp& gp, Smem& S, int k, bool has_acc, Trial acc, int par
     }
     {
       // lanes over rows: row summary over this wave's columns
-      const int t = r0 + gp.lane;
-      const int cl0 = gp.wave * RPW;
       Top2 rs = top2_id();
 #pragma unroll
       for (int cc = 0; cc < RPW; ++cc)
-        rs = top2_add(rs, d.RwT[(size_t)(c0 + cl0 + cc) * d.ldm + t] - S.vk[cl0 + cc],
-                      c0 + cl0 + cc);
+        rs = top2_add(rs, RT[cc] - S.vk[cl0 + cc], c0 + cl0 + cc);
       S.u.f.rsw[gp.wave][gp.lane] = rs;
     }
     __syncthreads();
