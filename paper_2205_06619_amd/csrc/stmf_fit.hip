@@ -141,8 +141,9 @@ struct BatchScratch {
                              // component at every cell of the tile
 };
 struct RefreshScratch {
-  int hc[TS][RMAX];          // argmax histogram of the tile columns
-  int hr[TS][RMAX];          // argmax histogram of the tile rows
+  int hc[TS][RMAX + 1];      // argmax histogram of the tile columns (rows padded:
+                             // the lanes of a wave count into distinct banks)
+  int hr[TS][RMAX + 1];      // argmax histogram of the tile rows
   double tdw[NWAVE][TS];
   Top2 csw[NWAVE][TS];
   Top2 rsw[NWAVE][TS];
