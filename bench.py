@@ -61,7 +61,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fit_kernel_gene_expr_500x2000_tra
 # rank ~ U{2..30}, missing ~ U[0.2, 0.8], integer planted), a stated subset
 # of its 256 problems with all 8 restarts, for a stated number of passes
 BATCHED = dict(count=32, restarts=8, iters=1, m=(50, 1000), n=(50, 5000), rank=(2, 30),
-               missing=(0.2, 0.8), seed=4, same_fit_problems=4, tune_sample=8, tune_visits=24)
+               missing=(0.2, 0.8), seed=4, same_fit_problems=4, tune_sample=8, tune_visits=24,
+               per_launch=64)
 # serving: FP32 noisy planted jobs of a stated subset of the batched shapes,
 # 30 passes each, Poisson arrivals at 0.5x and 0.9x the batched path's
 # saturation rate for the same job mix
@@ -109,16 +110,26 @@ def batched_compare():
                                   visits=b["tune_visits"], integer_exact=1)
     tune_s = time.perf_counter() - t0
     progress(f"batched: autotuned {tuned} in {tune_s:.1f} s")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs, statuses, info = stmf.stmf_fit_batched(dev, restarts=b["restarts"], integer_exact=1,
-                                                 **tuned)
-    torch.cuda.synchronize()
-    t_pop = time.perf_counter() - t0
-    assert statuses == [0] * len(probs)
-    progress(f"batched: population of {len(probs) * b['restarts']} fits in {t_pop:.1f} s")
+    # the population, up to per_launch problems (all their restarts) per
+    # persistent launch
+    t_pop, trials, spec, launches = 0.0, 0, 0, 0
+    for s0 in range(0, len(dev), b["per_launch"]):
+        part = dev[s0:s0 + b["per_launch"]]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs, statuses, info = stmf.stmf_fit_batched(part, restarts=b["restarts"],
+                                                     integer_exact=1, **tuned)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert statuses == [0] * len(part)
+        t_pop += dt
+        trials += info["trials"]
+        spec += info["spec_trials"]
+        launches += 1
+        del outs
+        progress(f"batched: {len(part) * b['restarts']} fits in {dt:.1f} s")
     fits = len(probs) * b["restarts"]
-    del outs
+    progress(f"batched: population of {fits} fits in {t_pop:.1f} s")
     # the same fits both ways: the first problems, every restart
     sub = dev[:b["same_fit_problems"]]
     torch.cuda.synchronize()
@@ -149,9 +160,10 @@ def batched_compare():
                                f"{b['restarts']} restarts, {b['iters']} pass(es); the first "
                                f"{b['same_fit_problems']} problems' fits also through the plain path"},
         "autotuned": {"options": tuned, "tune_s": tune_s},
-        "population": {"fits": fits, "batched_s": t_pop, "fits_per_s": fits / t_pop,
-                       "trials": info["trials"], "trials_per_s": info["trials"] / t_pop,
-                       "spec_trials": info["spec_trials"], "group_size": info["group_size"]},
+        "population": {"fits": fits, "launches": launches, "batched_s": t_pop,
+                       "fits_per_s": fits / t_pop, "trials": trials,
+                       "trials_per_s": trials / t_pop, "spec_trials": spec,
+                       "group_size": info["group_size"]},
         "same_fits": {"fits": sub_fits, "batched_s": t_sub, "plain_s": t_plain,
                       "batched_fits_per_s": sub_fits / t_sub, "plain_fits_per_s": sub_fits / t_plain,
                       "batched_updates_per_s": plain_updates / t_sub,
@@ -462,6 +474,8 @@ def main():
                     help="run only the serving comparison (one JSON line)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched comparison (one JSON line)")
+    ap.add_argument("--batched-problems", type=int, default=BATCHED["count"],
+                    help="problems of the 256-problem batched population to run (the first N)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, serving, selection, quality and large comparisons")
     args = ap.parse_args()
@@ -498,6 +512,7 @@ def main():
     if args.serving_only:
         print(json.dumps(serving_compare()), flush=True)
         return
+    BATCHED["count"] = max(1, min(256, args.batched_problems))
     if args.batched_only:
         print(json.dumps(batched_compare()), flush=True)
         return
