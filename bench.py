@@ -34,6 +34,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -365,14 +366,24 @@ def large_compare():
     }
 
 
+def _code_only(text: str) -> str:
+    """C++ source without its comments and blank space (string literals in
+    the kernel sources hold no comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources' code: a change of comments or layout keeps
+    the stored counter figures valid, any change of code drops them."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2205_06619_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
+            with open(os.path.join(csrc, name), encoding="utf-8") as f:
                 h.update(name.encode())
-                h.update(f.read())
+                h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -247,6 +247,12 @@ struct Grp {
 // resumed by a later launch.  A wait longer than BARRIER_TIMEOUT (or another
 // workgroup's abort) sets the fit's status and leaves.  Returns false when
 // this workgroup left on an abort.
+//
+// Ordering: data that crosses workgroups is written and read only with
+// device-scope accesses; a workgroup arrives after s_waitcnt(0) (its stores
+// are complete at the device level), and only thread 0 waits, between two
+// workgroup barriers, so no thread's later access can be issued (or moved
+// by the compiler) before the release has been seen.
 template <typename F>
 DEV bool group_sync_last(Grp& gp, Smem& S, F last_work) {
   GA FitCtl* ctl = gp.ctl;
