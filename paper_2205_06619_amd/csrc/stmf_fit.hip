@@ -637,6 +637,20 @@ DEV double dpp_add(double a) {
 DEV double row_sum(double v) {
   return dpp_add<0x128>(dpp_add<0x124>(dpp_add<0x4E>(dpp_add<0xB1>(v))));
 }
+// The same for two values at once: a's row sum in lane 16 * row, b's in lane
+// 16 * row + 1, each bit-identical to row_sum's.  In the first exchange even
+// lanes keep a and odd lanes b, each receiving from its partner the value it
+// keeps; the later exchanges stay within a parity.  Every addition has the
+// operands of the corresponding one of row_sum (b's in swapped order, which
+// IEEE addition does not see).
+DEV double pair_row_sum(double a, double b, bool odd) {
+  const double send = odd ? a : b, keep = odd ? b : a;
+  const unsigned long long s = __double_as_longlong(send);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)s, 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(s >> 32), 0xB1, 0xF, 0xF, false);
+  const double w = keep + __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+  return dpp_add<0x128>(dpp_add<0x124>(dpp_add<0x4E>(w)));
+}
 
 // A chunk of a batch's trial list: component k's trials [cs, cs + cn) of
 // the two byk ranges [a0, a0 + n0) (F-ULF) and [a1, a1 + n1) (F-URF).
@@ -828,48 +842,35 @@ DEV void batch_eval_pass(Grp& gp, Smem& S, int i, int par) {
           wave_trials<NE, MR>(gp, S, next.cs, next.cn, next.a0, next.n0, next.a1);
       chunk_loads<NE, MR>(gp, wnext, next, par, r0, c0, rawA, rawB);
       __syncthreads();
-      // The trial's first LDS reads are issued while the previous trial's
-      // lane sums are reduced, the rest AHEAD deep (see the residual pass);
-      // a read past the chunk's last trial stays inside the staging arrays
-      // and its value is never used.
-      constexpr int NQ = TS / 8, AHEAD = 3;
-      float vn = S.u.b.v.e.sB[gp.wave >> 1][gp.lane];
-      float4 qn[AHEAD];
-#pragma unroll
-      for (int t4 = 0; t4 < AHEAD; ++t4)
-        qn[t4] = reinterpret_cast<const float4*>(&S.u.b.v.e.sA[gp.wave >> 1][h0])[t4];
+      // Two trials per step (sl and sl + 4, the wave's consecutive ones): the
+      // two cell loops interleave, and one DPP reduction adds both (the last
+      // trial of an odd count goes alone, its partner reading its vectors).
 #pragma unroll 1
-      for (int sl = gp.wave >> 1; sl < cur.cn; sl += NWAVE / 2) {
-        const float vs = vn;
-        const float4* sa = reinterpret_cast<const float4*>(&S.u.b.v.e.sA[sl][h0]);
-        float4 sq[NQ];
+      for (int sl = gp.wave >> 1; sl < cur.cn; sl += NWAVE) {
+        const int slb = sl + NWAVE / 2;
+        const bool two = slb < cur.cn;
+        const int sb = two ? slb : sl;
+        const float vsa = S.u.b.v.e.sB[sl][gp.lane], vsb = S.u.b.v.e.sB[sb][gp.lane];
+        const float4* saa = reinterpret_cast<const float4*>(&S.u.b.v.e.sA[sl][h0]);
+        const float4* sab = reinterpret_cast<const float4*>(&S.u.b.v.e.sA[sb][h0]);
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
 #pragma unroll
-        for (int t4 = 0; t4 < AHEAD; ++t4) sq[t4] = qn[t4];
-        __builtin_amdgcn_sched_barrier(0);
-        double e0 = 0.0, e1 = 0.0, e2 = 0.0, e3 = 0.0;
-#pragma unroll
-        for (int t4 = 0; t4 < NQ; ++t4) {
-          const float4 s = sq[t4];
+        for (int t4 = 0; t4 < TS / 8; ++t4) {
+          const float4 x = saa[t4], y = sab[t4];
           const int t = 4 * t4;
-          const float d0 = Rev[t + 0] - vmax(Pc[t + 0], s.x + vs);
-          const float d1 = Rev[t + 1] - vmax(Pc[t + 1], s.y + vs);
-          const float d2 = Rev[t + 2] - vmax(Pc[t + 2], s.z + vs);
-          const float d3 = Rev[t + 3] - vmax(Pc[t + 3], s.w + vs);
-          e0 += fabs((double)d0);
-          e1 += fabs((double)d1);
-          e2 += fabs((double)d2);
-          e3 += fabs((double)d3);
-          if (t4 + AHEAD < NQ) sq[t4 + AHEAD] = sa[t4 + AHEAD];
-          __builtin_amdgcn_sched_barrier(0);
+          a0 += fabs((double)(Rev[t + 0] - vmax(Pc[t + 0], x.x + vsa)));
+          a1 += fabs((double)(Rev[t + 1] - vmax(Pc[t + 1], x.y + vsa)));
+          a2 += fabs((double)(Rev[t + 2] - vmax(Pc[t + 2], x.z + vsa)));
+          a3 += fabs((double)(Rev[t + 3] - vmax(Pc[t + 3], x.w + vsa)));
+          b0 += fabs((double)(Rev[t + 0] - vmax(Pc[t + 0], y.x + vsb)));
+          b1 += fabs((double)(Rev[t + 1] - vmax(Pc[t + 1], y.y + vsb)));
+          b2 += fabs((double)(Rev[t + 2] - vmax(Pc[t + 2], y.z + vsb)));
+          b3 += fabs((double)(Rev[t + 3] - vmax(Pc[t + 3], y.w + vsb)));
         }
-        const int nx = sl + NWAVE / 2 < TCH ? sl + NWAVE / 2 : sl;
-        vn = S.u.b.v.e.sB[nx][gp.lane];
-#pragma unroll
-        for (int t4 = 0; t4 < AHEAD; ++t4)
-          qn[t4] = reinterpret_cast<const float4*>(&S.u.b.v.e.sA[nx][h0])[t4];
-        __builtin_amdgcn_sched_barrier(0);
-        const double v = row_sum((e0 + e1) + (e2 + e3));
+        const double v = pair_row_sum((a0 + a1) + (a2 + a3), (b0 + b1) + (b2 + b3), gp.lane & 1);
         if ((gp.lane & 15) == 0) S.u.b.epl[sl][half][gp.lane >> 4] = v;
+        else if (two && (gp.lane & 15) == 1) S.u.b.epl[slb][half][gp.lane >> 4] = v;
       }
       prev = cur;
       cur = next;
