@@ -209,7 +209,6 @@ struct Smem {
   int cskip[CW];             // ByElement: an exact entry (td = 0), not a trial
   int kbest[CW][4], kval[CW][4];
   float kvalf[CW][4];
-  float vsel[CW];
   // TD_B: U of the first working row, and (U (x) V) and its argmax at (i, j0)
   float urow0[RMAX];
   float p_ij0;
@@ -221,7 +220,8 @@ struct Smem {
 };
 
 static_assert(sizeof(Smem) <= 160 * 1024, "LDS layout exceeds a CU's 160 KB");
-static_assert(2 * CW <= NTHR && CW * 4 <= NTHR, "one thread per candidate pair");
+static_assert(2 * CW <= NTHR, "one thread per candidate pair");
+static_assert(CW % (NTHR / 4) == 0, "whole rounds of four threads per candidate");
 static_assert(RMAX == 64, "one lane per component (two group keys) in the batch grouping");
 static_assert(TCH <= NTHR, "one thread per staged trial in the error reduction");
 static_assert(KB * TS == NTHR, "one thread per staged summary");
@@ -455,6 +455,33 @@ DEV WaveTrials wave_trials_range(const Grp& gp, const Smem& S, int base, int cn)
 DEV int lane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 DEV float lane_f(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
 
+// The R values the first residuals of a chunk's trials need (wave w: trials
+// w, w + NWAVE, ... of the chunk's cn): F-URF (side 1), column j of R at the
+// tile rows; F-ULF with rows of their own (MR), row i at the tile columns;
+// plain F-ULF takes row i from LDS and loads nothing.  Every slot loads,
+// unconditionally: one without a trial reads element 0 (a valid address, the
+// value unused).  Under branches the compiler merged each load into the
+// register array where it was issued and waited for it there.
+template <int NE, bool MR>
+DEV void residual_loads(const Grp& gp, const WaveTrials& w, int side, int cn, const GA float* Rw,
+                        const GA float* RwT, size_t ldn, size_t ldm, int r0, int c0,
+                        float (&raw)[NE]) {
+  const int x = gp.lane;
+  if (side) {
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+      const int sl = gp.wave + m * NWAVE;
+      raw[m] = RwT[sl < cn ? (size_t)lane_i(w.j, m) * ldm + r0 + x : 0];
+    }
+  } else if (MR) {
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+      const int sl = gp.wave + m * NWAVE;
+      raw[m] = Rw[sl < cn ? (size_t)lane_i(w.i, m) * ldn + c0 + x : 0];
+    }
+  }
+}
+
 // ------------------------------------------------------------ pass 1 of a batch
 // Second residual of every trial over this workgroup's tiles, combined across
 // tiles with an atomic min on order-preserving integer images (exact).  The
@@ -462,7 +489,8 @@ DEV float lane_f(float v, int l) { return __int_as_float(__builtin_amdgcn_readla
 // registers), then the F-URF trials (lanes over the tile columns).  Per block
 // of components the summaries are staged once; each trial then stages the
 // one first-residual vector it needs, 2 * TCH trials at a time (wave w takes
-// trials w, w + NWAVE, ...), every global load issued before any is used.
+// trials w, w + NWAVE, ...); the trial records and global loads of the next
+// chunk are issued before the current chunk is evaluated.
 // With MR (ByMatrix) the trials of a batch have rows of their own: the F-ULF
 // first residual takes R's row and the column summary's exclusion per trial.
 template <bool MR = false>
@@ -501,20 +529,16 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
         if (lo == hi) continue;
         __syncthreads();
         stage_block<MR>(gp, S, kb0, nb, side == 0, side == 1, r0, c0, i);
+        // the first chunk's trial records and loads; each later chunk's are
+        // taken while the chunk before it is evaluated
+        WaveTrials w = wave_trials_range<NE, MR>(gp, S, lo, hi - lo < 2 * TCH ? hi - lo : 2 * TCH);
+        float raw[NE];
+        residual_loads<NE, MR>(gp, w, side, hi - lo, Rw, RwT, ldn, ldm, r0, c0, raw);
 #pragma unroll 1
         for (int cs = lo; cs < hi; cs += 2 * TCH) {
           const int cn = hi - cs < 2 * TCH ? hi - cs : 2 * TCH;
           __syncthreads();
-          const WaveTrials w = wave_trials_range<NE, MR>(gp, S, cs, cn);
           if (side == 0 && MR) {
-            // unconditional loads (element 0 past the chunk's end): the
-            // compiler keeps them all in flight
-            float raw[NE];
-#pragma unroll
-            for (int m = 0; m < NE; ++m) {
-              const int sl = gp.wave + m * NWAVE;
-              raw[m] = Rw[sl < cn ? (size_t)lane_i(w.i, m) * ldn + c0 + x : 0];
-            }
 #pragma unroll
             for (int m = 0; m < NE; ++m) {
               const int sl = gp.wave + m * NWAVE;
@@ -530,20 +554,11 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
 #pragma unroll
             for (int m = 0; m < NE; ++m) {
               const int sl = gp.wave + m * NWAVE;
-              if (sl < cn) {
-                const Trial& tr = S.trials[S.byk[cs + sl]];
-                S.u.b.v.sX[sl][x] = in ? vmin(S.colb[tr.k - kb0][x], ri - tr.val) : 0.0f;
-              }
+              if (sl < cn)
+                S.u.b.v.sX[sl][x] =
+                    in ? vmin(S.colb[lane_i(w.k, m) - kb0][x], ri - lane_f(w.val, m)) : 0.0f;
             }
           } else {
-            // unconditional loads (element 0 past the chunk's end): the
-            // compiler keeps them all in flight
-            float raw[NE];
-#pragma unroll
-            for (int m = 0; m < NE; ++m) {
-              const int sl = gp.wave + m * NWAVE;
-              raw[m] = RwT[sl < cn ? (size_t)lane_i(w.j, m) * ldm + r0 + x : 0];
-            }
 #pragma unroll
             for (int m = 0; m < NE; ++m) {
               const int sl = gp.wave + m * NWAVE;
@@ -555,6 +570,11 @@ DEV void batch_residual_pass(Grp& gp, Smem& S, int i, int par) {
               }
             }
           }
+          // the next chunk's (past the range's end: no trials, and every
+          // load reads element 0)
+          const int ns = cs + 2 * TCH;
+          w = wave_trials_range<NE, MR>(gp, S, ns, hi - ns < 2 * TCH ? hi - ns : 2 * TCH);
+          residual_loads<NE, MR>(gp, w, side, hi - ns, Rw, RwT, ldn, ldm, r0, c0, raw);
           __syncthreads();
           // Each trial's 16 broadcast LDS reads are kept AHEAD deep in
           // flight, and the next trial's first AHEAD are issued before this
@@ -1555,8 +1575,8 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb, int sel) {
     if (S.nt >= T || avail0 == 0) break;
     const int avail = avail0 < CW ? avail0 : CW;
     // Component of each candidate in the window, four threads per candidate,
-    // each over components l = sub, sub + 4, ... (V_lj, and for TD_A the
-    // column counts, loaded in one round):
+    // each over components l = sub, sub + 4, ... (for TD_A the column counts,
+    // otherwise V_lj, loaded in one round), NTHR / 4 candidates per round:
     //   TD_A: the index counted most often in row i's and column j's argmax
     //         multisets (lowest on ties);
     //   TD:   f(i, j), the lowest argmax of U_il + V_lj;
@@ -1564,50 +1584,54 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb, int sel) {
     //   SEQ:  the candidate's own component;
     //   ByElement: f(i, j), and an entry with R_ij = (U (x) V)_ij is skipped.
     {
-      const int p = gp.tid >> 2, sub = gp.tid & 3;
-      float vv[RMAX / 4];
-      if (p < avail) {
-        const int e = S.cq[S.cq_head + p];
-        const int j = sel == SEL_SEQ ? e / RMAX : e;
+      const int sub = gp.tid & 3;
+#pragma unroll 1
+      for (int p0 = 0; p0 < CW; p0 += NTHR / 4) {
+        const int p = p0 + (gp.tid >> 2);
+        if (p0 < avail && p < avail) {
+          const int e = S.cq[S.cq_head + p];
+          const int j = sel == SEL_SEQ ? e / RMAX : e;
+          if (sel == SEL_TD_A) {
+            int cnt[RMAX / 4];
 #pragma unroll
-        for (int u = 0; u < RMAX / 4; ++u) {
-          const int l = sub + 4 * u;
-          vv[u] = l < d.r ? ld_atomic(&d.V[(size_t)l * d.ldn + j]) : 0.0f;
-        }
-        if (sel == SEL_TD_A) {
-          int cnt[RMAX / 4];
-#pragma unroll
-          for (int u = 0; u < RMAX / 4; ++u) {
-            const int l = sub + 4 * u;
-            cnt[u] = l < d.r ? ld_atomic(&ccol[(size_t)j * d.r + l]) : 0;
-          }
-          int best = -1, kb = 0;
-#pragma unroll
-          for (int u = 0; u < RMAX / 4; ++u) {
-            const int l = sub + 4 * u;
-            if (l < d.r) {
-              const int v = S.crow_i[l] + cnt[u];
-              if (v > best) { best = v; kb = l; }
+            for (int u = 0; u < RMAX / 4; ++u) {
+              const int l = sub + 4 * u;
+              cnt[u] = l < d.r ? ld_atomic(&ccol[(size_t)j * d.r + l]) : 0;
             }
-          }
-          S.kval[p][sub] = best;
-          S.kbest[p][sub] = kb;
-        } else if (sel != SEL_SEQ) {
-          // row i (TD) or row i0 (TD_B): value selects, not address selects
-          const bool own = sel == SEL_TD || sel == SEL_ELEM;
-          float best = 0.0f;
-          int kb = -1;
+            int best = -1, kb = 0;
 #pragma unroll
-          for (int u = 0; u < RMAX / 4; ++u) {
-            const int l = sub + 4 * u;
-            if (l < d.r) {
-              const float uv = own ? S.urow_i[l] : S.urow0[l];
-              const float x = uv + vv[u];
-              if (kb < 0 || x > best) { best = x; kb = l; }
+            for (int u = 0; u < RMAX / 4; ++u) {
+              const int l = sub + 4 * u;
+              if (l < d.r) {
+                const int v = S.crow_i[l] + cnt[u];
+                if (v > best) { best = v; kb = l; }
+              }
             }
+            S.kval[p][sub] = best;
+            S.kbest[p][sub] = kb;
+          } else if (sel != SEL_SEQ) {
+            float vv[RMAX / 4];
+#pragma unroll
+            for (int u = 0; u < RMAX / 4; ++u) {
+              const int l = sub + 4 * u;
+              vv[u] = l < d.r ? ld_atomic(&d.V[(size_t)l * d.ldn + j]) : 0.0f;
+            }
+            // row i (TD) or row i0 (TD_B): value selects, not address selects
+            const bool own = sel == SEL_TD || sel == SEL_ELEM;
+            float best = 0.0f;
+            int kb = -1;
+#pragma unroll
+            for (int u = 0; u < RMAX / 4; ++u) {
+              const int l = sub + 4 * u;
+              if (l < d.r) {
+                const float uv = own ? S.urow_i[l] : S.urow0[l];
+                const float x = uv + vv[u];
+                if (kb < 0 || x > best) { best = x; kb = l; }
+              }
+            }
+            S.kvalf[p][sub] = best;
+            S.kbest[p][sub] = kb;
           }
-          S.kvalf[p][sub] = best;
-          S.kbest[p][sub] = kb;
         }
       }
       __syncthreads();
@@ -1639,24 +1663,18 @@ DEV void build_batch(Grp& gp, Smem& S, int i, int T, int cb, int sel) {
         S.ck[q] = k;
         S.cskip[q] = skip;
       }
-      __syncthreads();
-      if (p < avail && (S.ck[p] & 3) == sub) {
-        const int want = S.ck[p] >> 2;
-        float v = 0.0f;
-#pragma unroll
-        for (int u = 0; u < RMAX / 4; ++u) v = u == want ? vv[u] : v;
-        S.vsel[p] = v;
-      }
     }
     __syncthreads();
     if (gp.tid < avail) {
+      // V_kj is loaded again rather than kept from the loads above (V does
+      // not change while a batch list is built), next to R_ij
       const int p = gp.tid;
       const int e = S.cq[S.cq_head + p];
       const int j = sel == SEL_SEQ ? e / RMAX : e;
       const int k = S.ck[p];
       const float Rij = d.Rw[(size_t)i * d.ldn + j];
+      const float Vkj = ld_atomic(&d.V[(size_t)k * d.ldn + j]);
       const float Uik = S.urow_i[k];
-      const float Vkj = S.vsel[p];
       const float vu = Rij - Vkj, vv2 = Rij - Uik;
       const bool cl = d.noop_rule && S.closed_s[k];
       S.cj[p] = j; S.cvu[p] = vu; S.cvv[p] = vv2;

@@ -19,7 +19,7 @@ constexpr int NWAVE = 8;        // waves per workgroup
 constexpr int NTHR = 64 * NWAVE;
 constexpr int TMAX = 1024;      // trials per speculative batch (upper bound)
 constexpr int TCH = 64;         // trials staged in LDS at a time
-constexpr int CW = 128;         // candidate columns examined at a time
+constexpr int CW = 256;         // candidate columns examined at a time
 constexpr int RMAX = 64;        // largest supported rank
 constexpr int SORT_MAX = 4096;  // widest matrix sorted in one workgroup's LDS
 
