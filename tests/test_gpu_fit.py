@@ -107,6 +107,20 @@ def test_fit_independent_of_batch_shape(S, batch_first, batch_max):
     _compare(g, o)
 
 
+@pytest.mark.parametrize("batch_first,batch_max", [(129, 257), (256, 1024), (100, 300)])
+def test_fit_long_rows_independent_of_batch_shape(S, batch_first, batch_max):
+    # rows of about 450 candidates: batches of these sizes span several
+    # candidate windows and several 128-trial chunks per operation, with
+    # ragged ends
+    print(f"fit long rows batch {batch_first}/{batch_max}", flush=True)
+    R, M = synth.int_planted(24, 600, 3, 0.25, seed=23)
+    o = oracle.fit(R, M, 3, 2, seed=23, prec="f32")
+    g = S.stmf_fit(_t(R), _t(M), 3, 2, seed=23, batch_first=batch_first, batch_max=batch_max,
+                   log_cap=64)
+    _compare(g, o)
+    assert g.info["spec_trials"] >= 24 * 2 * min(batch_first, 257) // 2
+
+
 def test_fit_count_scope_all_and_noop_off(S):
     print("fit scope=all noop=0", flush=True)
     R, M = synth.int_planted(40, 60, 3, 0.3, seed=31)
