@@ -273,8 +273,11 @@ def test_bymatrix_rounds_of_candidates(S, batch_max):
     _compare(g, o)
 
 
-def test_bymatrix_exact_start_tries_every_cell(S):
-    print("ByMatrix exact start", flush=True)
+@pytest.mark.parametrize("batch_max", [64, 512])
+def test_bymatrix_exact_start_tries_every_cell(S, batch_max):
+    # with 512: batches of both operations span several 128-trial chunks,
+    # each trial of a chunk on a row of its own
+    print(f"ByMatrix exact start batch_max={batch_max}", flush=True)
     rng = np.random.default_rng(6)
     Us = rng.integers(0, 20, (30, 2)).astype(np.float32)
     Vs = rng.integers(0, 20, (2, 50)).astype(np.float32)
@@ -282,7 +285,7 @@ def test_bymatrix_exact_start_tries_every_cell(S):
     M = np.ones_like(R, np.uint8)
     o = oracle.fit(R, M, 2, 3, prec="f32", init_mode=2, U0=Us, perm_mode=2, strategy=2, seed=6)
     g = S.stmf_fit(_t(R), _t(M), 2, 3, seed=6, U0=Us, perm_mode=2, strategy=2, log_cap=8,
-                   batch_max=64)
+                   batch_max=batch_max, batch_first=batch_max)
     assert g.info["accepted"] == 0 and g.info["trials"] + g.info["noops"] == 1500
     assert g.info["trials"] == o.stats["trials"] and g.info["noops"] == o.stats["noops"]
     np.testing.assert_array_equal(g.traj, [0.0] * 4)
