@@ -47,7 +47,8 @@ typedef enum {
   STMF_ENOMEM = 4,      /* workspace too small or misaligned                         */
   STMF_EHIP = 5,        /* a HIP runtime call failed                                 */
   STMF_EBUSY = 6,       /* serving engine: no slot or not enough memory free         */
-  STMF_ETIMEOUT = 7     /* a fit stopped: a group barrier waited > 4 s             */
+  STMF_ETIMEOUT = 7     /* a fit stopped: a group barrier waited longer than its
+                           bound (barrier_wait_us; 4 s by default)             */
 } stmf_status;
 
 /* Short English description of a status code (static string). */
@@ -207,6 +208,13 @@ typedef struct {
                              perm_mode 2.  stmf_fit only (the batched and
                              serving calls return STMF_EINVAL); the workspace
                              grows by about 20 bytes per cell.                  */
+  int barrier_wait_us;  /* bound of each wait at the fit's group barrier, in
+                           microseconds: 0 the default (4 s); a fit whose wait
+                           runs out stops with STMF_ETIMEOUT.  A negative value
+                           ends a wait at its first poll that finds the
+                           barrier still closed, so a fit on many workgroups
+                           stops at one of its first barriers (for tests of
+                           the abort path).                                   */
 } stmf_options;
 
 /* Per-row-visit decision record (decision_log). */

@@ -230,6 +230,7 @@ struct Grp {
   const FitDev* d;
   GA FitCtl* ctl;
   GA BarTree* bar;   // the group barrier's counters (unused by a group of one)
+  unsigned long long wait;  // bound of a barrier wait (100 MHz ticks)
   int g, G;
   int lane, wave, tid;
 };
@@ -244,8 +245,10 @@ struct Grp {
 // whole group, its 256 serialised atomics made each barrier about 10 us;
 // two levels about 2 us).  The counters only grow: an arrival's episode is
 // its count divided by the arrivals per episode, which also holds for a fit
-// resumed by a later launch.  A wait longer than BARRIER_TIMEOUT (or another
-// workgroup's abort) sets the fit's status and leaves.  Returns false when
+// resumed by a later launch.  A wait longer than the group's bound
+// (BARRIER_TIMEOUT unless the fit sets another; a bound of 0 ends a wait at
+// its first unanswered poll), or another workgroup's abort, sets the fit's
+// status and leaves.  Returns false when
 // this workgroup left on an abort.
 //
 // Ordering: data that crosses workgroups is written and read only with
@@ -280,7 +283,7 @@ DEV bool group_sync_last(Grp& gp, Smem& S, F last_work) {
         while ((int)(ld_atomic(&bar->rel[q][0]) - e) < 0) {
           st = ld_atomic(&ctl->status);
           if (st != 0) break;
-          if (__builtin_amdgcn_s_memrealtime() - t0 > BARRIER_TIMEOUT) {
+          if (__builtin_amdgcn_s_memrealtime() - t0 > gp.wait) {
             int zero = 0;
             __hip_atomic_compare_exchange_strong(&ctl->status, &zero, ST_TIMEOUT, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2516,6 +2519,7 @@ DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int max_row
       gq.g = b % qgroup;
       gq.G = qgroup;
       gq.d = nullptr;
+      gq.wait = BARRIER_TIMEOUT;
       gq.ctl = (GA FitCtl*)(gctl + b / qgroup);
       gq.bar = gbar ? (GA BarTree*)(gbar + b / qgroup) : nullptr;
       if (gq.g == 0 && gq.tid == 0) st_coh(&gq.ctl->decision, (int)atomicAdd(queue, 1u));
@@ -2537,6 +2541,8 @@ DEV void fit_kernel_body(const FitDev* __restrict__ fits, int nfits, int max_row
     gp.d = &fits[fid];
     gp.ctl = fits[fid].ctl;
     gp.bar = fits[fid].bar;
+    gp.wait = fits[fid].bar_wait < 0 ? 0ull
+              : fits[fid].bar_wait > 0 ? (unsigned long long)fits[fid].bar_wait : BARRIER_TIMEOUT;
     if (ld_atomic(&gp.ctl->phase) != 2) fit_run<MODE>(gp, S, max_rows);
   }
 }

@@ -295,6 +295,7 @@ static FitDev make_dev(const Layout& L, char* base, const stmf_options& o, int o
   d.bar = (BarTree*)(base + L.bar);
   d.ldmax = L.ldmax;
   d.gsize = L.G;
+  d.bar_wait = o.barrier_wait_us < 0 ? -1 : (long long)o.barrier_wait_us * 100;
   if (L.matrix) {
     d.mtd = (double*)(base + L.mtd);
     d.mfk = (int*)(base + L.mfk);

@@ -163,6 +163,9 @@ struct FitDev {
   STMF_G(BarTree) bar;       // the group barrier's counters
   int ldmax;
   int gsize;             // workgroups cooperating on this fit
+  long long bar_wait;    // bound of a group-barrier wait in 100 MHz ticks: 0 the
+                         // default, negative none (a wait ends at its first
+                         // unanswered poll)
 };
 
 }  // namespace stmf

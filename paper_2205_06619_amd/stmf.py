@@ -47,6 +47,7 @@ class Options(C.Structure):
         ("decision_log", C.c_void_p), ("log_cap", C.c_int), ("batch_first", C.c_int),
         ("batch_max", C.c_int), ("group_size", C.c_int), ("max_row_visits", C.c_int),
         ("selection", C.c_int), ("perm_mode", C.c_int), ("strategy", C.c_int),
+        ("barrier_wait_us", C.c_int),
     ]
 
 

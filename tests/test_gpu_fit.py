@@ -121,6 +121,26 @@ def test_fit_long_rows_independent_of_batch_shape(S, batch_first, batch_max):
     assert g.info["spec_trials"] >= 24 * 2 * min(batch_first, 257) // 2
 
 
+def test_fit_barrier_wait_bound(S):
+    # group-barrier waits end at their first unanswered poll: a fit on 32
+    # workgroups (whose arrivals at its hundreds of barriers are never all
+    # simultaneous) stops with STMF_ETIMEOUT and every workgroup leaves; the
+    # same fit with a finite bound then gives the default's result bit for bit
+    print("fit barrier wait bound", flush=True)
+    R, M = synth.int_planted(40, 2100, 3, 0.3, seed=41)
+    with pytest.raises(S.StmfError) as ex:
+        S.stmf_fit(_t(R), _t(M), 3, 1, seed=41, group_size=32, barrier_wait_us=-1)
+    assert ex.value.status == S.STMF_ETIMEOUT
+    a = S.stmf_fit(_t(R), _t(M), 3, 1, seed=41, group_size=32, barrier_wait_us=2_000_000,
+                   log_cap=64)
+    b = S.stmf_fit(_t(R), _t(M), 3, 1, seed=41, group_size=32, log_cap=64)
+    assert a.info["group_size"] == 32 and b.info["group_size"] == 32
+    assert _log_rows(a.log) == _log_rows(b.log)
+    np.testing.assert_array_equal(a.traj, b.traj)
+    np.testing.assert_array_equal(a.U.cpu().numpy(), b.U.cpu().numpy())
+    np.testing.assert_array_equal(a.V.cpu().numpy(), b.V.cpu().numpy())
+
+
 def test_fit_count_scope_all_and_noop_off(S):
     print("fit scope=all noop=0", flush=True)
     R, M = synth.int_planted(40, 60, 3, 0.3, seed=31)
